@@ -43,6 +43,8 @@ def lib():
         build(force=False)
         L = ctypes.CDLL(LIB)
         sig = {
+            "or_set_threads": (None, [ctypes.c_int]),
+            "or_get_threads": (ctypes.c_int, []),
             "or_hash": (ctypes.c_uint32, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint32]),
             "or_create": (_VP, [ctypes.c_float, ctypes.c_float, ctypes.c_int, ctypes.c_int,
                                 ctypes.c_int, ctypes.c_int]),
@@ -82,6 +84,14 @@ def lib():
 
 def _p(a, t):
     return a.ctypes.data_as(t)
+
+
+def set_threads(n: int) -> None:
+    lib().or_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().or_get_threads())
 
 
 def hash_index(x: int, y: int, z: int, mask: int) -> int:

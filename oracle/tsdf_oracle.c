@@ -31,6 +31,7 @@
  * thread count.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -42,6 +43,7 @@
 #define OR_SDF_INIT 32767         /* short SDF initial value, == 1.0, Sec. 3.1 */
 #define OR_Z_NEAR 0.05f           /* near plane of the search-range projection */
 #define OR_MAX_RAY_STEPS 65536    /* hard bound on raycast iterations */
+#define OR_MAX_SEGMENT_SAMPLES 64 /* samples kept per pixel segment */
 
 #define OR_FLAG_BLOCKS_EXHAUSTED 1u
 #define OR_FLAG_EXCESS_EXHAUSTED 2u
@@ -136,6 +138,8 @@ void or_destroy(or_volume *v)
 }
 
 int or_n_entries(const or_volume *v) { return v->n_buckets + v->n_excess; }
+void or_set_threads(int n) { omp_set_num_threads(n); }
+int or_get_threads(void) { return omp_get_max_threads(); }
 uint32_t or_flags(const or_volume *v) { return v->flags; }
 int or_n_free_blocks(const or_volume *v) { return v->n_free_blocks; }
 int or_n_free_excess(const or_volume *v) { return v->n_free_excess; }
@@ -407,14 +411,14 @@ void or_alloc_and_visible(or_volume *v, const float *depth, int W, int H, const 
     float Ri[9], ti[3];
     invert_pose(M, Ri, ti);
     float inv_block = 1.0f / (8.0f * v->voxel_size);
-    int keys[3 * 64];
+    int keys[3 * OR_MAX_SEGMENT_SAMPLES];
     v->n_swapped_in = 0;
 
     for (int y = 0; y < H; ++y) {
         for (int x = 0; x < W; ++x) {
             float d = depth[(size_t)y * W + x];
             if (!(d > 0.0f)) continue;
-            int m = segment_blocks(d, x, y, &K, Ri, ti, v->mu, inv_block, keys, 64);
+            int m = segment_blocks(d, x, y, &K, Ri, ti, v->mu, inv_block, keys, OR_MAX_SEGMENT_SAMPLES);
             for (int s = 0; s < m; ++s) {
                 int bx = keys[3 * s], by = keys[3 * s + 1], bz = keys[3 * s + 2];
                 int i = or_lookup(v, bx, by, bz);

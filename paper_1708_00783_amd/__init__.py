@@ -1,0 +1,316 @@
+"""Python binding of libtsdf.so (the gfx950 TSDF fusion hot path).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch supplies device memory (tensors) and streams.  The module
+refuses to load without the built library: there is no fallback path.
+
+The functions keep the C names of include/tsdf.h; `Volume` wraps one context
+and its workspace tensor.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libtsdf.so")
+
+TF_OK, TF_E_INVAL, TF_E_HIP, TF_E_ORDER, TF_E_SPACE = 0, -1, -2, -3, -4
+TF_DEPTH_F32_M, TF_DEPTH_U16_MM = 0, 1
+TF_FLAG_BLOCKS_EXHAUSTED = 0x1
+TF_FLAG_EXCESS_EXHAUSTED = 0x2
+TF_FLAG_REQUEST_OVERFLOW = 0x4
+TF_FLAG_TRANSFER_OVERFLOW = 0x8
+
+# every symbol include/tsdf.h declares
+EXPORTS = (
+    "tf_workspace_bytes", "tf_host_store_bytes", "tf_host_transfer_bytes", "tf_create",
+    "tf_destroy", "tf_reset", "tf_alloc_and_visible", "tf_integrate", "tf_raycast",
+    "tf_range_image", "tf_swap_out", "tf_get_stats", "tf_export_entries", "tf_export_visible",
+    "tf_export_voxels", "tf_status_string", "tf_profile_enable", "tf_profile_read",
+)
+
+
+class tf_intrinsics(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float),
+                ("cy", ctypes.c_float), ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class tf_params(ctypes.Structure):
+    _fields_ = [("voxel_size", ctypes.c_float), ("mu", ctypes.c_float), ("max_w", ctypes.c_int32),
+                ("n_buckets", ctypes.c_uint32), ("n_excess", ctypes.c_uint32),
+                ("n_blocks", ctypes.c_uint32), ("max_width", ctypes.c_uint32),
+                ("max_height", ctypes.c_uint32), ("swap_transfer_blocks", ctypes.c_uint32)]
+
+
+class tf_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in (
+        "flags", "n_allocated", "n_visible", "n_new", "n_free_excess", "n_swapped_in",
+        "n_swapped_out", "frames")] + [(n, ctypes.c_uint64) for n in (
+        "total_integrated_blocks", "total_written_columns", "total_range_records",
+        "total_rays_hit", "total_requests", "total_new_blocks", "integrate_calls",
+        "raycast_calls")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+KERNEL_CLASSES = ("alloc_rays", "insert", "visible", "integrate", "range_bin", "raycast", "swap")
+
+
+class tf_profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64 * 8), ("ms", ctypes.c_double * 8)]
+
+    def as_dict(self):
+        return {k: {"launches": int(self.launches[i]), "ms": float(self.ms[i])}
+                for i, k in enumerate(KERNEL_CLASSES)}
+
+
+class TsdfError(RuntimeError):
+    pass
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_F16 = ctypes.POINTER(ctypes.c_float)
+
+
+def lib():
+    """Load libtsdf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        sig = {
+            "tf_workspace_bytes": (ctypes.c_size_t, [P(tf_params)]),
+            "tf_host_store_bytes": (ctypes.c_size_t, [P(tf_params)]),
+            "tf_host_transfer_bytes": (ctypes.c_size_t, [P(tf_params)]),
+            "tf_create": (ctypes.c_int, [P(tf_params), _VP, ctypes.c_size_t, _VP, _VP, _VP, P(_VP)]),
+            "tf_destroy": (ctypes.c_int, [_VP]),
+            "tf_reset": (ctypes.c_int, [_VP, _VP]),
+            "tf_alloc_and_visible": (ctypes.c_int, [_VP, _VP, ctypes.c_int, P(tf_intrinsics), _F16, _VP]),
+            "tf_integrate": (ctypes.c_int, [_VP, _VP, ctypes.c_int, _F16, _VP]),
+            "tf_raycast": (ctypes.c_int, [_VP, _F16, P(tf_intrinsics), _VP, _VP, _VP]),
+            "tf_range_image": (ctypes.c_int, [_VP, _F16, P(tf_intrinsics), _VP, _VP, _VP]),
+            "tf_swap_out": (ctypes.c_int, [_VP, _VP]),
+            "tf_get_stats": (ctypes.c_int, [_VP, P(tf_stats), _VP]),
+            "tf_export_entries": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+            "tf_export_visible": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, P(ctypes.c_uint32), _VP]),
+            "tf_export_voxels": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP]),
+            "tf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+            "tf_profile_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
+            "tf_profile_read": (ctypes.c_int, [_VP, P(tf_profile), ctypes.c_int]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int, what: str = "") -> None:
+    if status != TF_OK:
+        msg = lib().tf_status_string(status).decode()
+        raise TsdfError(f"{what}: {msg} ({status})")
+
+
+def _pose_arg(pose):
+    M = np.ascontiguousarray(np.asarray(pose, np.float32).reshape(16))
+    return M, M.ctypes.data_as(_F16)
+
+
+def make_intrinsics(intr) -> tf_intrinsics:
+    """From synth.Intrinsics, a dict, or (fx, fy, cx, cy, W, H)."""
+    if hasattr(intr, "fx"):
+        return tf_intrinsics(intr.fx, intr.fy, intr.cx, intr.cy, intr.width, intr.height)
+    fx, fy, cx, cy, W, H = intr
+    return tf_intrinsics(fx, fy, cx, cy, int(W), int(H))
+
+
+def make_params(vp, max_width, max_height, swap_transfer_blocks=0) -> tf_params:
+    return tf_params(vp.voxel_size, vp.mu, vp.max_w, vp.n_buckets, vp.n_excess, vp.n_blocks,
+                     max_width, max_height, swap_transfer_blocks)
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ---- C-named thin wrappers ---------------------------------------------------------
+
+def tf_workspace_bytes(params: tf_params) -> int:
+    return int(lib().tf_workspace_bytes(ctypes.byref(params)))
+
+
+def tf_create(params, d_workspace_ptr, nbytes, h_store=None, h_transfer=None, stream=None):
+    ctx = _VP()
+    check(lib().tf_create(ctypes.byref(params), ctypes.c_void_p(d_workspace_ptr), nbytes,
+                          h_store, h_transfer, _stream_ptr(stream), ctypes.byref(ctx)), "tf_create")
+    return ctx
+
+
+def tf_alloc_and_visible(ctx, depth, depth_format, intr, pose, stream=None):
+    _, Mp = _pose_arg(pose)
+    K = make_intrinsics(intr)
+    check(lib().tf_alloc_and_visible(ctx, ctypes.c_void_p(depth.data_ptr()), depth_format,
+                                     ctypes.byref(K), Mp, _stream_ptr(stream)), "tf_alloc_and_visible")
+
+
+def tf_integrate(ctx, depth, depth_format, pose, stream=None):
+    _, Mp = _pose_arg(pose)
+    check(lib().tf_integrate(ctx, ctypes.c_void_p(depth.data_ptr()), depth_format, Mp,
+                             _stream_ptr(stream)), "tf_integrate")
+
+
+def tf_raycast(ctx, pose, intr, points, normals, stream=None):
+    _, Mp = _pose_arg(pose)
+    K = make_intrinsics(intr)
+    check(lib().tf_raycast(ctx, Mp, ctypes.byref(K), ctypes.c_void_p(points.data_ptr()),
+                           ctypes.c_void_p(normals.data_ptr()), _stream_ptr(stream)), "tf_raycast")
+
+
+def tf_range_image(ctx, pose, intr, zmin, zmax, stream=None):
+    _, Mp = _pose_arg(pose)
+    K = make_intrinsics(intr)
+    check(lib().tf_range_image(ctx, Mp, ctypes.byref(K), ctypes.c_void_p(zmin.data_ptr()),
+                               ctypes.c_void_p(zmax.data_ptr()), _stream_ptr(stream)), "tf_range_image")
+
+
+def tf_get_stats(ctx, stream=None) -> dict:
+    st = tf_stats()
+    check(lib().tf_get_stats(ctx, ctypes.byref(st), _stream_ptr(stream)), "tf_get_stats")
+    return st.as_dict()
+
+
+class Volume:
+    """One TSDF volume on the current HIP device."""
+
+    def __init__(self, vp, max_width, max_height, swap_transfer_blocks=0, stream=None):
+        import torch
+        self.params = make_params(vp, max_width, max_height, swap_transfer_blocks)
+        nbytes = tf_workspace_bytes(self.params)
+        if nbytes == 0:
+            raise TsdfError("invalid volume parameters")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.h_store = None
+        self.h_transfer = None
+        hs = ht = None
+        if swap_transfer_blocks:
+            n_store = int(lib().tf_host_store_bytes(ctypes.byref(self.params)))
+            n_xfer = int(lib().tf_host_transfer_bytes(ctypes.byref(self.params)))
+            self.h_store = np.empty(n_store, np.uint8)
+            self.h_transfer = torch.empty(n_xfer, dtype=torch.uint8, pin_memory=True)
+            hs = ctypes.c_void_p(self.h_store.ctypes.data)
+            ht = ctypes.c_void_p(self.h_transfer.data_ptr())
+        self.ctx = tf_create(self.params, self.workspace.data_ptr(), nbytes, hs, ht, stream)
+        self.n_entries = self.params.n_buckets + self.params.n_excess
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().tf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self, stream=None):
+        check(lib().tf_reset(self.ctx, _stream_ptr(stream)), "tf_reset")
+
+    def alloc_and_visible(self, depth, intr, pose, stream=None):
+        fmt = TF_DEPTH_U16_MM if depth.dtype.itemsize == 2 else TF_DEPTH_F32_M
+        tf_alloc_and_visible(self.ctx, depth, fmt, intr, pose, stream)
+
+    def integrate(self, depth, pose, stream=None):
+        fmt = TF_DEPTH_U16_MM if depth.dtype.itemsize == 2 else TF_DEPTH_F32_M
+        tf_integrate(self.ctx, depth, fmt, pose, stream)
+
+    def raycast(self, pose, intr, points=None, normals=None, stream=None):
+        import torch
+        K = make_intrinsics(intr)
+        if points is None:
+            points = torch.empty((K.height, K.width, 4), dtype=torch.float32, device="cuda")
+        if normals is None:
+            normals = torch.empty((K.height, K.width, 4), dtype=torch.float32, device="cuda")
+        tf_raycast(self.ctx, pose, K, points, normals, stream)
+        return points, normals
+
+    def range_image(self, pose, intr, stream=None):
+        import torch
+        K = make_intrinsics(intr)
+        zmin = torch.empty((K.height, K.width), dtype=torch.float32, device="cuda")
+        zmax = torch.empty((K.height, K.width), dtype=torch.float32, device="cuda")
+        tf_range_image(self.ctx, pose, K, zmin, zmax, stream)
+        return zmin, zmax
+
+    def swap_out(self, stream=None):
+        check(lib().tf_swap_out(self.ctx, _stream_ptr(stream)), "tf_swap_out")
+
+    def stats(self, stream=None) -> dict:
+        return tf_get_stats(self.ctx, stream)
+
+    def profile_enable(self, on=True):
+        check(lib().tf_profile_enable(self.ctx, 1 if on else 0), "tf_profile_enable")
+
+    def profile_read(self, reset=False) -> dict:
+        pr = tf_profile()
+        check(lib().tf_profile_read(self.ctx, ctypes.byref(pr), 1 if reset else 0), "tf_profile_read")
+        return pr.as_dict()
+
+    def frame(self, depth, intr, pose, points=None, normals=None, stream=None):
+        self.alloc_and_visible(depth, intr, pose, stream)
+        self.integrate(depth, pose, stream)
+        return self.raycast(pose, intr, points, normals, stream)
+
+    # ---- inspection (synchronising) ------------------------------------------------
+    def entries(self, stream=None):
+        n = self.n_entries
+        pos = np.empty((n, 3), np.int16)
+        off = np.empty(n, np.int32)
+        ptr = np.empty(n, np.int32)
+        check(lib().tf_export_entries(self.ctx, pos.ctypes.data_as(_VP), off.ctypes.data_as(_VP),
+                                      ptr.ctypes.data_as(_VP), _stream_ptr(stream)), "tf_export_entries")
+        return pos, off, ptr
+
+    def visible(self, stream=None) -> np.ndarray:
+        cnt = ctypes.c_uint32(0)
+        buf = np.empty(self.params.n_blocks, np.int32)
+        check(lib().tf_export_visible(self.ctx, buf.ctypes.data_as(_VP), buf.size, ctypes.byref(cnt),
+                                      _stream_ptr(stream)), "tf_export_visible")
+        return buf[:cnt.value].copy()
+
+    def block_voxels(self, entry_ids, stream=None):
+        import torch
+        ids = torch.as_tensor(np.ascontiguousarray(entry_ids, np.int32)).cuda()
+        n = ids.numel()
+        sdf = torch.empty((n, 512), dtype=torch.int16, device="cuda")
+        w = torch.empty((n, 512), dtype=torch.uint8, device="cuda")
+        if n:
+            check(lib().tf_export_voxels(self.ctx, ctypes.c_void_p(ids.data_ptr()), n,
+                                         ctypes.c_void_p(sdf.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+                                         _stream_ptr(stream)), "tf_export_voxels")
+        return sdf.cpu().numpy(), w.cpu().numpy()
+
+    def allocated_positions(self) -> np.ndarray:
+        pos, _, ptr = self.entries()
+        p = pos[ptr >= 0].astype(np.int32)
+        return p[np.lexsort((p[:, 2], p[:, 1], p[:, 0]))] if len(p) else p.reshape(0, 3)
+
+    def voxels_by_position(self):
+        pos, _, ptr = self.entries()
+        ids = np.flatnonzero(ptr >= 0).astype(np.int32)
+        p = pos[ids].astype(np.int32)
+        order = np.lexsort((p[:, 2], p[:, 1], p[:, 0]))
+        ids = ids[order]
+        sdf, w = self.block_voxels(ids)
+        return p[order], sdf, w

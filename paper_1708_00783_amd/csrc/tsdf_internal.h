@@ -1,0 +1,139 @@
+// tsdf_internal.h -- device-side data layout and kernel launchers of libtsdf.
+// Internal to the library (not installed, not shared with anything else).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tsdf {
+
+constexpr int kBlockVox = 512;          // 8x8x8 voxels per block (Sec. 3.1)
+constexpr int kBlockBytes = 1536;       // 512 x int16 SDF, then 512 x uint8 weight
+constexpr int kTile = 16;               // raycast tile = the paper's 16x16 fragments (Sec. 4.4)
+constexpr int kBinCap = 1024;           // block records per tile before the all-records fallback
+constexpr int32_t kPtrSwapped = -1;     // Sec. 3.2: ptr == -1 swapped out
+constexpr int32_t kPtrEmpty = -2;       // Sec. 3.2: ptr < -1 unallocated
+constexpr int32_t kPtrClaimed = -3;     // bucket claimed inside k_insert, block pointer pending
+constexpr float kZNear = 0.05f;         // near plane of the search-range projection
+constexpr int kMaxRaySteps = 65536;     // hard bound on raycast iterations
+constexpr int kMaxSegmentSamples = 64;  // samples kept per pixel segment
+constexpr int kIntegrateGrid = 2048;    // workgroups of the integration launch
+constexpr int kMarchGrid = 1024;        // workgroups of the persistent ray-march launch
+
+// vis[] byte per hash entry, reset by the visible-list compaction
+constexpr uint8_t kVisTouched = 1;      // touched by a ray segment or kept in view
+constexpr uint8_t kVisNew = 3;          // inserted this frame
+
+// hash entry (Sec. 3.2), 16 bytes so that one dwordx4 load fetches it
+struct alignas(16) DEntry {
+    int16_t x, y, z, pad;
+    int32_t offset;   // 0 ends the chain; k >= 1 -> entry n_buckets + k - 1
+    int32_t ptr;      // >= 0 block, -1 swapped out, < -1 unallocated
+};
+static_assert(sizeof(DEntry) == 16, "entry layout");
+
+struct alignas(16) Req {
+    unsigned long long key;   // packed block position, see pack_key
+    uint32_t slot;            // request-set slot to clear after insertion
+    uint32_t pad;
+};
+
+// axis-aligned pixel box of a projected block and its camera-z range
+struct alignas(16) Rec {
+    int16_t x0, y0, x1, y1;
+    float zlo, zhi;
+};
+
+// device counters; one per volume
+struct alignas(256) Ctrl {
+    int32_t free_blocks;     // height of the free-block stack
+    int32_t free_excess;     // height of the free excess-slot stack
+    uint32_t n_req;          // unique insertion requests of the current frame
+    uint32_t n_vis;          // visible-list length
+    uint32_t n_vis_prev;     // previous visible-list length (read by k_insert)
+    uint32_t n_ret;          // blocks to return to the free stack
+    uint32_t flags;          // sticky TF_FLAG_*
+    uint32_t n_rec;          // search-range records of the current raycast
+    uint32_t ray_ticket;     // last-workgroup detection in the raycast kernels
+    uint32_t n_new;          // blocks inserted by the last frame
+    uint32_t n_swapped_in;
+    uint32_t n_swapped_out;
+    uint32_t frames;
+    uint32_t req_overflow;   // request list overflowed this frame: sweep the request set
+    uint32_t n_swap_cand;    // swap-out candidates gathered by the last swap selection
+    uint32_t sweep_req;      // copy of req_overflow taken by k_insert for k_visible
+    // totals since creation (each written by a single thread of one kernel)
+    unsigned long long tot_vis;        // blocks visited by integration
+    unsigned long long tot_rec;        // projected blocks behind raycast search ranges
+    unsigned long long tot_req;        // insertion requests
+    unsigned long long tot_new;        // blocks inserted
+    unsigned long long n_integrate;    // integration launches
+    unsigned long long n_raycast;      // raycast launches
+    uint32_t march_next;               // ray queue head of the running march
+    uint32_t march_done;               // waves of the running march that finished
+};
+
+// device view of one volume (by value into every kernel)
+struct Vol {
+    DEntry *entries;
+    uint8_t *vis;
+    int32_t *free_blocks;
+    int32_t *free_excess;
+    uint8_t *voxels;                // n_blocks x kBlockBytes
+    int32_t *vlist;
+    unsigned long long *reqset;     // open-addressing set of requested keys
+    Req *reqs;
+    int32_t *ret;
+    float *depth;                   // metres, last ingested frame
+    Rec *recs;
+    int32_t *bins;
+    int32_t *bin_count;
+    Ctrl *ctrl;
+    unsigned long long *acc_cols;   // per integration workgroup: 8-voxel columns written back
+    unsigned long long *acc_hits;   // per ray-march workgroup: pixels with a hit
+    float2 *range;                  // per-pixel search range (zmin, zmax), then march result (t, F)
+    uint32_t *occ;                  // bucket-occupancy bitmap: bit h set once any entry hashes to h
+    uint8_t *host_has;              // swapping: 1 if the host store holds data for the entry
+    int32_t *xfer_idx;              // swapping: transfer-buffer entry indices
+    uint8_t *xfer_vox;              // swapping: transfer-buffer blocks
+    uint32_t n_buckets, n_excess, n_entries, n_blocks;
+    uint32_t reqset_mask, max_req;
+    uint32_t transfer_blocks;
+    float voxel, mu;
+    int32_t max_w;
+};
+
+// camera constants of one call (by value)
+struct Cam {
+    float M[12];      // world -> camera rows [R | t]
+    float Ri[9];      // camera -> world rotation R^T
+    float ti[3];      // camera -> world translation -R^T t
+    float fx, fy, cx, cy;
+    int32_t W, H;
+};
+
+// workspace carving
+struct Layout {
+    size_t entries, vis, free_blocks, free_excess, voxels, vlist, reqset, reqs, ret, depth,
+        recs, bins, bin_count, ctrl, acc_cols, acc_hits, range, occ, host_has, xfer_idx, xfer_vox, total;
+    uint32_t reqset_size, max_req, max_tiles;
+};
+
+// ---- kernel launchers (tsdf_kernels.hip) -----------------------------------
+hipError_t launch_init(const Vol &v, hipStream_t s);
+hipError_t launch_clear_bins(int32_t *bin_count, uint32_t n, hipStream_t s);
+hipError_t launch_alloc_rays(const Vol &v, const Cam &c, const void *depth, int fmt, hipStream_t s);
+hipError_t launch_insert(const Vol &v, const Cam &c, hipStream_t s);
+hipError_t launch_visible(const Vol &v, hipStream_t s);
+hipError_t launch_depth_convert(const Vol &v, const void *depth, int fmt, int n, hipStream_t s);
+hipError_t launch_integrate(const Vol &v, const Cam &c, hipStream_t s);
+hipError_t launch_range_bin(const Vol &v, const Cam &c, bool all_blocks, hipStream_t s);
+hipError_t launch_range_image(const Vol &v, const Cam &c, hipStream_t s);
+hipError_t launch_march(const Vol &v, const Cam &c, hipStream_t s);
+hipError_t launch_finalize(const Vol &v, const Cam &c, float4 *pts, float4 *nrm, hipStream_t s);
+hipError_t launch_range_write(const Vol &v, const Cam &c, float *zmin, float *zmax, hipStream_t s);
+hipError_t launch_export_voxels(const Vol &v, const int32_t *ids, uint32_t n, int16_t *sdf,
+                                uint8_t *w, hipStream_t s);
+
+}  // namespace tsdf

@@ -137,3 +137,13 @@ def c2_frames(n: int = 300, seed_index: int = 0, first: int = 0, noise: bool = T
     poses = c2_poses(max(300, first + n), seed_index)[first:first + n]
     depth = noisy_u16_frames(scene, poses, KINECT_INTR, 2, seed_index, noise)
     return depth, np.stack(poses).astype(np.float32), KINECT_INTR, scene
+
+
+def c2_frame(k: int, seed_index: int = 0, noise: bool = True) -> np.ndarray:
+    """Trajectory frame k of C2 as uint16 mm (same values as c2_frames)."""
+    scene = c2_scene(seed_index)
+    P = c2_poses(max(300, k + 1), seed_index)[k]
+    z = render_depth(scene, P, KINECT_INTR)
+    if noise:
+        z = kinect_noise(z, rng_for(2, 100000 + 1000 * seed_index + k))
+    return to_mm_u16(z)
