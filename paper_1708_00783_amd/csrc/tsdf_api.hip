@@ -88,7 +88,6 @@ Layout make_layout(const tf_params *p)
     L.acc_cols = take((size_t)kIntegrateGrid * 8);
     L.acc_hits = take((size_t)L.max_tiles * 8);
     L.occ = take((size_t)p->n_buckets / 8);
-    L.range = take((size_t)p->max_width * p->max_height * 8);
     if (p->swap_transfer_blocks) {
         L.host_has = take(n_vis);
         L.xfer_idx = take((size_t)p->swap_transfer_blocks * 4);
@@ -234,7 +233,6 @@ int tf_create(const tf_params *p, void *d_workspace, size_t bytes, void *h_store
     v.ctrl = (Ctrl *)(b + L.ctrl);
     v.acc_cols = (unsigned long long *)(b + L.acc_cols);
     v.acc_hits = (unsigned long long *)(b + L.acc_hits);
-    v.range = (float2 *)(b + L.range);
     v.occ = (uint32_t *)(b + L.occ);
     v.host_has = p->swap_transfer_blocks ? b + L.host_has : nullptr;
     v.xfer_idx = p->swap_transfer_blocks ? (int32_t *)(b + L.xfer_idx) : nullptr;
@@ -391,11 +389,7 @@ int tf_raycast(tf_ctx *ctx, const float pose_w2c[16], const tf_intrinsics *intr,
     }
     if (e != hipSuccess) return TF_E_HIP;
     Timed t(ctx, TF_K_RAYCAST, s);
-    e = launch_range_image(ctx->v, c, s);
-    if (e != hipSuccess) return TF_E_HIP;
-    e = launch_march(ctx->v, c, s);
-    if (e != hipSuccess) return TF_E_HIP;
-    return hip_status(launch_finalize(ctx->v, c, (float4 *)d_points, (float4 *)d_normals, s));
+    return hip_status(launch_raycast(ctx->v, c, (float4 *)d_points, (float4 *)d_normals, s));
 }
 
 int tf_range_image(tf_ctx *ctx, const float pose_w2c[16], const tf_intrinsics *intr, float *d_zmin, float *d_zmax,

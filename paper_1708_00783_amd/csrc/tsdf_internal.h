@@ -19,7 +19,6 @@ constexpr float kZNear = 0.05f;         // near plane of the search-range projec
 constexpr int kMaxRaySteps = 65536;     // hard bound on raycast iterations
 constexpr int kMaxSegmentSamples = 64;  // samples kept per pixel segment
 constexpr int kIntegrateGrid = 2048;    // workgroups of the integration launch
-constexpr int kMarchGrid = 1024;        // workgroups of the persistent ray-march launch
 
 // vis[] byte per hash entry, reset by the visible-list compaction
 constexpr uint8_t kVisTouched = 1;      // touched by a ray segment or kept in view
@@ -70,8 +69,6 @@ struct alignas(256) Ctrl {
     unsigned long long tot_new;        // blocks inserted
     unsigned long long n_integrate;    // integration launches
     unsigned long long n_raycast;      // raycast launches
-    uint32_t march_next;               // ray queue head of the running march
-    uint32_t march_done;               // waves of the running march that finished
 };
 
 // device view of one volume (by value into every kernel)
@@ -91,8 +88,7 @@ struct Vol {
     int32_t *bin_count;
     Ctrl *ctrl;
     unsigned long long *acc_cols;   // per integration workgroup: 8-voxel columns written back
-    unsigned long long *acc_hits;   // per ray-march workgroup: pixels with a hit
-    float2 *range;                  // per-pixel search range (zmin, zmax), then march result (t, F)
+    unsigned long long *acc_hits;   // per raycast tile: pixels with a hit
     uint32_t *occ;                  // bucket-occupancy bitmap: bit h set once any entry hashes to h
     uint8_t *host_has;              // swapping: 1 if the host store holds data for the entry
     int32_t *xfer_idx;              // swapping: transfer-buffer entry indices
@@ -116,7 +112,7 @@ struct Cam {
 // workspace carving
 struct Layout {
     size_t entries, vis, free_blocks, free_excess, voxels, vlist, reqset, reqs, ret, depth,
-        recs, bins, bin_count, ctrl, acc_cols, acc_hits, range, occ, host_has, xfer_idx, xfer_vox, total;
+        recs, bins, bin_count, ctrl, acc_cols, acc_hits, occ, host_has, xfer_idx, xfer_vox, total;
     uint32_t reqset_size, max_req, max_tiles;
 };
 
@@ -129,9 +125,8 @@ hipError_t launch_visible(const Vol &v, hipStream_t s);
 hipError_t launch_depth_convert(const Vol &v, const void *depth, int fmt, int n, hipStream_t s);
 hipError_t launch_integrate(const Vol &v, const Cam &c, hipStream_t s);
 hipError_t launch_range_bin(const Vol &v, const Cam &c, bool all_blocks, hipStream_t s);
-hipError_t launch_range_image(const Vol &v, const Cam &c, hipStream_t s);
-hipError_t launch_march(const Vol &v, const Cam &c, hipStream_t s);
-hipError_t launch_finalize(const Vol &v, const Cam &c, float4 *pts, float4 *nrm, hipStream_t s);
+hipError_t launch_raycast(const Vol &v, const Cam &c, float4 *pts, float4 *nrm, hipStream_t s);
+
 hipError_t launch_range_write(const Vol &v, const Cam &c, float *zmin, float *zmax, hipStream_t s);
 hipError_t launch_export_voxels(const Vol &v, const int32_t *ids, uint32_t n, int16_t *sdf,
                                 uint8_t *w, hipStream_t s);

@@ -24,6 +24,14 @@ namespace {
 
 constexpr int kWave = 64;
 
+// tuning knobs of the raycast (compile-time)
+#ifndef TSDF_RAY_XCD_BANDS
+#define TSDF_RAY_XCD_BANDS 1    // give each XCD a contiguous band of tiles
+#endif
+#ifndef TSDF_RAY_BITMAP
+#define TSDF_RAY_BITMAP 1       // consult the bucket-occupancy bitmap before an entry
+#endif
+
 __device__ __forceinline__ uint32_t hash_index(int x, int y, int z, uint32_t mask)
 {
     // Sec. 3.2 hashIndex
@@ -55,9 +63,20 @@ __device__ __forceinline__ uint32_t mix_key(unsigned long long k)
     return (uint32_t)k;
 }
 
+// loads through global-address-space pointers (the Vol pointers arrive
+// inside a by-value struct, so the compiler cannot infer their space)
+template <typename T>
+__device__ __forceinline__ T gload(const T *p)
+{
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ int4 load_entry(const DEntry *e, uint32_t i)
 {
-    return *reinterpret_cast<const int4 *>(e + i);
+    const v4i w = gload(reinterpret_cast<const v4i *>(e + i));
+    return make_int4(w.x, w.y, w.z, w.w);
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -496,22 +515,38 @@ __global__ __launch_bounds__(256) void k_integrate(Vol v, Cam c)
         const float p0 = c.M[0] * X + c.M[1] * Y;
         const float p1 = c.M[4] * X + c.M[5] * Y;
         const float p2 = c.M[8] * X + c.M[9] * Y;
-        bool changed = false;
+        // phase 1: projection of the column's 8 voxels (no memory traffic)
+        float czs[8];
+        int idx[8];
+        bool inimg[8];
 #pragma unroll
         for (int lz = 0; lz < 8; ++lz) {
             const float Z = (float)(8 * bz + lz) * vs;
             const float cx = (p0 + c.M[2] * Z) + c.M[3];
             const float cy = (p1 + c.M[6] * Z) + c.M[7];
             const float cz = (p2 + c.M[10] * Z) + c.M[11];
-            if (cz <= 0.0f) continue;
-            const float rz = 1.0f / cz;
+            czs[lz] = cz;
+            bool ok = cz > 0.0f;
+            const float rz = 1.0f / (ok ? cz : 1.0f);
             const float u = (c.fx * cx) * rz + c.cx;
             const float vv = (c.fy * cy) * rz + c.cy;
-            if (u < 1.0f || u > umax || vv < 1.0f || vv > vmax) continue;
-            const int ix = (int)(u + 0.5f), iy = (int)(vv + 0.5f);
-            const float d = depth[ix + iy * W];
+            ok = ok && !(u < 1.0f || u > umax || vv < 1.0f || vv > vmax);
+            const int ix = ok ? (int)(u + 0.5f) : 0, iy = ok ? (int)(vv + 0.5f) : 0;
+            inimg[lz] = ok;
+            idx[lz] = ix + iy * W;
+        }
+        // phase 2: the 8 depth reads, issued together
+        float dep[8];
+#pragma unroll
+        for (int lz = 0; lz < 8; ++lz) dep[lz] = gload(depth + idx[lz]);
+        // phase 3: the running-average update (Sec. 4.3)
+        bool changed = false;
+#pragma unroll
+        for (int lz = 0; lz < 8; ++lz) {
+            if (!inimg[lz]) continue;
+            const float d = dep[lz];
             if (d <= 0.0f) continue;
-            const float eta = d - cz;
+            const float eta = d - czs[lz];
             if (eta < neg_mu) continue;
             float f_new = eta * inv_mu;
             if (f_new > 1.0f) f_new = 1.0f;
@@ -660,7 +695,7 @@ __device__ void finish_tile(const Vol &v, int tile, bool count_raycast)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
-        v.bin_count[tile] = 0;
+        if (tile >= 0) v.bin_count[tile] = 0;
         __threadfence();
         const uint32_t t = atomicAdd(&v.ctrl->ray_ticket, 1u);
         if (t == gridDim.x - 1u) {
@@ -676,163 +711,74 @@ __device__ void finish_tile(const Vol &v, int tile, bool count_raycast)
 // ============================================================================
 namespace {
 
-// Resolve N block keys to device block pointers (-1 if absent or not on the
-// device) with all bucket loads issued before any result is examined; chains
-// are followed only for the keys that need it.
-template <int N>
-__device__ __forceinline__ void resolve_blocks(const Vol &v, const int (&bx)[N], const int (&by)[N],
-                                               const int (&bz)[N], int (&out)[N])
-{
-    uint32_t h[N], bits[N];
-    bool ok[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        ok[i] = in_short_range(bx[i]) && in_short_range(by[i]) && in_short_range(bz[i]);
-        h[i] = hash_index(bx[i], by[i], bz[i], v.n_buckets - 1u);
-        bits[i] = v.occ[h[i] >> 5];            // a few KB-to-MB bitmap, L2 resident
-    }
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        int r = -1;
-        if (ok[i] && ((bits[i] >> (h[i] & 31u)) & 1u)) {
-            const uint32_t kxy = (uint32_t)(uint16_t)bx[i] | ((uint32_t)(uint16_t)by[i] << 16);
-            int4 e = load_entry(v.entries, h[i]);
-            for (uint32_t it = 0; it <= v.n_excess; ++it) {
-                if ((uint32_t)e.x == kxy && (int16_t)(e.y & 0xffff) == (int16_t)bz[i] && e.w >= 0) {
-                    r = e.w;
-                    break;
-                }
-                if (e.z < 1 || (uint32_t)(e.z - 1) >= v.n_excess) break;
-                e = load_entry(v.entries, v.n_buckets + (uint32_t)(e.z - 1));
-            }
-        }
-        out[i] = r;
-    }
-}
-
-// four most recent (block key -> device pointer) results of this ray; a
-// shift register (static indices only, so it stays in registers)
-struct ProbeCache {
-    int x[4], y[4], z[4], ptr[4];
-    __device__ void clear()
-    {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            x[i] = 0x7fffffff;
-            y[i] = z[i] = 0;
-            ptr[i] = -1;
-        }
-    }
-    // branch-free lookup (any matching slot holds the same pointer: the
-    // table does not change during a raycast)
-    __device__ __forceinline__ bool find(int bx, int by, int bz, int &p) const
-    {
-        bool hit = false;
-        int r = -1;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const bool m = (x[i] == bx) & (y[i] == by) & (z[i] == bz);
-            r = m ? ptr[i] : r;
-            hit |= m;
-        }
-        p = r;
-        return hit;
-    }
-    __device__ __forceinline__ void put(int bx, int by, int bz, int p)
-    {
-#pragma unroll
-        for (int i = 3; i > 0; --i) {
-            x[i] = x[i - 1];
-            y[i] = y[i - 1];
-            z[i] = z[i - 1];
-            ptr[i] = ptr[i - 1];
-        }
-        x[0] = bx;
-        y[0] = by;
-        z[0] = bz;
-        ptr[0] = p;
-    }
-};
-
 __device__ __forceinline__ int block_of(float X) { return ((int)floorf(X)) >> 3; }
 
-// "allocated" test of the march (block of floor(P) has a device block).  On a
-// cache miss the block of P and of the next three positions the march visits
-// while it keeps finding unallocated space (t + step, t + 2 step, ...,
-// accumulated in float exactly as the march does) are resolved together.
-__device__ __forceinline__ bool allocated_at(const Vol &v, float ox, float oy, float oz, float dx, float dy,
-                                             float dz, float t, float step, ProbeCache &pc)
+// one-entry block cache (the paper's IndexCache, Sec. 3.3): the last block
+// key looked up and its device pointer (-1 = absent or not on the device)
+struct BlockCache {
+    int bx, by, bz, ptr;
+};
+
+// device pointer of a block (-1 = absent or not on the device); the bucket
+// bitmap answers most probes of empty space without touching the entries
+__device__ __forceinline__ int lookup_block(const Vol &v, int bx, int by, int bz)
 {
-    const float P0 = ox + t * dx, P1 = oy + t * dy, P2 = oz + t * dz;
-    const int b0 = block_of(P0), b1 = block_of(P1), b2 = block_of(P2);
-    int p;
-    if (pc.find(b0, b1, b2, p)) return p >= 0;
-    int kx[4], ky[4], kz[4], r[4];
-    kx[0] = b0;
-    ky[0] = b1;
-    kz[0] = b2;
-    float tt = t;
-#pragma unroll
-    for (int i = 1; i < 4; ++i) {
-        tt += step;
-        kx[i] = block_of(ox + tt * dx);
-        ky[i] = block_of(oy + tt * dy);
-        kz[i] = block_of(oz + tt * dz);
-    }
-    resolve_blocks<4>(v, kx, ky, kz, r);
-#pragma unroll
-    for (int i = 3; i >= 0; --i) pc.put(kx[i], ky[i], kz[i], r[i]);
-    return r[0] >= 0;
+    int ptr = -1, e = -1;
+#if TSDF_RAY_BITMAP
+    const uint32_t h = hash_index(bx, by, bz, v.n_buckets - 1u);
+    if ((gload(v.occ + (h >> 5)) >> (h & 31u)) & 1u) e = find_entry(v, bx, by, bz, 0, &ptr);
+#else
+    e = find_entry(v, bx, by, bz, 0, &ptr);
+#endif
+    return e >= 0 ? ptr : -1;
 }
 
-__device__ __forceinline__ float sdf_of(const Vol &v, int p, int j)
+__device__ __forceinline__ int cached_block(const Vol &v, int bx, int by, int bz, BlockCache &cc)
 {
-    return (float)reinterpret_cast<const int16_t *>(v.voxels + (size_t)p * kBlockBytes)[j] * (1.0f / 32767.0f);
+    if (bx == cc.bx && by == cc.by && bz == cc.bz) return cc.ptr;
+    cc.bx = bx;
+    cc.by = by;
+    cc.bz = bz;
+    cc.ptr = lookup_block(v, bx, by, bz);
+    return cc.ptr;
+}
+
+__device__ __forceinline__ float corner_F(const Vol &v, int p, int x, int y, int z)
+{
+    const int j = (z & 7) + 8 * (y & 7) + 64 * (x & 7);
+    const int16_t s = gload(reinterpret_cast<const int16_t *>(v.voxels + (size_t)(p >= 0 ? p : 0) * kBlockBytes) +
+                            (p >= 0 ? j : 0));
+    return p >= 0 ? (float)s * (1.0f / 32767.0f) : 1.0f;
 }
 
 // trilinear interpolation of F at voxel-unit P (absent voxels read 1.0):
-// lerp a + (b - a) t along x, then y, then z
-__device__ __forceinline__ float trilinear(const Vol &v, float X, float Y, float Z, ProbeCache &pc)
+// lerp a + (b - a) t along x, then y, then z.  The corner blocks are resolved
+// first (the cell's own block through the ray's cache; blocks across a face,
+// when the cell crosses one, by direct lookups), then the eight voxel loads
+// are issued together.
+__device__ __forceinline__ float trilinear(const Vol &v, float X, float Y, float Z, BlockCache &cc)
 {
     const float bx = floorf(X), by = floorf(Y), bz = floorf(Z);
     const float tx = X - bx, ty = Y - by, tz = Z - bz;
     const int ix = (int)bx, iy = (int)by, iz = (int)bz;
-    const int lx = ix & 7, ly = iy & 7, lz = iz & 7;
-    float f000, f100, f010, f110, f001, f101, f011, f111;
-    // the cell's corners lie in the block of (ix, iy, iz) and, along each axis
-    // where the cell crosses a block face (local index 7), its neighbour;
-    // distinct blocks are resolved once (repeats hit the probe cache)
     const int Bx = ix >> 3, By = iy >> 3, Bz = iz >> 3;
-    const int sx = lx == 7, sy = ly == 7, sz = lz == 7;
-    int pb[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int qx = Bx + ((q & 1) & sx), qy = By + (((q >> 1) & 1) & sy), qz = Bz + (((q >> 2) & 1) & sz);
-        int p;
-        if (!pc.find(qx, qy, qz, p)) {
-            int kx[1] = {qx}, ky[1] = {qy}, kz[1] = {qz}, r[1];
-            resolve_blocks<1>(v, kx, ky, kz, r);
-            p = r[0];
-            pc.put(qx, qy, qz, p);
-        }
-        pb[q] = p;
+    const bool sx = (ix & 7) == 7, sy = (iy & 7) == 7, sz = (iz & 7) == 7;
+    const int p000 = cached_block(v, Bx, By, Bz, cc);
+    int p100 = p000, p010 = p000, p001 = p000, p110 = p000, p101 = p000, p011 = p000, p111 = p000;
+    if (sx | sy | sz) {
+        if (sx) p100 = lookup_block(v, Bx + 1, By, Bz);
+        if (sy) p010 = lookup_block(v, Bx, By + 1, Bz);
+        if (sz) p001 = lookup_block(v, Bx, By, Bz + 1);
+        p110 = (sx & sy) ? lookup_block(v, Bx + 1, By + 1, Bz) : (sx ? p100 : p010);
+        p101 = (sx & sz) ? lookup_block(v, Bx + 1, By, Bz + 1) : (sx ? p100 : p001);
+        p011 = (sy & sz) ? lookup_block(v, Bx, By + 1, Bz + 1) : (sy ? p010 : p001);
+        p111 = (sx & sy & sz) ? lookup_block(v, Bx + 1, By + 1, Bz + 1)
+                              : (sx & sy) ? p110 : (sx & sz) ? p101 : (sy & sz) ? p011 : sx ? p100 : sy ? p010 : p001;
     }
-    // pb[c] is the block of corner c (duplicates where no face is crossed)
-    float f[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int cx = lx + (c & 1), cy = ly + ((c >> 1) & 1), cz = lz + (c >> 2);
-        const int j = (cz & 7) + 8 * (cy & 7) + 64 * (cx & 7);
-        f[c] = pb[c] >= 0 ? sdf_of(v, pb[c], j) : 1.0f;
-    }
-    f000 = f[0];
-    f100 = f[1];
-    f010 = f[2];
-    f110 = f[3];
-    f001 = f[4];
-    f101 = f[5];
-    f011 = f[6];
-    f111 = f[7];
+    const float f000 = corner_F(v, p000, ix, iy, iz), f100 = corner_F(v, p100, ix + 1, iy, iz);
+    const float f010 = corner_F(v, p010, ix, iy + 1, iz), f110 = corner_F(v, p110, ix + 1, iy + 1, iz);
+    const float f001 = corner_F(v, p001, ix, iy, iz + 1), f101 = corner_F(v, p101, ix + 1, iy, iz + 1);
+    const float f011 = corner_F(v, p011, ix, iy + 1, iz + 1), f111 = corner_F(v, p111, ix + 1, iy + 1, iz + 1);
     const float c00 = f000 + (f100 - f000) * tx;
     const float c10 = f010 + (f110 - f010) * tx;
     const float c01 = f001 + (f101 - f001) * tx;
@@ -842,90 +788,81 @@ __device__ __forceinline__ float trilinear(const Vol &v, float X, float Y, float
     return c0 + (c1 - c0) * tz;
 }
 
+// "allocated" test of the march: the block of floor(P) has a device block
+__device__ __forceinline__ bool allocated_at(const Vol &v, float P0, float P1, float P2, BlockCache &cc)
+{
+    return cached_block(v, block_of(P0), block_of(P1), block_of(P2), cc) >= 0;
+}
+
 enum { SEARCH_BLOCK_COARSE, SEARCH_BLOCK_FINE, SEARCH_SURFACE, BEHIND_SURFACE, WRONG_SIDE };
 
 }  // namespace
 
-// Ray march (Sec. 4.4) as a persistent kernel: rays come from a queue in
-// 8x8-pixel groups of 16x16 tiles; a wave refills its idle lanes with one
-// atomic whenever at least a quarter of them are idle, so a long ray does not
-// hold 63 finished lanes.  Each lane carries one ray's march state.
-namespace {
-
-__device__ __forceinline__ int ray_pixel(uint32_t r, int ntx, int W, int H, int &px, int &py)
+// search range on its own, written as an image (tf_range_image)
+__global__ __launch_bounds__(256) void k_range_write(Vol v, Cam c, float *zmin_out, float *zmax_out)
 {
-    const uint32_t tile = r >> 8, q = (r >> 6) & 3u, i = r & 63u;
-    px = (int)((tile % (uint32_t)ntx) * 16u + (q & 1u) * 8u + (i & 7u));
-    py = (int)((tile / (uint32_t)ntx) * 16u + (q >> 1) * 8u + (i >> 3));
-    return (px < W && py < H) ? py * W + px : -1;
+    __shared__ Rec lds[256];
+    const int ntx = (c.W + kTile - 1) / kTile;
+    const int tile = blockIdx.x;
+    const int px = (tile % ntx) * kTile + (int)(threadIdx.x % kTile);
+    const int py = (tile / ntx) * kTile + (int)(threadIdx.x / kTile);
+    float zmin, zmax;
+    tile_range(v, tile, px, py, zmin, zmax, lds);
+    finish_tile(v, tile, false);
+    if (px >= c.W || py >= c.H) return;
+    zmin_out[(size_t)py * c.W + px] = zmin;
+    zmax_out[(size_t)py * c.W + px] = zmax;
 }
 
-}  // namespace
-
-__global__ __launch_bounds__(256) void k_march(Vol v, Cam c)
+// ============================================================================
+// raycast, one workgroup per 16x16 tile (Sec. 4.4): the tile's search range
+// from its bin (LDS), the state machine per pixel, then the two refinement
+// steps and the normal for the hits of the wave together
+// ============================================================================
+__global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, float4 *pts, float4 *nrm)
 {
-    const uint32_t lane = lane_id();
+    __shared__ Rec lds[256];
     const int ntx = (c.W + kTile - 1) / kTile, nty = (c.H + kTile - 1) / kTile;
-    const uint32_t nrays = (uint32_t)(ntx * nty) * 256u;
-    const float vs = v.voxel;
-    const float inv_vs = 1.0f / vs;
-    const float mu_v = v.mu * inv_vs;
-    const float ox = c.ti[0] * inv_vs, oy = c.ti[1] * inv_vs, oz = c.ti[2] * inv_vs;
-
-    bool active = false, exhausted = false;
-    int pix = -1, state = SEARCH_BLOCK_COARSE, steps = 0;
-    float t = 0.f, t_end = 0.f, F = 1.f, dx = 0.f, dy = 0.f, dz = 0.f;
-    ProbeCache cc;
-    cc.clear();
-
-    for (;;) {
-        const unsigned long long idle = __ballot(!active);
-        if (!exhausted && __popcll(idle) >= 16) {
-            const int n = __popcll(idle);
-            const int leader = __ffsll((long long)idle) - 1;
-            uint32_t base = 0;
-            if ((int)lane == leader) base = atomicAdd(&v.ctrl->march_next, (uint32_t)n);
-            base = __shfl(base, leader);
-            if (base + (uint32_t)n >= nrays) exhausted = true;
-            if (!active) {
-                const uint32_t r = base + rank_in(idle);
-                int px, py;
-                pix = r < nrays ? ray_pixel(r, ntx, c.W, c.H, px, py) : -1;
-                if (pix >= 0) {
-                    const float2 rg = v.range[pix];
-                    if (rg.x <= rg.y) {
-                        const float a = ((float)px - c.cx) / c.fx;
-                        const float b = ((float)py - c.cy) / c.fy;
-                        const float nr = sqrtf((a * a + b * b) + 1.0f);
-                        const float rcx = a / nr, rcy = b / nr, rcz = 1.0f / nr;
-                        dx = (c.Ri[0] * rcx + c.Ri[1] * rcy) + c.Ri[2] * rcz;
-                        dy = (c.Ri[3] * rcx + c.Ri[4] * rcy) + c.Ri[5] * rcz;
-                        dz = (c.Ri[6] * rcx + c.Ri[7] * rcy) + c.Ri[8] * rcz;
-                        t = (rg.x * nr) * inv_vs;
-                        t_end = (rg.y * nr) * inv_vs;
-                        state = SEARCH_BLOCK_COARSE;
-                        F = 1.0f;
-                        steps = 0;
-                        active = true;   // cached block pointers stay valid across rays
-                    } else {
-                        v.range[pix] = make_float2(0.0f, 2.0f);   // no search interval: miss
-                    }
-                }
-            }
-        }
-        if (__ballot(active) == 0ull) {
-            if (exhausted) break;
-            continue;
-        }
-        if (!active) continue;
-
-        // one iteration of the state machine
-        bool finished = !(t < t_end && steps < kMaxRaySteps);
-        if (!finished) {
+    const int ntiles = ntx * nty;
+#if TSDF_RAY_XCD_BANDS
+    // workgroups go round-robin to the 8 XCDs: XCD k gets the k-th band of
+    // tiles, so its L2 holds the blocks of one band of the image
+    const int per = (ntiles + 7) / 8;
+    const int tile = (int)(blockIdx.x % 8u) * per + (int)(blockIdx.x / 8u);
+#else
+    const int tile = (int)blockIdx.x;
+#endif
+    const bool real = tile < ntiles;
+    const int q = (int)threadIdx.x >> 6, i = (int)threadIdx.x & 63;
+    const int px = real ? (tile % ntx) * kTile + (q & 1) * 8 + (i & 7) : 0;
+    const int py = real ? (tile / ntx) * kTile + (q >> 1) * 8 + (i >> 3) : 0;
+    float zmin = __builtin_inff(), zmax = -__builtin_inff();
+    if (real) tile_range(v, tile, px, py, zmin, zmax, lds);
+    finish_tile(v, real ? tile : -1, true);
+    const bool inside = real && px < c.W && py < c.H;
+    float4 out_p = make_float4(0.f, 0.f, 0.f, 0.f), out_n = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (inside && zmin <= zmax) {
+        const float vs = v.voxel;
+        const float inv_vs = 1.0f / vs;
+        const float mu_v = v.mu * inv_vs;
+        const float ox = c.ti[0] * inv_vs, oy = c.ti[1] * inv_vs, oz = c.ti[2] * inv_vs;
+        const float a = ((float)px - c.cx) / c.fx;
+        const float b = ((float)py - c.cy) / c.fy;
+        const float nr = sqrtf((a * a + b * b) + 1.0f);
+        const float rcx = a / nr, rcy = b / nr, rcz = 1.0f / nr;
+        const float dx = (c.Ri[0] * rcx + c.Ri[1] * rcy) + c.Ri[2] * rcz;
+        const float dy = (c.Ri[3] * rcx + c.Ri[4] * rcy) + c.Ri[5] * rcz;
+        const float dz = (c.Ri[6] * rcx + c.Ri[7] * rcy) + c.Ri[8] * rcz;
+        float t = (zmin * nr) * inv_vs;
+        const float t_end = (zmax * nr) * inv_vs;
+        int state = SEARCH_BLOCK_COARSE;
+        float F = 1.0f;
+        BlockCache cc = {0x7fffffff, 0, 0, -1};
+        int steps = 0;
+        while (t < t_end && steps < kMaxRaySteps) {
             ++steps;
             const float P0 = ox + t * dx, P1 = oy + t * dy, P2 = oz + t * dz;
-            const bool alloc = allocated_at(v, ox, oy, oz, dx, dy, dz, t,
-                                            state == SEARCH_BLOCK_COARSE ? 8.0f : mu_v, cc);
+            const bool alloc = allocated_at(v, P0, P1, P2, cc);
             if (state == SEARCH_BLOCK_COARSE) {
                 if (!alloc) {
                     t += 8.0f;
@@ -943,11 +880,10 @@ __global__ __launch_bounds__(256) void k_march(Vol v, Cam c)
                 } else if (state == SEARCH_SURFACE) {
                     if (F < 0.0f) {
                         state = BEHIND_SURFACE;
-                        finished = true;
-                    } else {
-                        const float s = F * mu_v;
-                        t += (s > 1.0f) ? s : 1.0f;
+                        break;
                     }
+                    const float s = F * mu_v;
+                    t += (s > 1.0f) ? s : 1.0f;
                 } else {
                     if (F >= 0.0f) {
                         state = SEARCH_SURFACE;
@@ -958,54 +894,10 @@ __global__ __launch_bounds__(256) void k_march(Vol v, Cam c)
                 }
             }
         }
-        if (finished) {
-            // hit: (t, F) with F < 0 for the refinement pass; miss: F = 2
-            v.range[pix] = make_float2(t, state == BEHIND_SURFACE ? F : 2.0f);
-            active = false;
-        }
-    }
-
-    // the last workgroup resets the queue for the next launch
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t done = atomicAdd(&v.ctrl->march_done, 1u);
-        if (done == gridDim.x - 1u) {
-            v.ctrl->march_next = 0u;
-            v.ctrl->march_done = 0u;
-            v.ctrl->n_raycast += 1ull;
-        }
-    }
-}
-
-// Refinement and normals of the hits (Sec. 4.4): one lane per pixel, 8x8
-// pixels per wave; two steps t += F mu_v, then the SDF-gradient normal.
-__global__ __launch_bounds__(256) void k_finalize(Vol v, Cam c, float4 *pts, float4 *nrm)
-{
-    const int ntx = (c.W + kTile - 1) / kTile;
-    int px, py;
-    const int pix = ray_pixel(blockIdx.x * 256u + threadIdx.x, ntx, c.W, c.H, px, py);
-    uint32_t hit = 0;
-    if (pix >= 0) {
-        const float2 tf = v.range[pix];
-        float4 out_p = make_float4(0.f, 0.f, 0.f, 0.f), out_n = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (tf.y < 0.0f) {
-            const float vs = v.voxel;
-            const float inv_vs = 1.0f / vs;
-            const float mu_v = v.mu * inv_vs;
-            const float ox = c.ti[0] * inv_vs, oy = c.ti[1] * inv_vs, oz = c.ti[2] * inv_vs;
-            const float a = ((float)px - c.cx) / c.fx;
-            const float b = ((float)py - c.cy) / c.fy;
-            const float nr = sqrtf((a * a + b * b) + 1.0f);
-            const float rcx = a / nr, rcy = b / nr, rcz = 1.0f / nr;
-            const float dx = (c.Ri[0] * rcx + c.Ri[1] * rcy) + c.Ri[2] * rcz;
-            const float dy = (c.Ri[3] * rcx + c.Ri[4] * rcy) + c.Ri[5] * rcz;
-            const float dz = (c.Ri[6] * rcx + c.Ri[7] * rcy) + c.Ri[8] * rcz;
-            ProbeCache cc;
-            cc.clear();
-            float t = tf.x + tf.y * mu_v;
+        if (state == BEHIND_SURFACE) {
+            t += F * mu_v;
             float P0 = ox + t * dx, P1 = oy + t * dy, P2 = oz + t * dz;
-            const float F = trilinear(v, P0, P1, P2, cc);
+            F = trilinear(v, P0, P1, P2, cc);
             t += F * mu_v;
             P0 = ox + t * dx;
             P1 = oy + t * dy;
@@ -1016,47 +908,19 @@ __global__ __launch_bounds__(256) void k_finalize(Vol v, Cam c, float4 *pts, flo
             const float gz = (trilinear(v, P0, P1, P2 + 1.0f, cc) - trilinear(v, P0, P1, P2 - 1.0f, cc)) * 0.5f;
             const float gn = sqrtf((gx * gx + gy * gy) + gz * gz);
             if (gn > 0.0f) out_n = make_float4(gx / gn, gy / gn, gz / gn, 1.0f);
-            hit = 1;
         }
-        pts[pix] = out_p;
-        nrm[pix] = out_n;
     }
     __shared__ uint32_t wg_hits;
     if (threadIdx.x == 0) wg_hits = 0;
     __syncthreads();
-    if (hit) atomicAdd(&wg_hits, 1u);
+    if (inside) {
+        const size_t p = (size_t)py * c.W + px;
+        pts[p] = out_p;
+        nrm[p] = out_n;
+        if (out_p.w == 1.0f) atomicAdd(&wg_hits, 1u);
+    }
     __syncthreads();
-    if (threadIdx.x == 0 && wg_hits) v.acc_hits[blockIdx.x] += wg_hits;
-}
-
-
-__global__ __launch_bounds__(256) void k_range_image(Vol v, Cam c)
-{
-    __shared__ Rec lds[256];
-    const int ntx = (c.W + kTile - 1) / kTile;
-    const int tile = blockIdx.x;
-    const int px = (tile % ntx) * kTile + (int)(threadIdx.x % kTile);
-    const int py = (tile / ntx) * kTile + (int)(threadIdx.x / kTile);
-    float zmin, zmax;
-    tile_range(v, tile, px, py, zmin, zmax, lds);
-    finish_tile(v, tile, true);
-    if (px >= c.W || py >= c.H) return;
-    v.range[(size_t)py * c.W + px] = make_float2(zmin, zmax);
-}
-
-__global__ __launch_bounds__(256) void k_range_write(Vol v, Cam c, float *zmin_out, float *zmax_out)
-{
-    __shared__ Rec lds[256];
-    const int ntx = (c.W + kTile - 1) / kTile;
-    const int tile = blockIdx.x;
-    const int px = (tile % ntx) * kTile + (int)(threadIdx.x % kTile);
-    const int py = (tile / ntx) * kTile + (int)(threadIdx.x / kTile);
-    float zmin, zmax;
-    tile_range(v, tile, px, py, zmin, zmax, lds);
-    finish_tile(v, tile, false);
-    if (px >= c.W || py >= c.H) return;
-    zmin_out[(size_t)py * c.W + px] = zmin;
-    zmax_out[(size_t)py * c.W + px] = zmax;
+    if (threadIdx.x == 0 && wg_hits) v.acc_hits[tile] += wg_hits;
 }
 
 // ============================================================================
@@ -1159,23 +1023,15 @@ hipError_t launch_range_bin(const Vol &v, const Cam &c, bool all_blocks, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_range_image(const Vol &v, const Cam &c, hipStream_t s)
+hipError_t launch_raycast(const Vol &v, const Cam &c, float4 *pts, float4 *nrm, hipStream_t s)
 {
     const int ntiles = ((c.W + kTile - 1) / kTile) * ((c.H + kTile - 1) / kTile);
-    hipLaunchKernelGGL(k_range_image, dim3(ntiles), dim3(256), 0, s, v, c);
-    return hipGetLastError();
-}
-
-hipError_t launch_march(const Vol &v, const Cam &c, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_march, dim3(kMarchGrid), dim3(256), 0, s, v, c);
-    return hipGetLastError();
-}
-
-hipError_t launch_finalize(const Vol &v, const Cam &c, float4 *pts, float4 *nrm, hipStream_t s)
-{
-    const int ntiles = ((c.W + kTile - 1) / kTile) * ((c.H + kTile - 1) / kTile);
-    hipLaunchKernelGGL(k_finalize, dim3(ntiles), dim3(256), 0, s, v, c, pts, nrm);
+#if TSDF_RAY_XCD_BANDS
+    const int grid = ((ntiles + 7) / 8) * 8;
+#else
+    const int grid = ntiles;
+#endif
+    hipLaunchKernelGGL(k_raycast, dim3(grid), dim3(256), 0, s, v, c, pts, nrm);
     return hipGetLastError();
 }
 
