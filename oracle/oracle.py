@@ -73,6 +73,10 @@ def lib():
             "or_get_visible": (ctypes.c_int, [_VP, _I32]),
             "or_get_block_voxels": (None, [_VP, _I32, ctypes.c_int, _I16, _U8]),
             "or_get_host_block": (ctypes.c_int, [_VP, ctypes.c_int, _I16, _U8]),
+            "or_compose": (None, [_F, _F, _F]),
+            "or_multi_range": (None, [_VP, _F, ctypes.c_int, ctypes.c_int, ctypes.c_int, _F, _F, _F, _F]),
+            "or_multi_raycast": (None, [_VP, _F, ctypes.c_int, ctypes.c_int, ctypes.c_int, _F, _F, _F, _F,
+                                        _F, _F]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -270,6 +274,49 @@ class Volume:
         self.integrate(depth_m, intr, pose)
         H0, W0 = np.shape(depth_m)
         return self.raycast(W or W0, H or H0, intr, pose)
+
+
+def compose(A, P) -> np.ndarray:
+    """A * inv(P) (rigid, double, rounded once): the camera matrix of a submap"""
+    A = np.ascontiguousarray(A, np.float32).reshape(16)
+    P = np.ascontiguousarray(P, np.float32).reshape(16)
+    out = np.empty(16, np.float32)
+    lib().or_compose(_p(A, _F), _p(P, _F), _p(out, _F))
+    return out.reshape(4, 4)
+
+
+class Multi:
+    """Rigid submaps (Sec. 7.2): volumes with poses P_i (world -> submap)."""
+
+    def __init__(self, vols, poses):
+        self.vols = list(vols)
+        self.poses = np.ascontiguousarray(np.asarray(poses, np.float32).reshape(len(self.vols), 16))
+        self._arr = (ctypes.c_void_p * len(self.vols))(*[v._h for v in self.vols])
+
+    def integrate_frame(self, i, depth_m, intr, M_d):
+        """allocate + integrate one frame into submap i (camera M_d composed with P_i)"""
+        Mi = compose(M_d, self.poses[i])
+        self.vols[i].alloc_and_visible(depth_m, intr, Mi)
+        self.vols[i].integrate(depth_m, intr, Mi)
+
+    def range_image(self, W, H, intr, V):
+        k = np.ascontiguousarray(intr, np.float32)
+        Vv = np.ascontiguousarray(V, np.float32).reshape(16)
+        zmin = np.empty((H, W), np.float32)
+        zmax = np.empty((H, W), np.float32)
+        lib().or_multi_range(ctypes.cast(self._arr, _VP), _p(self.poses, _F), len(self.vols), W, H, _p(k, _F),
+                             _p(Vv, _F), _p(zmin, _F), _p(zmax, _F))
+        return zmin, zmax
+
+    def raycast(self, W, H, intr, V):
+        zmin, zmax = self.range_image(W, H, intr, V)
+        k = np.ascontiguousarray(intr, np.float32)
+        Vv = np.ascontiguousarray(V, np.float32).reshape(16)
+        pts = np.empty((H, W, 4), np.float32)
+        nrm = np.empty((H, W, 4), np.float32)
+        lib().or_multi_raycast(ctypes.cast(self._arr, _VP), _p(self.poses, _F), len(self.vols), W, H, _p(k, _F),
+                               _p(Vv, _F), _p(zmin, _F), _p(zmax, _F), _p(pts, _F), _p(nrm, _F))
+        return pts, nrm
 
 
 def sort_rows(a: np.ndarray) -> np.ndarray:

@@ -856,3 +856,255 @@ int or_get_host_block(const or_volume *v, int entry, int16_t *sdf, uint8_t *w)
     memcpy(w, &v->host_w[(size_t)entry * OR_BLOCK_VOX], OR_BLOCK_VOX);
     return 1;
 }
+
+/* ==========================================================================
+ * Submaps (Sec. 7.2).  Submap i is an ordinary volume with its own voxel
+ * grid; P_i is its pose, mapping world points into the submap frame.
+ * ========================================================================== */
+
+/* rigid inverse in double: [R^T | -R^T t] */
+static void invert_pose_d(const float *P, double *Q)
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Q[4 * i + j] = (double)P[4 * j + i];
+    for (int i = 0; i < 3; ++i)
+        Q[4 * i + 3] = -(((double)P[i] * (double)P[3] + (double)P[4 + i] * (double)P[7]) + (double)P[8 + i] * (double)P[11]);
+    Q[12] = Q[13] = Q[14] = 0.0;
+    Q[15] = 1.0;
+}
+
+/* A * inv(P) for rigid 4x4 transforms, in double, rounded once to float:
+ * the camera matrix of a submap (world->camera composed with submap->world) */
+void or_compose(const float *A, const float *P, float *out)
+{
+    double Q[16];
+    invert_pose_d(P, Q);
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+            double s = (((double)A[4 * r] * Q[c] + (double)A[4 * r + 1] * Q[4 + c]) + (double)A[4 * r + 2] * Q[8 + c]) +
+                       (double)A[4 * r + 3] * Q[12 + c];
+            out[4 * r + c] = (float)s;
+        }
+}
+
+/* search range of a view over the blocks of every submap (each projected
+ * with the composed matrix V * inv(P_i)); the reading of Sec. 4.4 applied to
+ * all submaps: min/max camera z over the boxes covering the pixel */
+void or_multi_range(or_volume **vols, const float *poses, int n, int W, int H, const float *intr, const float *V,
+                    float *zmin, float *zmax)
+{
+    float *zlo = (float *)malloc(sizeof(float) * (size_t)W * H);
+    float *zhi = (float *)malloc(sizeof(float) * (size_t)W * H);
+    for (int p = 0; p < W * H; ++p) {
+        zmin[p] = INFINITY;
+        zmax[p] = -INFINITY;
+    }
+    for (int i = 0; i < n; ++i) {
+        float C[16];
+        or_compose(V, &poses[16 * i], C);
+        or_range(vols[i], NULL, -1, W, H, intr, C, zlo, zhi);
+        for (int p = 0; p < W * H; ++p) {
+            if (zlo[p] < zmin[p]) zmin[p] = zlo[p];
+            if (zhi[p] > zmax[p]) zmax[p] = zhi[p];
+        }
+    }
+    free(zlo);
+    free(zhi);
+}
+
+static float read_W(const or_volume *v, int x, int y, int z)
+{
+    int bx = floor_div8(x), by = floor_div8(y), bz = floor_div8(z);
+    int i = find_entry(v, bx, by, bz, 0);
+    if (i < 0) return 0.0f;
+    int l = (x - 8 * bx) + 8 * (y - 8 * by) + 64 * (z - 8 * bz);
+    return (float)v->w[(size_t)v->e[i].ptr * OR_BLOCK_VOX + l];
+}
+
+/* trilinear interpolation of the weight (absent voxels weigh 0), same
+ * order of operations as or_trilinear */
+static float trilinear_w(const or_volume *v, float X, float Y, float Z)
+{
+    float bx = floorf(X), by = floorf(Y), bz = floorf(Z);
+    float tx = X - bx, ty = Y - by, tz = Z - bz;
+    int ix = (int)bx, iy = (int)by, iz = (int)bz;
+    float f000 = read_W(v, ix, iy, iz), f100 = read_W(v, ix + 1, iy, iz);
+    float f010 = read_W(v, ix, iy + 1, iz), f110 = read_W(v, ix + 1, iy + 1, iz);
+    float f001 = read_W(v, ix, iy, iz + 1), f101 = read_W(v, ix + 1, iy, iz + 1);
+    float f011 = read_W(v, ix, iy + 1, iz + 1), f111 = read_W(v, ix + 1, iy + 1, iz + 1);
+    float c00 = f000 + (f100 - f000) * tx;
+    float c10 = f010 + (f110 - f010) * tx;
+    float c01 = f001 + (f101 - f001) * tx;
+    float c11 = f011 + (f111 - f011) * tx;
+    float c0 = c00 + (c10 - c00) * ty;
+    float c1 = c01 + (c11 - c01) * ty;
+    return c0 + (c1 - c0) * tz;
+}
+
+typedef struct {
+    or_volume **vols;
+    int n;
+    float R[64][9];   /* per submap: rotation of P_i */
+    float s[64][3];   /* per submap: translation of P_i in voxel units */
+} or_multi_view;
+
+/* position of world voxel-unit point P in submap i's voxel units:
+ * Q = R_i P + t_i / v, each row ((r0 P0 + r1 P1) + r2 P2) + s */
+static void to_submap(const or_multi_view *m, int i, const float *P, float *Q)
+{
+    for (int r = 0; r < 3; ++r)
+        Q[r] = ((m->R[i][3 * r] * P[0] + m->R[i][3 * r + 1] * P[1]) + m->R[i][3 * r + 2] * P[2]) + m->s[i][r];
+}
+
+static int multi_allocated(const or_multi_view *m, const float *P)
+{
+    for (int i = 0; i < m->n; ++i) {
+        float Q[3];
+        to_submap(m, i, P, Q);
+        if (allocated_at(m->vols[i], Q[0], Q[1], Q[2])) return 1;
+    }
+    return 0;
+}
+
+/* combined field F^ at world voxel-unit P: the weighted average of the
+ * submaps' trilinear F, weighted by their trilinear weight, over the submaps
+ * with a non-zero weight there; a single contributor gives its F unchanged;
+ * none gives 1 (every corner of every submap reads the default voxel then) */
+static float multi_F(const or_multi_view *m, const float *P)
+{
+    int cnt = 0;
+    float first = 1.0f, num = 0.0f, den = 0.0f;
+    for (int i = 0; i < m->n; ++i) {
+        float Q[3];
+        to_submap(m, i, P, Q);
+        float w = trilinear_w(m->vols[i], Q[0], Q[1], Q[2]);
+        if (!(w > 0.0f)) continue;
+        float F = or_trilinear(m->vols[i], Q[0], Q[1], Q[2]);
+        if (cnt == 0) first = F;
+        num = num + w * F;
+        den = den + w;
+        ++cnt;
+    }
+    if (cnt == 0) return 1.0f;
+    if (cnt == 1) return first;
+    return num / den;
+}
+
+/* raycast of the combined field (Sec. 7.2: rendering the submaps together
+ * as a view), with the state machine, refinement and normals of or_raycast */
+void or_multi_raycast(or_volume **vols, const float *poses, int n, int W, int H, const float *intr, const float *V,
+                      const float *zmin, const float *zmax, float *points, float *normals)
+{
+    or_multi_view m;
+    m.vols = vols;
+    m.n = n > 64 ? 64 : n;
+    const float vs = vols[0]->voxel_size;
+    const float inv_vs = 1.0f / vs;
+    const float mu_v = vols[0]->mu * inv_vs;
+    for (int i = 0; i < m.n; ++i) {
+        const float *P = &poses[16 * i];
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c) m.R[i][3 * r + c] = P[4 * r + c];
+            m.s[i][r] = P[4 * r + 3] * inv_vs;
+        }
+    }
+    const float fx = intr[0], fy = intr[1], cx = intr[2], cy = intr[3];
+    float Ri[9], ti[3];
+    invert_pose(V, Ri, ti);
+    const float o[3] = {ti[0] * inv_vs, ti[1] * inv_vs, ti[2] * inv_vs};
+
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int p = 0; p < W * H; ++p) {
+        int x = p % W, y = p / W;
+        float *pt = &points[4 * (size_t)p];
+        float *nm = &normals[4 * (size_t)p];
+        pt[0] = pt[1] = pt[2] = pt[3] = 0.0f;
+        nm[0] = nm[1] = nm[2] = nm[3] = 0.0f;
+        if (!(zmin[p] <= zmax[p])) continue;
+        float a = ((float)x - cx) / fx;
+        float b = ((float)y - cy) / fy;
+        float nr = sqrtf((a * a + b * b) + 1.0f);
+        float rc[3] = {a / nr, b / nr, 1.0f / nr};
+        float dir[3];
+        for (int r = 0; r < 3; ++r)
+            dir[r] = (Ri[3 * r] * rc[0] + Ri[3 * r + 1] * rc[1]) + Ri[3 * r + 2] * rc[2];
+        float t = (zmin[p] * nr) * inv_vs;
+        float t_end = (zmax[p] * nr) * inv_vs;
+        int state = SEARCH_BLOCK_COARSE;
+        float F = 1.0f;
+        float P[3];
+        int steps = 0;
+        while (t < t_end && steps < OR_MAX_RAY_STEPS) {
+            ++steps;
+            P[0] = o[0] + t * dir[0];
+            P[1] = o[1] + t * dir[1];
+            P[2] = o[2] + t * dir[2];
+            int alloc = multi_allocated(&m, P);
+            if (state == SEARCH_BLOCK_COARSE) {
+                if (!alloc) {
+                    t += 8.0f;
+                } else {
+                    t -= 8.0f;
+                    state = SEARCH_BLOCK_FINE;
+                }
+            } else if (!alloc) {
+                state = SEARCH_BLOCK_FINE;
+                t += mu_v;
+            } else {
+                F = multi_F(&m, P);
+                if (state == SEARCH_BLOCK_FINE) {
+                    state = (F < 0.0f) ? WRONG_SIDE : SEARCH_SURFACE;
+                } else if (state == SEARCH_SURFACE) {
+                    if (F < 0.0f) {
+                        state = BEHIND_SURFACE;
+                        break;
+                    }
+                    float s = F * mu_v;
+                    t += (s > 1.0f) ? s : 1.0f;
+                } else {
+                    if (F >= 0.0f) {
+                        state = SEARCH_SURFACE;
+                    } else {
+                        float s = -F * mu_v;
+                        t += (s > 1.0f) ? s : 1.0f;
+                    }
+                }
+            }
+        }
+        if (state != BEHIND_SURFACE) continue;
+        t += F * mu_v;
+        P[0] = o[0] + t * dir[0];
+        P[1] = o[1] + t * dir[1];
+        P[2] = o[2] + t * dir[2];
+        F = multi_F(&m, P);
+        t += F * mu_v;
+        P[0] = o[0] + t * dir[0];
+        P[1] = o[1] + t * dir[1];
+        P[2] = o[2] + t * dir[2];
+        pt[0] = P[0] * vs;
+        pt[1] = P[1] * vs;
+        pt[2] = P[2] * vs;
+        pt[3] = 1.0f;
+        float q[3];
+        q[0] = P[0] + 1.0f; q[1] = P[1]; q[2] = P[2];
+        float fxp = multi_F(&m, q);
+        q[0] = P[0] - 1.0f;
+        float fxm = multi_F(&m, q);
+        q[0] = P[0]; q[1] = P[1] + 1.0f;
+        float fyp = multi_F(&m, q);
+        q[1] = P[1] - 1.0f;
+        float fym = multi_F(&m, q);
+        q[1] = P[1]; q[2] = P[2] + 1.0f;
+        float fzp = multi_F(&m, q);
+        q[2] = P[2] - 1.0f;
+        float fzm = multi_F(&m, q);
+        float gx = (fxp - fxm) * 0.5f, gy = (fyp - fym) * 0.5f, gz = (fzp - fzm) * 0.5f;
+        float gn = sqrtf((gx * gx + gy * gy) + gz * gz);
+        if (gn > 0.0f) {
+            nm[0] = gx / gn;
+            nm[1] = gy / gn;
+            nm[2] = gz / gn;
+            nm[3] = 1.0f;
+        }
+    }
+}

@@ -10,6 +10,7 @@ Seeds: numpy PCG64, seed = 1000 * config + index.
 from __future__ import annotations
 
 import dataclasses
+import functools
 import math
 
 import numpy as np
@@ -146,4 +147,110 @@ def c2_frame(k: int, seed_index: int = 0, noise: bool = True) -> np.ndarray:
     z = render_depth(scene, P, KINECT_INTR)
     if noise:
         z = kinect_noise(z, rng_for(2, 100000 + 1000 * seed_index + k))
+    return to_mm_u16(z)
+
+
+# ----------------------------------------------------------------------------
+# C3: 12x12x3 m layout of 3x3 rooms (4x4 m) with one door per shared wall
+# ----------------------------------------------------------------------------
+
+WALL = 0.1
+DOOR_W, DOOR_H = 1.0, 2.1
+
+
+@functools.lru_cache(maxsize=4)
+def c3_layout(seed_index: int = 0):
+    """(scene, doors) -- doors as {(room_a, room_b): (x, y)} door centres at
+    floor level.  Rooms are (i, j) with x in [4i, 4i+4], y in [4j, 4j+4]."""
+    rng = rng_for(3, seed_index)
+    boxes = []
+    doors = {}
+    h = WALL / 2
+    # walls between room columns (x = 4, 8) and room rows (y = 4, 8)
+    for axis in (0, 1):
+        for k in (1, 2):
+            c = 4.0 * k
+            for seg in range(3):
+                lo, hi = 4.0 * seg, 4.0 * seg + 4.0
+                d = rng.uniform(lo + 0.8, hi - 0.8)          # door centre along the wall
+                parts = [(lo, d - DOOR_W / 2, 0.0, 3.0), (d + DOOR_W / 2, hi, 0.0, 3.0),
+                         (d - DOOR_W / 2, d + DOOR_W / 2, DOOR_H, 3.0)]
+                for a, b, z0, z1 in parts:
+                    if b - a <= 1e-6:
+                        continue
+                    mid = ((a + b) / 2, (z0 + z1) / 2)
+                    half_along, half_z = (b - a) / 2, (z1 - z0) / 2
+                    if axis == 0:   # wall at x = c, spanning y
+                        boxes.append(((c, mid[0], mid[1]), (h, half_along, half_z), 0.0))
+                    else:           # wall at y = c, spanning x
+                        boxes.append(((mid[0], c, mid[1]), (half_along, h, half_z), 0.0))
+                if axis == 0:
+                    doors[((k - 1, seg), (k, seg))] = (c, d)
+                else:
+                    doors[((seg, k - 1), (seg, k))] = (d, c)
+    spheres = []
+    for _ in range(200):
+        ri, rj = rng.integers(0, 3, size=2)
+        size = rng.uniform(0.1, 0.6)
+        cx = rng.uniform(4 * ri + 0.5, 4 * ri + 3.5)
+        cy = rng.uniform(4 * rj + 0.5, 4 * rj + 3.5)
+        cz = rng.uniform(size / 2, 2.0)
+        if rng.uniform() < 0.5:
+            spheres.append(((cx, cy, cz), size / 2))
+        else:
+            boxes.append(((cx, cy, cz), (size / 2,) * 3, rng.uniform(0, math.pi / 2)))
+    scene = Scene(rooms=[((0.0, 0.0, 0.0), (12.0, 12.0, 3.0))], spheres=spheres, boxes=boxes)
+    return scene, doors
+
+
+def _catmull_rom(points, n):
+    P = np.asarray(points, np.float64)
+    P = np.vstack([P[0], P, P[-1]])
+    seg = np.linalg.norm(np.diff(P[1:-1], axis=0), axis=1)
+    cum = np.concatenate([[0.0], np.cumsum(seg)])
+    s = np.linspace(0.0, cum[-1], n)
+    out = np.empty((n, 3))
+    for k, sk in enumerate(s):
+        i = min(np.searchsorted(cum, sk, side="right") - 1, len(seg) - 1)
+        u = (sk - cum[i]) / max(seg[i], 1e-12)
+        p0, p1, p2, p3 = P[i], P[i + 1], P[i + 2], P[i + 3]
+        out[k] = 0.5 * ((2 * p1) + (-p0 + p2) * u + (2 * p0 - 5 * p1 + 4 * p2 - p3) * u * u +
+                        (-p0 + 3 * p1 - 3 * p2 + p3) * u ** 3)
+    return out
+
+
+@functools.lru_cache(maxsize=4)
+def c3_poses(n: int = 1500, seed_index: int = 0) -> list:
+    """A smoothed walk through the rooms in snake order, passing every shared
+    door on the way at 1.5 m height, facing forward (slightly down)."""
+    _, doors = c3_layout(seed_index)
+    order = [(0, 0), (1, 0), (2, 0), (2, 1), (1, 1), (0, 1), (0, 2), (1, 2), (2, 2)]
+    way = []
+    for a, b in zip(order[:-1], order[1:]):
+        way.append((4 * a[0] + 2.0, 4 * a[1] + 2.0))
+        key = (a, b) if (a, b) in doors else (b, a)
+        dx, dy = doors[key]
+        # approach and leave the door perpendicular to its wall
+        if a[0] != b[0]:
+            way += [(dx - 0.6, dy), (dx + 0.6, dy)] if b[0] > a[0] else [(dx + 0.6, dy), (dx - 0.6, dy)]
+        else:
+            way += [(dx, dy - 0.6), (dx, dy + 0.6)] if b[1] > a[1] else [(dx, dy + 0.6), (dx, dy - 0.6)]
+    way.append((4 * order[-1][0] + 2.0, 4 * order[-1][1] + 2.0))
+    pts = _catmull_rom([(x, y, 1.5) for x, y in way], n + 1)
+    poses = []
+    for k in range(n):
+        fwd = pts[k + 1] - pts[k]
+        fwd[2] = 0.0
+        fwd /= max(np.linalg.norm(fwd), 1e-9)
+        target = pts[k] + 1.5 * fwd + np.array([0.0, 0.0, -0.25])
+        poses.append(look_at(pts[k], target))
+    return poses
+
+
+def c3_frame(k: int, seed_index: int = 0, noise: bool = True, intr: Intrinsics = KINECT_INTR):
+    scene, _ = c3_layout(seed_index)
+    P = c3_poses(1500, seed_index)[k]
+    z = render_depth(scene, P, intr)
+    if noise:
+        z = kinect_noise(z, rng_for(3, 100000 + 1000 * seed_index + k))
     return to_mm_u16(z)
