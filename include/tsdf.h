@@ -53,6 +53,7 @@ extern "C" {
 #define TF_FLAG_EXCESS_EXHAUSTED 0x2u   /* the excess list ran out of slots (Sec. 3.2) */
 #define TF_FLAG_REQUEST_OVERFLOW 0x4u   /* more new blocks in one frame than n_blocks */
 #define TF_FLAG_TRANSFER_OVERFLOW 0x8u  /* swap candidates beyond the transfer buffer (Sec. 5, O1) */
+#define TF_FLAG_BIN_OVERFLOW 0x10u      /* batched raycast: block x tile entries beyond the bin capacity */
 
 typedef struct tf_ctx tf_ctx;    /* opaque, host-side */
 typedef void *tf_stream;         /* hipStream_t */
@@ -174,6 +175,13 @@ int tf_range_image(tf_ctx *ctx, const float pose_w2c[16], const tf_intrinsics *i
  * disabled. */
 int tf_swap_out(tf_ctx *ctx, tf_stream stream);
 
+/* Copies of host-store blocks (swapping only; synchronous host work): for
+ * each of n entries, 512 voxels in the in-block order lx + 8 ly + 64 lz and,
+ * in h_has (may be NULL), 1 if the store holds data for the entry (else the
+ * default voxel is written).  TF_E_INVAL without swapping. */
+int tf_export_host_voxels(tf_ctx *ctx, const int32_t *h_entries, uint32_t n, int16_t *h_sdf, uint8_t *h_w,
+                          uint8_t *h_has);
+
 /* Optional per-kernel timing: with `on` != 0 every later launch is bracketed
  * by a pair of HIP events recorded on its stream (a small host cost per
  * launch).  tf_profile_read synchronises on the outstanding events, returns
@@ -204,6 +212,119 @@ int tf_export_visible(tf_ctx *ctx, int32_t *h_list, uint32_t cap, uint32_t *h_co
  * voxel (32767, 0).  Enqueued only. */
 int tf_export_voxels(tf_ctx *ctx, const int32_t *d_entries, uint32_t n, int16_t *d_sdf,
                      uint8_t *d_w, tf_stream stream);
+
+/* ==========================================================================
+ * Rigid submaps, batched (Sec. 7.2)
+ *
+ * A batched map holds n_submaps independent volumes of identical parameters,
+ * each with a fixed rigid pose P_i (world -> submap, row-major 4x4).  A depth
+ * frame is fused into a caller-chosen subset of them: submap i sees the
+ * camera M_d P_i^-1 (composed in double, rounded once to float).  Views are
+ * raycast on the combined field of all submaps: at a world point X the
+ * trilinear SDFs F_i(P_i X) averaged with their trilinear weights W_i(P_i X)
+ * as weights, over the submaps with W_i > 0 (one such submap gives F_i
+ * unchanged, none gives 1); a point counts as allocated when any submap has
+ * a block at floor(P_i X).  The search range of a pixel is taken over the
+ * blocks of every submap.  Submaps never swap.
+ *
+ * Memory: device workspace tf_multi_workspace_bytes() and a pinned host
+ * parameter buffer of tf_multi_host_bytes() (hipHostMalloc'd), both owned by
+ * the caller.  Per call the library writes the frame's parameters into the
+ * pinned buffer (two alternating halves; it waits for the frame before last
+ * to finish with a half before overwriting it) and copies them to the device
+ * on the stream.
+ * ========================================================================== */
+typedef struct tf_multi tf_multi;   /* opaque, host-side */
+
+#define TF_MULTI_MAX_SUBMAPS 64
+#define TF_MULTI_MAX_SELECT 12       /* submaps one frame is fused into */
+#define TF_MULTI_MAX_VIEWS 8
+
+typedef struct {
+    tf_intrinsics intr;   /* width x height at most the map's view bound */
+    float pose_w2c[16];   /* world -> camera of the view */
+    float *d_points;      /* height x width x 4 device floats: world hit point, w = 1 on a hit, else all 0 */
+    float *d_normals;     /* height x width x 4: unit normal of the combined field, w = 1 where valid */
+} tf_view;
+
+/* launch shapes, chosen by tf_multi_autotune or set by the caller */
+typedef struct {
+    int32_t tile_w, tile_h;        /* raycast tile: 16x16, 32x8, 16x8 or 8x8 pixels, one workgroup each */
+    int32_t integrate_threads;     /* threads per integration workgroup: 64, 128, 256 or 512 */
+    int32_t integrate_groups;      /* integration workgroups per selected submap, 1..2048 */
+    int32_t bin_groups;            /* workgroups per view of the binning passes, 1..65535 */
+} tf_multi_config;
+
+typedef struct {
+    uint32_t flags;                     /* OR of every submap's flags and TF_FLAG_BIN_OVERFLOW */
+    uint32_t n_submaps;
+    uint64_t allocated_blocks;          /* sum over submaps */
+    uint64_t total_integrated_blocks;   /* sum over submaps: blocks visited by integrations */
+    uint64_t total_written_columns;     /* sum over submaps: 8-voxel columns written back */
+    uint64_t total_bin_entries;         /* (block, tile) pairs binned by all raycasts */
+    uint64_t total_rays_hit;            /* pixels with a hit over all raycasts and views */
+    uint64_t raycast_calls;
+} tf_multi_stats;
+
+/* Device workspace for n_submaps submaps of parameters p (p->max_width x
+ * p->max_height bounds the depth frames; swap_transfer_blocks must be 0),
+ * views up to view_w x view_h, and bin_capacity (block, tile) entries per
+ * raycast call over all its views.  0 if an argument is out of range. */
+size_t tf_multi_workspace_bytes(const tf_params *p, uint32_t n_submaps, uint32_t view_w, uint32_t view_h,
+                                uint32_t bin_capacity);
+/* Bytes of the pinned host parameter buffer. */
+size_t tf_multi_host_bytes(void);
+
+/* poses: n_submaps x 16 host floats (P_i).  Enqueues the initialisation of
+ * every submap on `stream`.  *out receives the handle.  TF_E_SPACE when
+ * bytes < tf_multi_workspace_bytes(), TF_E_INVAL for other bad arguments. */
+int tf_multi_create(const tf_params *p, uint32_t n_submaps, const float *poses, uint32_t view_w, uint32_t view_h,
+                    uint32_t bin_capacity, void *d_workspace, size_t bytes, void *h_pinned, size_t h_bytes,
+                    tf_stream stream, tf_multi **out);
+int tf_multi_destroy(tf_multi *m);   /* frees host state only; waits for nothing */
+
+/* Borrowed handle of submap i (valid until tf_multi_destroy): every
+ * single-volume call applies to it (exports, statistics, its own frames in
+ * its own coordinates). */
+int tf_multi_submap(tf_multi *m, uint32_t i, tf_ctx **out);
+
+int tf_multi_set_config(tf_multi *m, const tf_multi_config *c);   /* TF_E_INVAL for unsupported shapes */
+int tf_multi_get_config(const tf_multi *m, tf_multi_config *c);
+
+/* Fuse one frame (allocation, visible lists and integration of Sec. 4.2-4.3)
+ * into the submaps sel[0..n_sel-1] (distinct, 1 <= n_sel <= 12), each with
+ * camera pose_w2c P_i^-1.  The frame is at most p->max_width x p->max_height. */
+int tf_multi_integrate(tf_multi *m, const void *d_depth, int depth_format, const tf_intrinsics *intr,
+                       const float pose_w2c[16], const uint32_t *sel, uint32_t n_sel, tf_stream stream);
+
+/* Raycast the combined field into views[0..n_views-1] (1 <= n_views <= 8). */
+int tf_multi_raycast(tf_multi *m, const tf_view *views, uint32_t n_views, tf_stream stream);
+
+/* tf_multi_integrate followed by tf_multi_raycast.  With use_graph != 0 the
+ * launches are captured once into a HIP graph per (frame size, view sizes,
+ * launch shapes) and replayed: a replay only rewrites the pinned parameters. */
+int tf_multi_frame(tf_multi *m, const void *d_depth, int depth_format, const tf_intrinsics *intr,
+                   const float pose_w2c[16], const uint32_t *sel, uint32_t n_sel, const tf_view *views,
+                   uint32_t n_views, int use_graph, tf_stream stream);
+
+/* Per-pixel search range of one view over every submap's blocks: d_zmin,
+ * d_zmax (height x width device floats, camera z; +inf / -inf where no block
+ * projects). */
+int tf_multi_range_image(tf_multi *m, const tf_view *view, float *d_zmin, float *d_zmax, tf_stream stream);
+
+/* Time every supported launch shape on this frame and these views (reps
+ * timed repetitions each) and keep the fastest.  Integration shapes are timed
+ * with a dry pass that computes every update and stores none; the frame's
+ * allocation runs once, as the frame's own integration would run it, so the
+ * map changes only by the blocks this frame allocates.  The views' outputs
+ * are overwritten.  Synchronising.  best / best_ms (frame ms of the chosen
+ * shapes) may be NULL. */
+int tf_multi_autotune(tf_multi *m, const void *d_depth, int depth_format, const tf_intrinsics *intr,
+                      const float pose_w2c[16], const uint32_t *sel, uint32_t n_sel, const tf_view *views,
+                      uint32_t n_views, int reps, tf_multi_config *best, float *best_ms, tf_stream stream);
+
+/* Synchronising. */
+int tf_multi_get_stats(tf_multi *m, tf_multi_stats *out, tf_stream stream);
 
 /* Human-readable name of a status code. */
 const char *tf_status_string(int status);

@@ -23,6 +23,7 @@ TF_FLAG_BLOCKS_EXHAUSTED = 0x1
 TF_FLAG_EXCESS_EXHAUSTED = 0x2
 TF_FLAG_REQUEST_OVERFLOW = 0x4
 TF_FLAG_TRANSFER_OVERFLOW = 0x8
+TF_FLAG_BIN_OVERFLOW = 0x10
 
 # every symbol include/tsdf.h declares
 EXPORTS = (
@@ -30,6 +31,11 @@ EXPORTS = (
     "tf_destroy", "tf_reset", "tf_alloc_and_visible", "tf_integrate", "tf_raycast",
     "tf_range_image", "tf_swap_out", "tf_get_stats", "tf_export_entries", "tf_export_visible",
     "tf_export_voxels", "tf_status_string", "tf_profile_enable", "tf_profile_read",
+    "tf_export_host_voxels",
+    "tf_multi_workspace_bytes", "tf_multi_host_bytes", "tf_multi_create", "tf_multi_destroy",
+    "tf_multi_submap", "tf_multi_set_config", "tf_multi_get_config", "tf_multi_integrate",
+    "tf_multi_raycast", "tf_multi_frame", "tf_multi_range_image", "tf_multi_autotune",
+    "tf_multi_get_stats",
 )
 
 
@@ -66,6 +72,28 @@ class tf_profile(ctypes.Structure):
     def as_dict(self):
         return {k: {"launches": int(self.launches[i]), "ms": float(self.ms[i])}
                 for i, k in enumerate(KERNEL_CLASSES)}
+
+
+class tf_view(ctypes.Structure):
+    _fields_ = [("intr", tf_intrinsics), ("pose_w2c", ctypes.c_float * 16),
+                ("d_points", ctypes.c_void_p), ("d_normals", ctypes.c_void_p)]
+
+
+class tf_multi_config(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "tile_w", "tile_h", "integrate_threads", "integrate_groups", "bin_groups")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class tf_multi_stats(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("n_submaps", ctypes.c_uint32)] + [(n, ctypes.c_uint64) for n in (
+        "allocated_blocks", "total_integrated_blocks", "total_written_columns", "total_bin_entries",
+        "total_rays_hit", "raycast_calls")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
 
 
 class TsdfError(RuntimeError):
@@ -105,6 +133,28 @@ def lib():
             "tf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
             "tf_profile_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
             "tf_profile_read": (ctypes.c_int, [_VP, P(tf_profile), ctypes.c_int]),
+            "tf_export_host_voxels": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP]),
+            "tf_multi_workspace_bytes": (ctypes.c_size_t, [P(tf_params), ctypes.c_uint32, ctypes.c_uint32,
+                                                           ctypes.c_uint32, ctypes.c_uint32]),
+            "tf_multi_host_bytes": (ctypes.c_size_t, []),
+            "tf_multi_create": (ctypes.c_int, [P(tf_params), ctypes.c_uint32, _F16, ctypes.c_uint32,
+                                               ctypes.c_uint32, ctypes.c_uint32, _VP, ctypes.c_size_t, _VP,
+                                               ctypes.c_size_t, _VP, P(_VP)]),
+            "tf_multi_destroy": (ctypes.c_int, [_VP]),
+            "tf_multi_submap": (ctypes.c_int, [_VP, ctypes.c_uint32, P(_VP)]),
+            "tf_multi_set_config": (ctypes.c_int, [_VP, P(tf_multi_config)]),
+            "tf_multi_get_config": (ctypes.c_int, [_VP, P(tf_multi_config)]),
+            "tf_multi_integrate": (ctypes.c_int, [_VP, _VP, ctypes.c_int, P(tf_intrinsics), _F16,
+                                                  P(ctypes.c_uint32), ctypes.c_uint32, _VP]),
+            "tf_multi_raycast": (ctypes.c_int, [_VP, P(tf_view), ctypes.c_uint32, _VP]),
+            "tf_multi_frame": (ctypes.c_int, [_VP, _VP, ctypes.c_int, P(tf_intrinsics), _F16,
+                                              P(ctypes.c_uint32), ctypes.c_uint32, P(tf_view), ctypes.c_uint32,
+                                              ctypes.c_int, _VP]),
+            "tf_multi_range_image": (ctypes.c_int, [_VP, P(tf_view), _VP, _VP, _VP]),
+            "tf_multi_autotune": (ctypes.c_int, [_VP, _VP, ctypes.c_int, P(tf_intrinsics), _F16,
+                                                 P(ctypes.c_uint32), ctypes.c_uint32, P(tf_view), ctypes.c_uint32,
+                                                 ctypes.c_int, P(tf_multi_config), P(ctypes.c_float), _VP]),
+            "tf_multi_get_stats": (ctypes.c_int, [_VP, P(tf_multi_stats), _VP]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -213,7 +263,23 @@ class Volume:
         self.ctx = tf_create(self.params, self.workspace.data_ptr(), nbytes, hs, ht, stream)
         self.n_entries = self.params.n_buckets + self.params.n_excess
 
+    @classmethod
+    def borrowed(cls, ctx, params, owner):
+        """A view of a context the library owns (a submap of a MultiMap)."""
+        v = cls.__new__(cls)
+        v.params = params
+        v.workspace = None
+        v.h_store = v.h_transfer = None
+        v.ctx = ctx
+        v.n_entries = params.n_buckets + params.n_excess
+        v._owner = owner
+        v._borrowed = True
+        return v
+
     def close(self):
+        if getattr(self, "_borrowed", False):
+            self.ctx = None
+            return
         if getattr(self, "ctx", None):
             lib().tf_destroy(self.ctx)
             self.ctx = None
@@ -301,6 +367,16 @@ class Volume:
                                          _stream_ptr(stream)), "tf_export_voxels")
         return sdf.cpu().numpy(), w.cpu().numpy()
 
+    def host_voxels(self, entry_ids):
+        """(sdf, w, has) of host-store blocks (swapping volumes only)"""
+        ids = np.ascontiguousarray(entry_ids, np.int32)
+        sdf = np.empty((ids.size, 512), np.int16)
+        w = np.empty((ids.size, 512), np.uint8)
+        has = np.empty(ids.size, np.uint8)
+        check(lib().tf_export_host_voxels(self.ctx, ids.ctypes.data_as(_VP), ids.size, sdf.ctypes.data_as(_VP),
+                                          w.ctypes.data_as(_VP), has.ctypes.data_as(_VP)), "tf_export_host_voxels")
+        return sdf, w, has.astype(bool)
+
     def allocated_positions(self) -> np.ndarray:
         pos, _, ptr = self.entries()
         p = pos[ptr >= 0].astype(np.int32)
@@ -314,3 +390,132 @@ class Volume:
         ids = ids[order]
         sdf, w = self.block_voxels(ids)
         return p[order], sdf, w
+
+
+# ---- rigid submaps, batched ------------------------------------------------------
+
+def make_view(intr, pose, points, normals) -> tf_view:
+    v = tf_view()
+    v.intr = make_intrinsics(intr)
+    M = np.ascontiguousarray(np.asarray(pose, np.float32).reshape(16))
+    for i in range(16):
+        v.pose_w2c[i] = float(M[i])
+    v.d_points = points.data_ptr()
+    v.d_normals = normals.data_ptr()
+    return v
+
+
+def _sel_arg(sel):
+    a = (ctypes.c_uint32 * len(sel))(*[int(x) for x in sel])
+    return a, len(sel)
+
+
+class MultiMap:
+    """Batched rigid submaps (Sec. 7.2) on the current HIP device: n volumes of
+    parameters vp with poses P_i (world -> submap, n x 4 x 4)."""
+
+    def __init__(self, vp, poses, frame_w, frame_h, view_w, view_h, bin_capacity, stream=None):
+        import torch
+        self.params = make_params(vp, frame_w, frame_h, 0)
+        self.poses = np.ascontiguousarray(np.asarray(poses, np.float32).reshape(-1, 16))
+        self.n = self.poses.shape[0]
+        nbytes = int(lib().tf_multi_workspace_bytes(ctypes.byref(self.params), self.n, view_w, view_h,
+                                                    bin_capacity))
+        if nbytes == 0:
+            raise TsdfError("invalid batched-map parameters")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        hb = int(lib().tf_multi_host_bytes())
+        self.h_params = torch.empty(hb, dtype=torch.uint8, pin_memory=True)
+        h = _VP()
+        check(lib().tf_multi_create(ctypes.byref(self.params), self.n, self.poses.ctypes.data_as(_F16), view_w,
+                                    view_h, bin_capacity, ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                    ctypes.c_void_p(self.h_params.data_ptr()), hb, _stream_ptr(stream),
+                                    ctypes.byref(h)), "tf_multi_create")
+        self.h = h
+        self._subs = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tf_multi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submap(self, i) -> Volume:
+        if i not in self._subs:
+            c = _VP()
+            check(lib().tf_multi_submap(self.h, i, ctypes.byref(c)), "tf_multi_submap")
+            self._subs[i] = Volume.borrowed(c, self.params, self)
+        return self._subs[i]
+
+    def set_config(self, **kw):
+        c = self.get_config()
+        for k, v in kw.items():
+            setattr(c, k, int(v))
+        check(lib().tf_multi_set_config(self.h, ctypes.byref(c)), "tf_multi_set_config")
+
+    def get_config(self) -> tf_multi_config:
+        c = tf_multi_config()
+        check(lib().tf_multi_get_config(self.h, ctypes.byref(c)), "tf_multi_get_config")
+        return c
+
+    def integrate(self, depth, intr, pose, sel, stream=None):
+        fmt = TF_DEPTH_U16_MM if depth.dtype.itemsize == 2 else TF_DEPTH_F32_M
+        _, Mp = _pose_arg(pose)
+        K = make_intrinsics(intr)
+        a, n = _sel_arg(sel)
+        check(lib().tf_multi_integrate(self.h, ctypes.c_void_p(depth.data_ptr()), fmt, ctypes.byref(K), Mp, a, n,
+                                       _stream_ptr(stream)), "tf_multi_integrate")
+
+    @staticmethod
+    def _views(views):
+        arr = (tf_view * len(views))(*[make_view(*v) for v in views])
+        return arr, len(views)
+
+    def raycast(self, views, stream=None):
+        """views: list of (intr, pose, points, normals)"""
+        arr, n = self._views(views)
+        check(lib().tf_multi_raycast(self.h, arr, n, _stream_ptr(stream)), "tf_multi_raycast")
+
+    def frame(self, depth, intr, pose, sel, views, use_graph=True, stream=None):
+        fmt = TF_DEPTH_U16_MM if depth.dtype.itemsize == 2 else TF_DEPTH_F32_M
+        _, Mp = _pose_arg(pose)
+        K = make_intrinsics(intr)
+        a, ns = _sel_arg(sel)
+        arr, nv = self._views(views)
+        check(lib().tf_multi_frame(self.h, ctypes.c_void_p(depth.data_ptr()), fmt, ctypes.byref(K), Mp, a, ns,
+                                   arr, nv, 1 if use_graph else 0, _stream_ptr(stream)), "tf_multi_frame")
+
+    def range_image(self, intr, pose, stream=None):
+        import torch
+        K = make_intrinsics(intr)
+        zmin = torch.empty((K.height, K.width), dtype=torch.float32, device="cuda")
+        zmax = torch.empty((K.height, K.width), dtype=torch.float32, device="cuda")
+        dummy = torch.empty(4, dtype=torch.float32, device="cuda")
+        v = make_view(intr, pose, dummy, dummy)
+        check(lib().tf_multi_range_image(self.h, ctypes.byref(v), ctypes.c_void_p(zmin.data_ptr()),
+                                         ctypes.c_void_p(zmax.data_ptr()), _stream_ptr(stream)),
+              "tf_multi_range_image")
+        return zmin, zmax
+
+    def autotune(self, depth, intr, pose, sel, views, reps=3, stream=None):
+        fmt = TF_DEPTH_U16_MM if depth.dtype.itemsize == 2 else TF_DEPTH_F32_M
+        _, Mp = _pose_arg(pose)
+        K = make_intrinsics(intr)
+        a, ns = _sel_arg(sel)
+        arr, nv = self._views(views)
+        best = tf_multi_config()
+        ms = ctypes.c_float(0.0)
+        check(lib().tf_multi_autotune(self.h, ctypes.c_void_p(depth.data_ptr()), fmt, ctypes.byref(K), Mp, a, ns,
+                                      arr, nv, reps, ctypes.byref(best), ctypes.byref(ms), _stream_ptr(stream)),
+              "tf_multi_autotune")
+        return best.as_dict(), float(ms.value)
+
+    def stats(self, stream=None) -> dict:
+        st = tf_multi_stats()
+        check(lib().tf_multi_get_stats(self.h, ctypes.byref(st), _stream_ptr(stream)), "tf_multi_get_stats")
+        return st.as_dict()

@@ -3,39 +3,39 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <vector>
 
 #include "tsdf.h"
+#include "tsdf_ctx.h"
 #include "tsdf_internal.h"
 
 using namespace tsdf;
 
-// ring of HIP event pairs per kernel class; a slot is harvested before reuse
-struct Profiler {
-    static const int R = 128;
-    bool on = false;
-    bool created = false;
-    hipEvent_t ev[TF_K_COUNT][R][2];
-    bool pending[TF_K_COUNT][R] = {};
-    int next[TF_K_COUNT] = {};
-    uint64_t launches[TF_K_COUNT] = {};
-    double ms[TF_K_COUNT] = {};
-};
+namespace tsdf {
 
-struct tf_ctx {
-    tf_params p;
-    Profiler prof;
-    Layout L;
-    Vol v;
-    uint8_t *ws;
-    void *h_store;
-    void *h_transfer;
-    bool have_alloc;
-    tf_intrinsics alloc_intr;
-    float alloc_pose[16];
-    const void *alloc_depth;
-    int alloc_fmt;
-};
+// camera constants of a world->camera matrix M (row-major 4x4) and intrinsics
+void make_cam(const float *M, const tf_intrinsics *K, Cam &c)
+{
+    for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < 4; ++j) c.M[4 * r + j] = M[4 * r + j];
+    // inverse of the rigid transform: [R^T | -R^T t], -R^T t in double
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) c.Ri[3 * i + j] = M[4 * j + i];
+    for (int i = 0; i < 3; ++i) {
+        double s = ((double)M[i] * (double)M[3] + (double)M[4 + i] * (double)M[7]) + (double)M[8 + i] * (double)M[11];
+        c.ti[i] = (float)(-s);
+    }
+    c.fx = K->fx;
+    c.fy = K->fy;
+    c.cx = K->cx;
+    c.cy = K->cy;
+    c.W = K->width;
+    c.H = K->height;
+}
+
+}  // namespace tsdf
 
 namespace {
 
@@ -83,7 +83,7 @@ Layout make_layout(const tf_params *p)
     L.ret = take((size_t)L.max_req * 4);
     L.depth = take((size_t)p->max_width * p->max_height * 4);
     L.recs = take((size_t)p->n_blocks * sizeof(Rec));
-    L.bins = take((size_t)L.max_tiles * kBinCap * 4);
+    L.bins = take((size_t)L.max_tiles * kBinCap * sizeof(Rec));
     L.bin_count = take((size_t)L.max_tiles * 4);
     L.acc_cols = take((size_t)kIntegrateGrid * 8);
     L.acc_hits = take((size_t)L.max_tiles * 8);
@@ -92,29 +92,11 @@ Layout make_layout(const tf_params *p)
         L.host_has = take(n_vis);
         L.xfer_idx = take((size_t)p->swap_transfer_blocks * 4);
         L.xfer_vox = take((size_t)p->swap_transfer_blocks * kBlockBytes);
+        L.swap_chunks = take(((n_entries + kSwapChunk - 1) / kSwapChunk) * 4);
     }
     L.voxels = take((size_t)p->n_blocks * kBlockBytes);
     L.total = o;
     return L;
-}
-
-void make_cam(const float *M, const tf_intrinsics *K, Cam &c)
-{
-    for (int r = 0; r < 3; ++r)
-        for (int j = 0; j < 4; ++j) c.M[4 * r + j] = M[4 * r + j];
-    // inverse of the rigid transform: [R^T | -R^T t], -R^T t in double
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) c.Ri[3 * i + j] = M[4 * j + i];
-    for (int i = 0; i < 3; ++i) {
-        double s = ((double)M[i] * (double)M[3] + (double)M[4 + i] * (double)M[7]) + (double)M[8 + i] * (double)M[11];
-        c.ti[i] = (float)(-s);
-    }
-    c.fx = K->fx;
-    c.fy = K->fy;
-    c.cx = K->cx;
-    c.cy = K->cy;
-    c.W = K->width;
-    c.H = K->height;
 }
 
 bool intr_ok(const tf_ctx *ctx, const tf_intrinsics *K)
@@ -175,6 +157,65 @@ struct Timed {
     }
 };
 
+// secondary integration on the host (the same per-voxel rule as k_swap_merge):
+// copy a (the store) becomes the weighted average of a and b
+void merge_block_host(uint8_t *a, const uint8_t *b, int max_w)
+{
+    int16_t *sa = (int16_t *)a;
+    const int16_t *sb = (const int16_t *)b;
+    for (int j = 0; j < kBlockVox; ++j) {
+        int wa = a[1024 + j], wb = b[1024 + j];
+        if (wb == 0) continue;
+        if (wa == 0) {
+            sa[j] = sb[j];
+            a[1024 + j] = b[1024 + j];
+            continue;
+        }
+        const float fa = (float)sa[j] * (1.0f / 32767.0f);
+        const float fb = (float)sb[j] * (1.0f / 32767.0f);
+        const float avg = ((float)wa * fa + (float)wb * fb) / (float)(wa + wb);
+        int w = wa + wb;
+        if (w > max_w) w = max_w;
+        sa[j] = (int16_t)(avg * 32767.0f);
+        a[1024 + j] = (uint8_t)w;
+    }
+}
+
+// swap-in after the visible list (Sec. 5): the device lists the visible
+// entries whose host store holds data; the host takes the lowest entry
+// indices up to the transfer capacity, gathers their blocks into the pinned
+// transfer buffer and sends it; one kernel fuses them into the device blocks.
+hipError_t swap_in(tf_ctx *ctx, hipStream_t s)
+{
+    Vol &v = ctx->v;
+    hipError_t e = launch_swap_candidates(v, s);
+    Ctrl c;
+    if (e == hipSuccess) e = hipMemcpyAsync(&c, v.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess || c.n_swap_cand == 0) return e;
+    ctx->cand.resize(c.n_swap_cand);
+    e = hipMemcpyAsync(ctx->cand.data(), v.ret, (size_t)c.n_swap_cand * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    std::sort(ctx->cand.begin(), ctx->cand.end());
+    const uint32_t T = ctx->p.swap_transfer_blocks;
+    const uint32_t m = c.n_swap_cand < T ? c.n_swap_cand : T;
+    if (c.n_swap_cand > T) ctx->host_flags |= TF_FLAG_TRANSFER_OVERFLOW;
+    int32_t *hidx = (int32_t *)ctx->h_transfer;
+    uint8_t *hvox = (uint8_t *)ctx->h_transfer + (size_t)T * 4;
+    const uint8_t *store = (const uint8_t *)ctx->h_store;
+    for (uint32_t k = 0; k < m; ++k) {
+        const int32_t idx = ctx->cand[k];
+        hidx[k] = idx;
+        memcpy(hvox + (size_t)k * kBlockBytes, store + (size_t)idx * kBlockBytes, kBlockBytes);
+        ctx->host_has[idx] = 0;
+    }
+    e = hipMemcpyAsync(v.xfer_idx, hidx, (size_t)m * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(v.xfer_vox, hvox, (size_t)m * kBlockBytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_swap_merge(v, m, s);
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -215,6 +256,8 @@ int tf_create(const tf_params *p, void *d_workspace, size_t bytes, void *h_store
     ctx->h_store = h_store;
     ctx->h_transfer = h_transfer;
     ctx->have_alloc = false;
+    ctx->host_flags = 0;
+    if (p->swap_transfer_blocks) ctx->host_has.assign((size_t)p->n_buckets + p->n_excess, 0);
     Vol &v = ctx->v;
     uint8_t *b = ctx->ws;
     v.entries = (DEntry *)(b + L.entries);
@@ -228,7 +271,7 @@ int tf_create(const tf_params *p, void *d_workspace, size_t bytes, void *h_store
     v.ret = (int32_t *)(b + L.ret);
     v.depth = (float *)(b + L.depth);
     v.recs = (Rec *)(b + L.recs);
-    v.bins = (int32_t *)(b + L.bins);
+    v.bins = (Rec *)(b + L.bins);
     v.bin_count = (int32_t *)(b + L.bin_count);
     v.ctrl = (Ctrl *)(b + L.ctrl);
     v.acc_cols = (unsigned long long *)(b + L.acc_cols);
@@ -237,6 +280,8 @@ int tf_create(const tf_params *p, void *d_workspace, size_t bytes, void *h_store
     v.host_has = p->swap_transfer_blocks ? b + L.host_has : nullptr;
     v.xfer_idx = p->swap_transfer_blocks ? (int32_t *)(b + L.xfer_idx) : nullptr;
     v.xfer_vox = p->swap_transfer_blocks ? b + L.xfer_vox : nullptr;
+    v.swap_chunks = p->swap_transfer_blocks ? (uint32_t *)(b + L.swap_chunks) : nullptr;
+    v.alist = nullptr;
     v.n_buckets = p->n_buckets;
     v.n_excess = p->n_excess;
     v.n_entries = p->n_buckets + p->n_excess;
@@ -314,6 +359,8 @@ int tf_reset(tf_ctx *ctx, tf_stream stream)
     if (e == hipSuccess) e = launch_clear_bins(ctx->v.bin_count, ctx->L.max_tiles, s);
     if (e == hipSuccess) e = launch_clear_bins((int32_t *)ctx->v.acc_hits, 2 * ctx->L.max_tiles, s);
     ctx->have_alloc = false;
+    ctx->host_flags = 0;
+    std::fill(ctx->host_has.begin(), ctx->host_has.end(), (uint8_t)0);
     return hip_status(e);
 }
 
@@ -337,6 +384,10 @@ int tf_alloc_and_visible(tf_ctx *ctx, const void *d_depth, int depth_format, con
     if (e == hipSuccess) {
         Timed t(ctx, TF_K_VISIBLE, s);
         e = launch_visible(ctx->v, s);
+    }
+    if (e == hipSuccess && ctx->p.swap_transfer_blocks) {
+        Timed t(ctx, TF_K_SWAP, s);
+        e = swap_in(ctx, s);
     }
     if (e != hipSuccess) return TF_E_HIP;
     ctx->have_alloc = true;
@@ -408,8 +459,61 @@ int tf_swap_out(tf_ctx *ctx, tf_stream stream)
 {
     if (!ctx) return TF_E_INVAL;
     if (!ctx->p.swap_transfer_blocks) return TF_E_INVAL;
-    (void)stream;
-    return TF_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    Vol &v = ctx->v;
+    Timed t(ctx, TF_K_SWAP, s);
+    hipError_t e = launch_swap_select(v, s);
+    Ctrl c;
+    if (e == hipSuccess) e = hipMemcpyAsync(&c, v.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return TF_E_HIP;
+    const uint32_t T = ctx->p.swap_transfer_blocks;
+    const uint32_t m = c.n_swap_cand < T ? c.n_swap_cand : T;
+    int32_t *hidx = (int32_t *)ctx->h_transfer;
+    uint8_t *hvox = (uint8_t *)ctx->h_transfer + (size_t)T * 4;
+    if (m) {
+        e = launch_swap_gather(v, m, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(hidx, v.xfer_idx, (size_t)m * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(hvox, v.xfer_vox, (size_t)m * kBlockBytes, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return TF_E_HIP;
+        uint8_t *store = (uint8_t *)ctx->h_store;
+        for (uint32_t k = 0; k < m; ++k) {
+            const int32_t idx = hidx[k];
+            uint8_t *dst = store + (size_t)idx * kBlockBytes;
+            // host data that never made it back in is fused, not overwritten
+            if (ctx->host_has[idx])
+                merge_block_host(dst, hvox + (size_t)k * kBlockBytes, ctx->p.max_w);
+            else
+                memcpy(dst, hvox + (size_t)k * kBlockBytes, kBlockBytes);
+            ctx->host_has[idx] = 1;
+        }
+    }
+    e = launch_swap_release(v, m, s);
+    return hip_status(e);
+}
+
+int tf_export_host_voxels(tf_ctx *ctx, const int32_t *h_entries, uint32_t n, int16_t *h_sdf, uint8_t *h_w,
+                          uint8_t *h_has)
+{
+    if (!ctx || (n && (!h_entries || !h_sdf || !h_w))) return TF_E_INVAL;
+    if (!ctx->p.swap_transfer_blocks) return TF_E_INVAL;
+    const size_t n_entries = ctx->host_has.size();
+    const uint8_t *store = (const uint8_t *)ctx->h_store;
+    for (uint32_t k = 0; k < n; ++k) {
+        const int32_t e = h_entries[k];
+        const bool has = e >= 0 && (size_t)e < n_entries && ctx->host_has[e];
+        if (h_has) h_has[k] = has ? 1 : 0;
+        for (int lz = 0; lz < 8; ++lz)
+            for (int ly = 0; ly < 8; ++ly)
+                for (int lx = 0; lx < 8; ++lx) {
+                    const int j = lz + 8 * ly + 64 * lx;            // store (device) order
+                    const size_t o = (size_t)k * kBlockVox + lx + 8 * ly + 64 * lz;
+                    h_sdf[o] = has ? ((const int16_t *)(store + (size_t)e * kBlockBytes))[j] : (int16_t)32767;
+                    h_w[o] = has ? store[(size_t)e * kBlockBytes + 1024 + j] : (uint8_t)0;
+                }
+    }
+    return TF_OK;
 }
 
 int tf_get_stats(tf_ctx *ctx, tf_stats *h_out, tf_stream stream)
@@ -420,7 +524,7 @@ int tf_get_stats(tf_ctx *ctx, tf_stats *h_out, tf_stream stream)
     hipError_t e = hipMemcpyAsync(&c, ctx->v.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return TF_E_HIP;
-    h_out->flags = c.flags;
+    h_out->flags = c.flags | ctx->host_flags;
     h_out->n_allocated = ctx->p.n_blocks - (uint32_t)c.free_blocks;
     h_out->n_visible = c.n_vis;
     h_out->n_new = c.n_new;

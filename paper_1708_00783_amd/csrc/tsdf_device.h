@@ -1,0 +1,642 @@
+// tsdf_device.h -- device helpers and kernel bodies of libtsdf shared by the
+// single-volume launches (tsdf_kernels.hip) and the batched-submap launches
+// (tsdf_multi.hip).  Internal to the library.
+//
+// Compiled with -ffp-contract=off and correctly rounded fp32 division and
+// square root: every float expression below is evaluated as written, one IEEE
+// operation at a time.
+#pragma once
+
+#include "tsdf_internal.h"
+#include "tsdf.h"
+
+namespace tsdf {
+
+namespace {
+
+constexpr int kWave = 64;
+
+// tuning knobs of the raycast (compile-time)
+#ifndef TSDF_RAY_XCD_BANDS
+#define TSDF_RAY_XCD_BANDS 1    // give each XCD a contiguous band of tiles
+#endif
+#ifndef TSDF_RAY_BITMAP
+#define TSDF_RAY_BITMAP 1       // consult the bucket-occupancy bitmap before an entry
+#endif
+
+__device__ __forceinline__ uint32_t hash_index(int x, int y, int z, uint32_t mask)
+{
+    // Sec. 3.2 hashIndex
+    return (((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349669u) ^ ((uint32_t)z * 83492791u)) & mask;
+}
+
+__device__ __forceinline__ bool in_short_range(int a) { return a >= -32768 && a <= 32767; }
+
+__device__ __forceinline__ unsigned long long pack_key(int x, int y, int z)
+{
+    return (1ull << 48) | ((unsigned long long)(uint16_t)x << 32) |
+           ((unsigned long long)(uint16_t)y << 16) | (unsigned long long)(uint16_t)z;
+}
+
+__device__ __forceinline__ void unpack_key(unsigned long long k, int &x, int &y, int &z)
+{
+    x = (int16_t)(uint16_t)(k >> 32);
+    y = (int16_t)(uint16_t)(k >> 16);
+    z = (int16_t)(uint16_t)k;
+}
+
+__device__ __forceinline__ uint32_t mix_key(unsigned long long k)
+{
+    k ^= k >> 30;
+    k *= 0xbf58476d1ce4e5b9ull;
+    k ^= k >> 27;
+    k *= 0x94d049bb133111ebull;
+    k ^= k >> 31;
+    return (uint32_t)k;
+}
+
+// loads through global-address-space pointers (the Vol pointers arrive
+// inside a by-value struct, so the compiler cannot infer their space)
+template <typename T>
+__device__ __forceinline__ T gload(const T *p)
+{
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int4 load_entry(const DEntry *e, uint32_t i)
+{
+    const v4i w = gload(reinterpret_cast<const v4i *>(e + i));
+    return make_int4(w.x, w.y, w.z, w.w);
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t rank_in(unsigned long long m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Retrieval (Sec. 3.3): bucket, then the chain of `offset` links.  Matches an
+// entry whose position equals the key and whose ptr >= min_ptr.  Returns the
+// entry index (and its ptr) or -1.
+__device__ __forceinline__ int find_entry_in(const DEntry *entries, uint32_t n_buckets, uint32_t n_excess, int bx,
+                                             int by, int bz, int min_ptr, int *ptr_out)
+{
+    if (!in_short_range(bx) || !in_short_range(by) || !in_short_range(bz)) return -1;
+    uint32_t i = hash_index(bx, by, bz, n_buckets - 1u);
+    const uint32_t kxy = (uint32_t)(uint16_t)bx | ((uint32_t)(uint16_t)by << 16);
+    for (uint32_t it = 0; it <= n_excess; ++it) {
+        int4 w = load_entry(entries, i);
+        if ((uint32_t)w.x == kxy && (int16_t)(w.y & 0xffff) == (int16_t)bz && w.w >= min_ptr) {
+            *ptr_out = w.w;
+            return (int)i;
+        }
+        if (w.z < 1 || (uint32_t)(w.z - 1) >= n_excess) return -1;
+        i = n_buckets + (uint32_t)(w.z - 1);
+    }
+    return -1;
+}
+
+__device__ __forceinline__ int find_entry(const Vol &v, int bx, int by, int bz, int min_ptr, int *ptr_out)
+{
+    return find_entry_in(v.entries, v.n_buckets, v.n_excess, bx, by, bz, min_ptr, ptr_out);
+}
+
+__device__ __forceinline__ void cam_transform(const Cam &c, float X, float Y, float Z, float &x, float &y, float &z)
+{
+    x = ((c.M[0] * X + c.M[1] * Y) + c.M[2] * Z) + c.M[3];
+    y = ((c.M[4] * X + c.M[5] * Y) + c.M[6] * Z) + c.M[7];
+    z = ((c.M[8] * X + c.M[9] * Y) + c.M[10] * Z) + c.M[11];
+}
+
+// Pop up to one element per requesting lane from a stack whose height is
+// *head (Sec. 4.2 "atomic subtraction on a stack of free voxel block
+// indices"), with one atomic per wave; the height never goes below zero.
+__device__ __forceinline__ int32_t wave_pop(int32_t *head, const int32_t *stack, bool want)
+{
+    unsigned long long m = __ballot(want);
+    if (m == 0) return -1;
+    const int cnt = __popcll(m);
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0, take = 0;
+    if ((int)lane_id() == leader) {
+        int cur = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (;;) {
+            take = cur < cnt ? cur : cnt;
+            if (take <= 0) {
+                take = 0;
+                break;
+            }
+            int prev = atomicCAS(head, cur, cur - take);
+            if (prev == cur) {
+                base = cur - take;
+                break;
+            }
+            cur = prev;
+        }
+    }
+    base = __shfl(base, leader);
+    take = __shfl(take, leader);
+    const int r = (int)rank_in(m);
+    if (want && r < take) return stack[base + take - 1 - r];
+    return -1;
+}
+
+// Insert a key into the per-frame request set (open addressing, linear
+// probing); the lane that adds it appends it to the request list.
+__device__ __forceinline__ void request_block(const Vol &v, int bx, int by, int bz)
+{
+    const unsigned long long key = pack_key(bx, by, bz);
+    uint32_t s = mix_key(key) & v.reqset_mask;
+    for (uint32_t it = 0; it <= v.reqset_mask; ++it) {
+        unsigned long long cur = __hip_atomic_load(&v.reqset[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == key) return;
+        if (cur == 0ull) {
+            unsigned long long prev = atomicCAS(&v.reqset[s], 0ull, key);
+            if (prev == 0ull) {
+                uint32_t idx = atomicAdd(&v.ctrl->n_req, 1u);
+                if (idx < v.max_req) {
+                    v.reqs[idx].key = key;
+                    v.reqs[idx].slot = s;
+                } else {
+                    // more new blocks than the whole block array: the budget is exhausted too
+                    atomicOr(&v.ctrl->flags, TF_FLAG_REQUEST_OVERFLOW | TF_FLAG_BLOCKS_EXHAUSTED);
+                    v.ctrl->req_overflow = 1u;
+                }
+                return;
+            }
+            if (prev == key) return;
+        }
+        s = (s + 1u) & v.reqset_mask;
+    }
+    atomicOr(&v.ctrl->flags, TF_FLAG_REQUEST_OVERFLOW);
+    v.ctrl->req_overflow = 1u;
+}
+
+// Frustum re-test of a block kept from the previous visible list (Sec. 4.2,
+// part 3): some corner in front of the camera projects into the image.
+__device__ __forceinline__ bool block_in_frustum(const Vol &v, const Cam &c, int bx, int by, int bz)
+{
+    const float umax = (float)(c.W - 1), vmax = (float)(c.H - 1);
+    for (int k = 0; k < 8; ++k) {
+        int px = 8 * (bx + (k & 1)), py = 8 * (by + ((k >> 1) & 1)), pz = 8 * (bz + (k >> 2));
+        float x, y, z;
+        cam_transform(c, (float)px * v.voxel, (float)py * v.voxel, (float)pz * v.voxel, x, y, z);
+        if (z <= 0.0f) continue;
+        float rz = 1.0f / z;
+        float u = (c.fx * x) * rz + c.cx;
+        float vv = (c.fy * y) * rz + c.cy;
+        if (u >= 0.0f && u <= umax && vv >= 0.0f && vv <= vmax) return true;
+    }
+    return false;
+}
+
+
+// ============================================================================
+// kernel bodies (each launch wraps one; blockIdx.x / gridDim.x index the work
+// of one volume, so a batched launch may use blockIdx.y for the volume)
+// ============================================================================
+// ============================================================================
+// allocation, part 1: segments, probes, marks, requests
+// ============================================================================
+// write_depth: keep the converted depth map (integration reads it)
+template <int FMT>
+__device__ __forceinline__ void alloc_rays_body(const Vol &v, const Cam &c, const void *din, bool write_depth)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p == 0) {
+        Ctrl *C = v.ctrl;
+        C->n_vis_prev = C->n_vis;
+        C->sweep_req = 0u;
+        C->n_vis = 0u;
+        C->n_new = 0u;
+        C->n_swapped_in = 0u;
+        C->n_swap_cand = 0u;
+    }
+    const int W = c.W, H = c.H;
+    if (p >= W * H) return;
+    float d;
+    if (FMT == TF_DEPTH_U16_MM)
+        d = (float)reinterpret_cast<const uint16_t *>(din)[p] / 1000.0f;   // Sec. 4 depth ingest
+    else
+        d = reinterpret_cast<const float *>(din)[p];
+    if (write_depth) v.depth[p] = d;
+    if (!(d > 0.0f)) return;
+
+    // the segment between camera depths d - mu and d + mu (Sec. 4.2), in block units
+    const int x = p % W, y = p / W;
+    const float a = ((float)x - c.cx) / c.fx;
+    const float b = ((float)y - c.cy) / c.fy;
+    const float z0 = d - v.mu, z1 = d + v.mu;
+    const float c0x = z0 * a, c0y = z0 * b, c0z = z0;
+    const float c1x = z1 * a, c1y = z1 * b, c1z = z1;
+    const float inv_block = 1.0f / (8.0f * v.voxel);
+    float q0[3], dq[3];
+    for (int r = 0; r < 3; ++r) {
+        float w0 = ((c.Ri[3 * r] * c0x + c.Ri[3 * r + 1] * c0y) + c.Ri[3 * r + 2] * c0z) + c.ti[r];
+        float w1 = ((c.Ri[3 * r] * c1x + c.Ri[3 * r + 1] * c1y) + c.Ri[3 * r + 2] * c1z) + c.ti[r];
+        q0[r] = w0 * inv_block;
+        float q1 = w1 * inv_block;
+        dq[r] = q1 - q0[r];
+    }
+    const float L = sqrtf((dq[0] * dq[0] + dq[1] * dq[1]) + dq[2] * dq[2]);
+    int n = (int)ceilf(2.0f * L);
+    if (n < 1) n = 1;
+    const float sx = dq[0] / (float)n, sy = dq[1] / (float)n, sz = dq[2] / (float)n;
+
+    int pbx = 0, pby = 0, pbz = 0;
+    bool have_prev = false;
+    int m = 0;
+    for (int k = 0; k <= n && m < kMaxSegmentSamples; ++k) {
+        const float qx = q0[0] + (float)k * sx;
+        const float qy = q0[1] + (float)k * sy;
+        const float qz = q0[2] + (float)k * sz;
+        const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
+        if (!(fx >= -32768.0f && fx <= 32767.0f && fy >= -32768.0f && fy <= 32767.0f &&
+              fz >= -32768.0f && fz <= 32767.0f))
+            continue;
+        ++m;
+        const int bx = (int)fx, by = (int)fy, bz = (int)fz;
+        if (have_prev && bx == pbx && by == pby && bz == pbz) continue;
+        have_prev = true;
+        pbx = bx;
+        pby = by;
+        pbz = bz;
+        int ptr;
+        int e = find_entry(v, bx, by, bz, kPtrSwapped, &ptr);
+        if (e >= 0) {
+            if (ptr >= 0)
+                v.vis[e] = kVisTouched;
+            else if (v.host_has)
+                request_block(v, bx, by, bz);   // swapped out: revive with a fresh device block (Sec. 5)
+        } else {
+            request_block(v, bx, by, bz);
+        }
+    }
+}
+
+// ============================================================================
+// allocation, parts 2 and 3a: insertion and the previous list's frustum test
+// ============================================================================
+__device__ __forceinline__ void insert_body(const Vol &v, const Cam &c)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t gwave = (blockIdx.x * 256u + threadIdx.x) / kWave;
+    const uint32_t nwaves = gridDim.x * (256u / kWave);
+    uint32_t n = v.ctrl->n_req;
+    if (n > v.max_req) n = v.max_req;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        v.ctrl->sweep_req = v.ctrl->req_overflow;
+        v.ctrl->req_overflow = 0u;
+    }
+
+    for (uint32_t base = gwave * kWave; base < n; base += nwaves * kWave) {
+        const uint32_t i = base + lane;
+        const bool active = i < n;
+        int bx = 0, by = 0, bz = 0;
+        if (active) {
+            Req r = v.reqs[i];
+            v.reqset[r.slot] = 0ull;
+            unpack_key(r.key, bx, by, bz);
+        }
+        // a request for a swapped-out block revives its entry (Sec. 5)
+        int revive = -1;
+        if (active && v.host_has) {
+            int pp;
+            const int e = find_entry(v, bx, by, bz, kPtrSwapped, &pp);
+            if (e >= 0 && pp == kPtrSwapped) revive = e;
+        }
+        const int32_t blk = wave_pop(&v.ctrl->free_blocks, v.free_blocks, active);
+        if (active && blk < 0) atomicOr(&v.ctrl->flags, TF_FLAG_BLOCKS_EXHAUSTED);
+        const uint32_t h = hash_index(bx, by, bz, v.n_buckets - 1u);
+        int entry = -1;
+        bool need_excess = false;
+        const unsigned long long posw = (unsigned long long)(uint16_t)bx | ((unsigned long long)(uint16_t)by << 16) |
+                                        ((unsigned long long)(uint16_t)bz << 32);
+        if (active && blk >= 0 && revive >= 0) {
+            v.entries[revive].ptr = blk;
+            entry = revive;
+        } else if (active && blk >= 0) {
+            int prev = atomicCAS(&v.entries[h].ptr, kPtrEmpty, kPtrClaimed);
+            if (prev == kPtrEmpty) {
+                *reinterpret_cast<unsigned long long *>(&v.entries[h]) = posw;
+                v.entries[h].ptr = blk;
+                entry = (int)h;
+            } else {
+                need_excess = true;
+            }
+        }
+        const int32_t slot = wave_pop(&v.ctrl->free_excess, v.free_excess, need_excess);
+        if (need_excess) {
+            if (slot < 0) {
+                atomicOr(&v.ctrl->flags, TF_FLAG_EXCESS_EXHAUSTED);
+                uint32_t ri = atomicAdd(&v.ctrl->n_ret, 1u);
+                v.ret[ri] = blk;
+            } else {
+                const uint32_t idx = v.n_buckets + (uint32_t)slot;
+                *reinterpret_cast<unsigned long long *>(&v.entries[idx]) = posw;
+                v.entries[idx].ptr = blk;
+                int32_t old = __hip_atomic_load(&v.entries[h].offset, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (;;) {
+                    v.entries[idx].offset = old;
+                    int32_t pr = atomicCAS(&v.entries[h].offset, old, slot + 1);
+                    if (pr == old) break;
+                    old = pr;
+                }
+                entry = (int)idx;
+            }
+        }
+        if (entry >= 0) {
+            v.vis[entry] = kVisNew;
+            if (revive < 0) atomicOr(&v.occ[h >> 5], 1u << (h & 31u));
+            if (revive < 0 && v.alist) {
+                // submap volumes keep a list of their allocated blocks (no swapping there)
+                const uint32_t ai = atomicAdd(&v.ctrl->n_alloc, 1u);
+                v.alist[ai] = make_int4((int)((uint32_t)(uint16_t)bx | ((uint32_t)(uint16_t)by << 16)), bz, blk, entry);
+            }
+        }
+        // initialise each new block (Sec. 3.1: sdf 32767, weight 0) with the whole wave
+        unsigned long long m = __ballot(entry >= 0);
+        const unsigned long long mi = __ballot(entry >= 0 && revive < 0);
+        if (lane == 0 && mi) atomicAdd(&v.ctrl->n_new, (uint32_t)__popcll(mi));
+        while (m) {
+            const int l = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const int b = __shfl(blk, l);
+            uint8_t *dst = v.voxels + (size_t)b * kBlockBytes;
+            reinterpret_cast<uint4 *>(dst)[lane] = make_uint4(0x7fff7fffu, 0x7fff7fffu, 0x7fff7fffu, 0x7fff7fffu);
+            reinterpret_cast<uint2 *>(dst + 1024)[lane] = make_uint2(0u, 0u);
+        }
+    }
+
+    const uint32_t np = v.ctrl->n_vis_prev;
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < np; i += gridDim.x * 256u) {
+        const int e = v.vlist[i];
+        const int4 w = load_entry(v.entries, (uint32_t)e);
+        if (w.w < 0 || v.vis[e] != 0) continue;
+        const int bx = (int16_t)(w.x & 0xffff), by = (int16_t)((uint32_t)w.x >> 16), bz = (int16_t)(w.y & 0xffff);
+        if (block_in_frustum(v, c, bx, by, bz)) v.vis[e] = kVisTouched;
+    }
+}
+
+// ============================================================================
+// allocation, part 3b: compaction of the marks into the visible list
+// ============================================================================
+__device__ __forceinline__ void visible_body(const Vol &v)
+{
+    const uint32_t lane = lane_id();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        Ctrl *C = v.ctrl;
+        C->tot_req += C->n_req < v.max_req ? C->n_req : v.max_req;
+        C->tot_new += C->n_new;
+        C->n_req = 0u;
+        C->frames += 1u;
+        const uint32_t nr = C->n_ret;
+        if (nr) {
+            const int32_t h = C->free_blocks;
+            for (uint32_t i = 0; i < nr; ++i) v.free_blocks[h + (int32_t)i] = v.ret[i];
+            C->free_blocks = h + (int32_t)nr;
+            C->n_ret = 0u;
+        }
+    }
+    if (v.ctrl->sweep_req) {
+        for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i <= v.reqset_mask; i += gridDim.x * 256u)
+            v.reqset[i] = 0ull;
+    }
+    const uint32_t gwave = (blockIdx.x * 256u + threadIdx.x) / kWave;
+    const uint32_t nwaves = gridDim.x * (256u / kWave);
+    const uint32_t nchunks = (v.n_entries + 15u) / 16u;
+    for (uint32_t cb = gwave * kWave; cb < nchunks; cb += nwaves * kWave) {
+        const uint32_t ch = cb + lane;
+        uint4 f = make_uint4(0u, 0u, 0u, 0u);
+        if (ch < nchunks) f = reinterpret_cast<const uint4 *>(v.vis)[ch];
+        const uint32_t words[4] = {f.x, f.y, f.z, f.w};
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) cnt += ((words[j >> 2] >> (8 * (j & 3))) & 0xffu) ? 1u : 0u;
+        uint32_t incl = cnt;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            uint32_t t = __shfl_up(incl, d);
+            if ((int)lane >= d) incl += t;
+        }
+        const uint32_t total = __shfl(incl, kWave - 1);
+        if (total == 0) continue;
+        uint32_t base = 0;
+        if (lane == kWave - 1) base = atomicAdd(&v.ctrl->n_vis, total);
+        base = __shfl(base, kWave - 1);
+        uint32_t pos = base + incl - cnt;
+        if (cnt) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if ((words[j >> 2] >> (8 * (j & 3))) & 0xffu) v.vlist[pos++] = (int32_t)(ch * 16u + (uint32_t)j);
+            reinterpret_cast<uint4 *>(v.vis)[ch] = make_uint4(0u, 0u, 0u, 0u);
+        }
+    }
+}
+
+// ============================================================================
+// integration (Sec. 4.3)
+// ============================================================================
+// Lane (lx, ly) = (lane >> 3, lane & 7) owns the 8 voxels lz = 0..7 of one
+// column; the device in-block order lz + 8 ly + 64 lx puts them in 16
+// contiguous bytes of SDF and 8 of weight, so a wave moves a block in one
+// dwordx4 and one dwordx2 access per lane.
+// NT threads per workgroup; rcp_w (260 floats) and wg_cols are the caller's
+// LDS; dry: compute every update but store nothing (timing probes)
+template <int NT>
+__device__ __forceinline__ void integrate_body(const Vol &v, const Cam &c, float *rcp_w, uint32_t *wg_cols, bool dry)
+{
+    for (int k = threadIdx.x; k < 260; k += NT) rcp_w[k] = k ? 1.0f / (float)k : 0.0f;
+    __syncthreads();
+    const uint32_t lane = lane_id();
+    const uint32_t gwave = (blockIdx.x * (uint32_t)NT + threadIdx.x) / kWave;
+    const uint32_t nwaves = gridDim.x * ((uint32_t)NT / kWave);
+    const uint32_t nvis = v.ctrl->n_vis;
+    const int lx = (int)(lane >> 3), ly = (int)(lane & 7);
+    const float vs = v.voxel;
+    const float inv_mu = 1.0f / v.mu;
+    const float neg_mu = -v.mu;
+    const float k_sdf = 1.0f / 32767.0f;
+    const float umax = (float)(c.W - 2), vmax = (float)(c.H - 2);
+    const int W = c.W;
+    const int max_w = v.max_w;
+    const float *depth = v.depth;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        v.ctrl->tot_vis += nvis;
+        v.ctrl->n_integrate += 1ull;
+    }
+    uint32_t cols = 0;
+
+    for (uint32_t i = gwave; i < nvis; i += nwaves) {
+        const int e = v.vlist[i];
+        const int4 w = load_entry(v.entries, (uint32_t)e);
+        const int ptr = w.w;
+        if (ptr < 0) continue;
+        const int bx = (int16_t)(w.x & 0xffff), by = (int16_t)((uint32_t)w.x >> 16), bz = (int16_t)(w.y & 0xffff);
+        uint8_t *blk = v.voxels + (size_t)ptr * kBlockBytes;
+        uint4 s8 = reinterpret_cast<const uint4 *>(blk)[lane];
+        uint2 w8 = reinterpret_cast<const uint2 *>(blk + 1024)[lane];
+        uint32_t sw[4] = {s8.x, s8.y, s8.z, s8.w};
+        uint32_t ww[2] = {w8.x, w8.y};
+        const float X = (float)(8 * bx + lx) * vs;
+        const float Y = (float)(8 * by + ly) * vs;
+        const float p0 = c.M[0] * X + c.M[1] * Y;
+        const float p1 = c.M[4] * X + c.M[5] * Y;
+        const float p2 = c.M[8] * X + c.M[9] * Y;
+        // phase 1: projection of the column's 8 voxels (no memory traffic)
+        float czs[8];
+        int idx[8];
+        bool inimg[8];
+#pragma unroll
+        for (int lz = 0; lz < 8; ++lz) {
+            const float Z = (float)(8 * bz + lz) * vs;
+            const float cx = (p0 + c.M[2] * Z) + c.M[3];
+            const float cy = (p1 + c.M[6] * Z) + c.M[7];
+            const float cz = (p2 + c.M[10] * Z) + c.M[11];
+            czs[lz] = cz;
+            bool ok = cz > 0.0f;
+            const float rz = 1.0f / (ok ? cz : 1.0f);
+            const float u = (c.fx * cx) * rz + c.cx;
+            const float vv = (c.fy * cy) * rz + c.cy;
+            ok = ok && !(u < 1.0f || u > umax || vv < 1.0f || vv > vmax);
+            const int ix = ok ? (int)(u + 0.5f) : 0, iy = ok ? (int)(vv + 0.5f) : 0;
+            inimg[lz] = ok;
+            idx[lz] = ix + iy * W;
+        }
+        // phase 2: the 8 depth reads, issued together
+        float dep[8];
+#pragma unroll
+        for (int lz = 0; lz < 8; ++lz) dep[lz] = gload(depth + idx[lz]);
+        // phase 3: the running-average update (Sec. 4.3)
+        bool changed = false;
+#pragma unroll
+        for (int lz = 0; lz < 8; ++lz) {
+            if (!inimg[lz]) continue;
+            const float d = dep[lz];
+            if (d <= 0.0f) continue;
+            const float eta = d - czs[lz];
+            if (eta < neg_mu) continue;
+            float f_new = eta * inv_mu;
+            if (f_new > 1.0f) f_new = 1.0f;
+            const uint32_t sh = 16u * (lz & 1);
+            const int s_old = (int16_t)((sw[lz >> 1] >> sh) & 0xffffu);
+            const uint32_t whs = 8u * (lz & 3);
+            const int w_old = (int)((ww[lz >> 2] >> whs) & 0xffu);
+            const float f_old = (float)s_old * k_sdf;
+            const float avg = ((float)w_old * f_old + f_new) * rcp_w[w_old + 1];
+            int w_new = w_old + 1;
+            if (w_new > max_w) w_new = max_w;
+            const int s_new = (int16_t)(avg * 32767.0f);
+            sw[lz >> 1] = (sw[lz >> 1] & ~(0xffffu << sh)) | (((uint32_t)s_new & 0xffffu) << sh);
+            ww[lz >> 2] = (ww[lz >> 2] & ~(0xffu << whs)) | ((uint32_t)w_new << whs);
+            changed = true;
+        }
+        if (changed && !dry) {
+            reinterpret_cast<uint4 *>(blk)[lane] = make_uint4(sw[0], sw[1], sw[2], sw[3]);
+            reinterpret_cast<uint2 *>(blk + 1024)[lane] = make_uint2(ww[0], ww[1]);
+            ++cols;
+        }
+    }
+    // per-workgroup count of written columns (no cross-workgroup atomics)
+    if (threadIdx.x == 0) *wg_cols = 0;
+    __syncthreads();
+    if (cols && !dry) atomicAdd(wg_cols, cols);
+    __syncthreads();
+    if (threadIdx.x == 0 && *wg_cols) v.acc_cols[blockIdx.x] += *wg_cols;
+}
+
+// ============================================================================
+// search range (Sec. 4.4): the projected box and camera-z range of a block
+// ============================================================================
+// Box of the cube with voxel corner (x0, y0, z0) and edge `span` voxels, seen
+// by camera matrix M (12 floats) with the intrinsics of c: the pixel box of
+// its corner projections (floor/ceil, clipped to the image) and the corners'
+// camera-z range; a cube reaching closer than kZNear covers the whole image
+// from kZNear.  False when it lies behind the near plane or off the image.
+__device__ __forceinline__ bool cube_record(const float *M, const Cam &c, float voxel, int x0, int y0, int z0,
+                                            int span, Rec &r)
+{
+    float xs[8], ys[8], zs[8];
+    float zlo = __builtin_inff(), zhi = -__builtin_inff();
+    for (int k = 0; k < 8; ++k) {
+        const int px = x0 + span * (k & 1), py = y0 + span * ((k >> 1) & 1), pz = z0 + span * (k >> 2);
+        const float X = (float)px * voxel, Y = (float)py * voxel, Z = (float)pz * voxel;
+        xs[k] = ((M[0] * X + M[1] * Y) + M[2] * Z) + M[3];
+        ys[k] = ((M[4] * X + M[5] * Y) + M[6] * Z) + M[7];
+        zs[k] = ((M[8] * X + M[9] * Y) + M[10] * Z) + M[11];
+        if (zs[k] < zlo) zlo = zs[k];
+        if (zs[k] > zhi) zhi = zs[k];
+    }
+    if (zhi < kZNear) return false;
+    if (zlo < kZNear) {
+        r.x0 = 0;
+        r.y0 = 0;
+        r.x1 = (int16_t)(c.W - 1);
+        r.y1 = (int16_t)(c.H - 1);
+        r.zlo = kZNear;
+        r.zhi = zhi;
+        return true;
+    }
+    float umin = __builtin_inff(), umax = -__builtin_inff(), vmin = __builtin_inff(), vmax = -__builtin_inff();
+    for (int k = 0; k < 8; ++k) {
+        float rz = 1.0f / zs[k];
+        float u = (c.fx * xs[k]) * rz + c.cx;
+        float vv = (c.fy * ys[k]) * rz + c.cy;
+        if (u < umin) umin = u;
+        if (u > umax) umax = u;
+        if (vv < vmin) vmin = vv;
+        if (vv > vmax) vmax = vv;
+    }
+    float fx0 = floorf(umin), fx1 = ceilf(umax), fy0 = floorf(vmin), fy1 = ceilf(vmax);
+    if (fx0 < 0.0f) fx0 = 0.0f;
+    if (fy0 < 0.0f) fy0 = 0.0f;
+    if (fx1 > (float)(c.W - 1)) fx1 = (float)(c.W - 1);
+    if (fy1 > (float)(c.H - 1)) fy1 = (float)(c.H - 1);
+    if (fx0 > fx1 || fy0 > fy1) return false;
+    r.x0 = (int16_t)(int)fx0;
+    r.x1 = (int16_t)(int)fx1;
+    r.y0 = (int16_t)(int)fy0;
+    r.y1 = (int16_t)(int)fy1;
+    r.zlo = zlo;
+    r.zhi = zhi;
+    return true;
+}
+
+__device__ __forceinline__ bool block_record(const Vol &v, const Cam &c, int bx, int by, int bz, Rec &r)
+{
+    return cube_record(c.M, c, v.voxel, 8 * bx, 8 * by, 8 * bz, 8, r);
+}
+
+// ============================================================================
+// trilinear reads (Sec. 4.4)
+// ============================================================================
+__device__ __forceinline__ int block_of(float X) { return ((int)floorf(X)) >> 3; }
+
+// the 2x2x2 cell of a trilinear read: corner block pointers, in-block voxel
+// indices (lz + 8 ly + 64 lx) and the interpolation fractions
+struct Cell {
+    int p[8], j[8];
+    float tx, ty, tz;
+};
+
+// absent voxels read 1.0; lerp a + (b - a) t along x, then y, then z
+__device__ __forceinline__ float cell_interp(const Cell &C, const int16_t (&s)[8])
+{
+    float f[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) f[c] = C.p[c] >= 0 ? (float)s[c] * (1.0f / 32767.0f) : 1.0f;
+    const float c00 = f[0] + (f[1] - f[0]) * C.tx;
+    const float c10 = f[2] + (f[3] - f[2]) * C.tx;
+    const float c01 = f[4] + (f[5] - f[4]) * C.tx;
+    const float c11 = f[6] + (f[7] - f[6]) * C.tx;
+    const float c0 = c00 + (c10 - c00) * C.ty;
+    const float c1 = c01 + (c11 - c01) * C.ty;
+    return c0 + (c1 - c0) * C.tz;
+}
+
+}  // namespace
+
+}  // namespace tsdf

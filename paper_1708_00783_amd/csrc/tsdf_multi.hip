@@ -1,0 +1,606 @@
+// tsdf_multi.hip -- gfx950 kernels of the batched rigid submaps (Sec. 7.2).
+//
+//   k_m_alloc / k_m_insert / k_m_visible / k_m_integrate
+//       one depth frame into the submaps selected for it, blockIdx.y = slot of
+//       the selection; each runs the single-volume body on its submap with the
+//       camera composed with that submap's pose
+//   k_m_bin<false>, k_m_scan, k_m_bin<true>
+//       every allocated block of every submap against every view: count the
+//       (block, tile) pairs, exclusive offsets, then fill the tile bins.  A
+//       block is binned by its cube grown by kExpand voxels, so that a tile's
+//       bin holds every block any trilinear read of its rays can touch
+//   k_m_raycast<TW, TH>
+//       one workgroup per TWxTH tile of any view: the per-pixel search range,
+//       the tile's submap set and an LDS block table from the bin, then the
+//       ray state machine on the combined field
+//
+// The combined field at a world point (voxel units) is the weighted average of
+// the submaps' trilinear SDF, each weighted by its trilinear weight, over the
+// submaps whose weight there is positive; one contributor gives its value
+// unchanged and none gives 1.  Submaps are summed in ascending index order.
+#include "tsdf_device.h"
+
+namespace tsdf {
+
+// ============================================================================
+// integration of one frame into the selected submaps
+// ============================================================================
+__global__ __launch_bounds__(256) void k_m_alloc(const Vol *vols, const MFrame *f)
+{
+    const int y = (int)blockIdx.y;
+    if (y >= f->n_sel) return;
+    const Vol v = vols[f->sel[y]];
+    const Cam c = f->icam[y];
+    // every submap reads the one shared depth map; slot 0 writes it
+    if (f->fmt == TF_DEPTH_U16_MM)
+        alloc_rays_body<TF_DEPTH_U16_MM>(v, c, f->depth, y == 0);
+    else
+        alloc_rays_body<TF_DEPTH_F32_M>(v, c, f->depth, y == 0);
+}
+
+__global__ __launch_bounds__(256) void k_m_insert(const Vol *vols, const MFrame *f)
+{
+    const int y = (int)blockIdx.y;
+    if (y >= f->n_sel) return;
+    const Vol v = vols[f->sel[y]];
+    const Cam c = f->icam[y];
+    insert_body(v, c);
+}
+
+__global__ __launch_bounds__(256) void k_m_visible(const Vol *vols, const MFrame *f)
+{
+    const int y = (int)blockIdx.y;
+    if (y >= f->n_sel) return;
+    const Vol v = vols[f->sel[y]];
+    visible_body(v);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_m_integrate(const Vol *vols, const MFrame *f, int dry)
+{
+    __shared__ float rcp_w[260];
+    __shared__ uint32_t wg_cols;
+    const int y = (int)blockIdx.y;
+    if (y >= f->n_sel) return;
+    const Vol v = vols[f->sel[y]];
+    const Cam c = f->icam[y];
+    integrate_body<NT>(v, c, rcp_w, &wg_cols, dry != 0);
+}
+
+// ============================================================================
+// tile bins of every view
+// ============================================================================
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_m_bin(const MSub *subs, const MFrame *f, MTiles t, float voxel)
+{
+    const int vi = (int)blockIdx.y;
+    if (vi >= f->n_views) return;
+    const Cam vc = f->view[vi].cam;
+    const int ntx = f->view[vi].ntx, base = f->view[vi].tile_base;
+    const int tw = f->tw, th = f->th;
+    const int n_sub = f->n_sub;
+    for (int sm = 0; sm < n_sub; ++sm) {
+        const uint32_t n = subs[sm].ctrl->n_alloc;
+        const int4 *al = subs[sm].alist;
+        const float *M = f->C[vi][sm];
+        for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+            const int4 b = al[i];
+            const int bx = (int16_t)(b.x & 0xffff), by = (int16_t)((uint32_t)b.x >> 16), bz = b.y;
+            Rec ex;
+            if (!cube_record(M, vc, voxel, 8 * bx - kExpand, 8 * by - kExpand, 8 * bz - kExpand, 8 + 2 * kExpand, ex))
+                continue;
+            const int tx0 = ex.x0 / tw, tx1 = ex.x1 / tw, ty0 = ex.y0 / th, ty1 = ex.y1 / th;
+            if (!FILL) {
+                for (int ty = ty0; ty <= ty1; ++ty)
+                    for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&t.cnt[base + ty * ntx + tx], 1);
+                continue;
+            }
+            // the search-range box of the block itself (empty when it is behind
+            // the near plane or off the image: then it only feeds the table)
+            Rec r;
+            if (!cube_record(M, vc, voxel, 8 * bx, 8 * by, 8 * bz, 8, r)) {
+                r.x0 = 1;
+                r.x1 = 0;
+                r.y0 = 1;
+                r.y1 = 0;
+                r.zlo = __builtin_inff();
+                r.zhi = -__builtin_inff();
+            }
+            r.bx = (int16_t)bx;
+            r.by = (int16_t)by;
+            r.bz = (int16_t)bz;
+            r.pad = (int16_t)sm;
+            r.ptr = b.z;
+            r.pad2 = 0;
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) {
+                    const int g = base + ty * ntx + tx;
+                    const uint32_t idx = t.off[g] + (uint32_t)atomicAdd(&t.cur[g], 1);
+                    if (idx < t.cap) t.bins[idx] = r;
+                }
+        }
+    }
+}
+
+// exclusive offsets of the tile counts (one workgroup); clears the counts and
+// cursors for the next launch
+__global__ __launch_bounds__(1024) void k_m_scan(MTiles t)
+{
+    __shared__ uint32_t part[1024];
+    const uint32_t n = t.n_tiles;
+    const uint32_t per = (n + 1023u) / 1024u;
+    const uint32_t b0 = threadIdx.x * per;
+    const uint32_t b1 = b0 + per < n ? b0 + per : n;
+    uint32_t sum = 0;
+    for (uint32_t i = b0; i < b1; ++i) sum += (uint32_t)t.cnt[i];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024u; d <<= 1) {
+        const uint32_t add = threadIdx.x >= d ? part[threadIdx.x - d] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - sum;
+    for (uint32_t i = b0; i < b1; ++i) {
+        const uint32_t c = (uint32_t)t.cnt[i];
+        t.off[i] = run;
+        run += c;
+        t.cnt[i] = 0;
+        t.cur[i] = 0;
+    }
+    if (threadIdx.x == 1023) {
+        const uint32_t total = part[1023];
+        t.off[n] = total;
+        t.mc->tot_bin += total;
+        t.mc->n_raycast += 1ull;
+        if (total > t.cap) t.mc->flags |= TF_FLAG_BIN_OVERFLOW;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_m_clear(MTiles t)
+{
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < t.n_tiles; i += gridDim.x * 256u) {
+        t.cnt[i] = 0;
+        t.cur[i] = 0;
+        t.off[i] = 0u;
+        t.acc_hits[i] = 0ull;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) t.off[t.n_tiles] = 0u;
+}
+
+// ============================================================================
+// combined-field raycast
+// ============================================================================
+namespace {
+
+// LDS of one tile: a chunk of bin records, the (submap, block) -> pointer
+// table, and the tile's submaps in ascending order with what the field reads
+template <int NT>
+struct MTileLds {
+    static constexpr int TT = 4 * NT;           // table slots
+    Rec chunk[NT];
+    unsigned long long key[TT];                 // 0 = empty
+    int ptr[TT];
+    float Rs[kMaxSubmaps][12];                  // rotation rows, then translation (voxel units)
+    const DEntry *ent[kMaxSubmaps];
+    const uint32_t *occ[kMaxSubmaps];
+    const uint8_t *vox[kMaxSubmaps];
+    uint32_t nb[kMaxSubmaps], ne[kMaxSubmaps];
+    int smid[kMaxSubmaps];
+    unsigned long long mask;
+    uint32_t n_tab, hits;
+};
+
+template <int NT>
+__device__ __forceinline__ uint32_t mslot(int sm, int bx, int by, int bz)
+{
+    return (hash_index(bx, by, bz, 0xffffffffu) ^ ((uint32_t)sm * 0x9e3779b1u)) & (uint32_t)(MTileLds<NT>::TT - 1);
+}
+
+__device__ __forceinline__ unsigned long long mkey(int sm, int bx, int by, int bz)
+{
+    return pack_key(bx, by, bz) | ((unsigned long long)sm << 49);
+}
+
+// Search range of the pixel and the tile's LDS state from its bin.  Every
+// thread of the workgroup calls it.
+template <int NT>
+__device__ __forceinline__ void m_tile_setup(const MSub *subs, const MTiles &t, uint32_t g, int px, int py,
+                                             float &zmin, float &zmax, MTileLds<NT> &L)
+{
+    constexpr int TT = MTileLds<NT>::TT;
+    zmin = __builtin_inff();
+    zmax = -__builtin_inff();
+    for (int k = threadIdx.x; k < TT; k += NT) L.key[k] = 0ull;
+    if (threadIdx.x == 0) {
+        L.mask = 0ull;
+        L.n_tab = 0u;
+        L.hits = 0u;
+    }
+    const uint32_t o0 = t.off[g];
+    uint32_t o1 = t.off[g + 1];
+    if (o1 > t.cap) o1 = t.cap;
+    const int n = o1 > o0 ? (int)(o1 - o0) : 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += NT) {
+        const int j = base + (int)threadIdx.x;
+        if (j < n) {
+            const Rec r = t.bins[o0 + (uint32_t)j];
+            L.chunk[threadIdx.x] = r;
+            atomicOr(&L.mask, 1ull << (uint32_t)r.pad);
+            // keys in one bin are distinct; keep the table at most half full
+            if (atomicAdd(&L.n_tab, 1u) < (uint32_t)(TT / 2)) {
+                const unsigned long long key = mkey(r.pad, r.bx, r.by, r.bz);
+                uint32_t sl = mslot<NT>(r.pad, r.bx, r.by, r.bz);
+                for (int k = 0; k < TT; ++k) {
+                    if (atomicCAS(&L.key[sl], 0ull, key) == 0ull) {
+                        L.ptr[sl] = r.ptr;
+                        break;
+                    }
+                    sl = (sl + 1u) & (uint32_t)(TT - 1);
+                }
+            }
+        }
+        __syncthreads();
+        const int m = (n - base) < NT ? (n - base) : NT;
+        for (int k = 0; k < m; ++k) {
+            const Rec r = L.chunk[k];
+            if (px >= r.x0 && px <= r.x1 && py >= r.y0 && py <= r.y1) {
+                if (r.zlo < zmin) zmin = r.zlo;
+                if (r.zhi > zmax) zmax = r.zhi;
+            }
+        }
+        __syncthreads();
+    }
+    // the tile's submaps, ascending
+    if (threadIdx.x < (unsigned)kMaxSubmaps) {
+        const unsigned long long m = L.mask;
+        const int sm = (int)threadIdx.x;
+        if ((m >> sm) & 1ull) {
+            const int k = __popcll(m & ((1ull << sm) - 1ull));
+            const MSub &S = subs[sm];
+            for (int q = 0; q < 9; ++q) L.Rs[k][q] = S.R[q];
+            for (int q = 0; q < 3; ++q) L.Rs[k][9 + q] = S.s[q];
+            L.ent[k] = S.entries;
+            L.occ[k] = S.occ;
+            L.vox[k] = S.voxels;
+            L.nb[k] = S.n_buckets;
+            L.ne[k] = S.n_excess;
+            L.smid[k] = sm;
+        }
+    }
+    __syncthreads();
+}
+
+// device pointer of block (bx, by, bz) of the k-th submap of the tile (-1 =
+// absent): the LDS table first, then the submap's bucket bitmap and hash table
+template <int NT>
+__device__ __forceinline__ int m_lookup(const MTileLds<NT> &L, int k, int bx, int by, int bz)
+{
+    constexpr int TT = MTileLds<NT>::TT;
+    if (!in_short_range(bx) || !in_short_range(by) || !in_short_range(bz)) return -1;
+    const int sm = L.smid[k];
+    const unsigned long long key = mkey(sm, bx, by, bz);
+    uint32_t sl = mslot<NT>(sm, bx, by, bz);
+    for (int it = 0; it < TT; ++it) {
+        const unsigned long long kk = L.key[sl];
+        if (kk == key) return L.ptr[sl];
+        if (kk == 0ull) break;
+        sl = (sl + 1u) & (uint32_t)(TT - 1);
+    }
+    const uint32_t h = hash_index(bx, by, bz, L.nb[k] - 1u);
+    if (!((gload(L.occ[k] + (h >> 5)) >> (h & 31u)) & 1u)) return -1;
+    int ptr = -1;
+    const int e = find_entry_in(L.ent[k], L.nb[k], L.ne[k], bx, by, bz, 0, &ptr);
+    return e >= 0 ? ptr : -1;
+}
+
+template <int NT>
+__device__ __forceinline__ void to_sub(const MTileLds<NT> &L, int k, float P0, float P1, float P2, float &Q0,
+                                       float &Q1, float &Q2)
+{
+    const float *R = L.Rs[k];
+    Q0 = ((R[0] * P0 + R[1] * P1) + R[2] * P2) + R[9];
+    Q1 = ((R[3] * P0 + R[4] * P1) + R[5] * P2) + R[10];
+    Q2 = ((R[6] * P0 + R[7] * P1) + R[8] * P2) + R[11];
+}
+
+// "allocated" of the combined map: some submap has a device block at floor(P_i X)
+template <int NT>
+__device__ __forceinline__ bool m_allocated(const MTileLds<NT> &L, int ns, float P0, float P1, float P2)
+{
+    for (int k = 0; k < ns; ++k) {
+        float Q0, Q1, Q2;
+        to_sub(L, k, P0, P1, P2, Q0, Q1, Q2);
+        if (m_lookup(L, k, block_of(Q0), block_of(Q1), block_of(Q2)) >= 0) return true;
+    }
+    return false;
+}
+
+// combined field at world voxel-unit P
+template <int NT>
+__device__ __forceinline__ float m_field(const MTileLds<NT> &L, int ns, float P0, float P1, float P2)
+{
+    int cnt = 0;
+    float first = 1.0f, num = 0.0f, den = 0.0f;
+    for (int k = 0; k < ns; ++k) {
+        float Q0, Q1, Q2;
+        to_sub(L, k, P0, P1, P2, Q0, Q1, Q2);
+        const float fbx = floorf(Q0), fby = floorf(Q1), fbz = floorf(Q2);
+        Cell C;
+        C.tx = Q0 - fbx;
+        C.ty = Q1 - fby;
+        C.tz = Q2 - fbz;
+        const int ix = (int)fbx, iy = (int)fby, iz = (int)fbz;
+        const int Bx = ix >> 3, By = iy >> 3, Bz = iz >> 3;
+        const bool sx = (ix & 7) == 7, sy = (iy & 7) == 7, sz = (iz & 7) == 7;
+        const int p000 = m_lookup(L, k, Bx, By, Bz);
+        int p100 = p000, p010 = p000, p001 = p000, p110 = p000, p101 = p000, p011 = p000, p111 = p000;
+        if (sx | sy | sz) {
+            if (sx) p100 = m_lookup(L, k, Bx + 1, By, Bz);
+            if (sy) p010 = m_lookup(L, k, Bx, By + 1, Bz);
+            if (sz) p001 = m_lookup(L, k, Bx, By, Bz + 1);
+            p110 = (sx & sy) ? m_lookup(L, k, Bx + 1, By + 1, Bz) : (sx ? p100 : p010);
+            p101 = (sx & sz) ? m_lookup(L, k, Bx + 1, By, Bz + 1) : (sx ? p100 : p001);
+            p011 = (sy & sz) ? m_lookup(L, k, Bx, By + 1, Bz + 1) : (sy ? p010 : p001);
+            p111 = (sx & sy & sz) ? m_lookup(L, k, Bx + 1, By + 1, Bz + 1)
+                                  : (sx & sy) ? p110 : (sx & sz) ? p101 : (sy & sz) ? p011 : sx ? p100 : sy ? p010 : p001;
+        }
+        C.p[0] = p000;
+        C.p[1] = p100;
+        C.p[2] = p010;
+        C.p[3] = p110;
+        C.p[4] = p001;
+        C.p[5] = p101;
+        C.p[6] = p011;
+        C.p[7] = p111;
+        const uint8_t *vox = L.vox[k];
+        int16_t s[8];
+        uint8_t w8[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int cx = ix + (c & 1), cy = iy + ((c >> 1) & 1), cz = iz + (c >> 2);
+            C.j[c] = (cz & 7) + 8 * (cy & 7) + 64 * (cx & 7);
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const uint8_t *blk = vox + (size_t)(C.p[c] >= 0 ? C.p[c] : 0) * kBlockBytes;
+            const int j = C.p[c] >= 0 ? C.j[c] : 0;
+            s[c] = gload(reinterpret_cast<const int16_t *>(blk) + j);
+            w8[c] = gload(blk + 1024 + j);
+        }
+        // trilinear weight (absent voxels weigh 0), same order as the SDF
+        float wf[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) wf[c] = C.p[c] >= 0 ? (float)w8[c] : 0.0f;
+        const float c00 = wf[0] + (wf[1] - wf[0]) * C.tx;
+        const float c10 = wf[2] + (wf[3] - wf[2]) * C.tx;
+        const float c01 = wf[4] + (wf[5] - wf[4]) * C.tx;
+        const float c11 = wf[6] + (wf[7] - wf[6]) * C.tx;
+        const float c0 = c00 + (c10 - c00) * C.ty;
+        const float c1 = c01 + (c11 - c01) * C.ty;
+        const float w = c0 + (c1 - c0) * C.tz;
+        if (!(w > 0.0f)) continue;
+        const float F = cell_interp(C, s);
+        if (cnt == 0) first = F;
+        num = num + w * F;
+        den = den + w;
+        ++cnt;
+    }
+    if (cnt == 0) return 1.0f;
+    if (cnt == 1) return first;
+    return num / den;
+}
+
+enum { M_COARSE, M_FINE, M_SURFACE, M_BEHIND, M_WRONG_SIDE };
+
+// the view of flat tile index g (views are few; their tile ranges ascend)
+__device__ __forceinline__ int view_of(const MFrame *f, int g)
+{
+    int vi = 0;
+    while (vi + 1 < f->n_views && g >= f->view[vi + 1].tile_base) ++vi;
+    return vi;
+}
+
+}  // namespace
+
+// one workgroup per TW x TH tile of any view; waves cover 8x8 pixel squares
+template <int TW, int TH>
+__global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MFrame *f, MTiles t, float voxel,
+                                                      float mu)
+{
+    constexpr int NT = TW * TH;
+    __shared__ MTileLds<NT> L;
+    const int g = (int)blockIdx.x;
+    const int vi = view_of(f, g);
+    const MView &V = f->view[vi];
+    const int tile = g - V.tile_base;
+    const int W = V.cam.W, H = V.cam.H;
+    const int q = (int)threadIdx.x >> 6, i = (int)threadIdx.x & 63;
+    const int px = (tile % V.ntx) * TW + (q % (TW / 8)) * 8 + (i & 7);
+    const int py = (tile / V.ntx) * TH + (q / (TW / 8)) * 8 + (i >> 3);
+    float zmin, zmax;
+    m_tile_setup<NT>(subs, t, (uint32_t)g, px, py, zmin, zmax, L);
+    const int ns = __popcll(L.mask);
+    const bool inside = px < W && py < H;
+    float4 out_p = make_float4(0.f, 0.f, 0.f, 0.f), out_n = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (inside && zmin <= zmax) {
+        const Cam &c = V.cam;
+        const float inv_vs = 1.0f / voxel;
+        const float mu_v = mu * inv_vs;
+        const float ox = c.ti[0] * inv_vs, oy = c.ti[1] * inv_vs, oz = c.ti[2] * inv_vs;
+        const float a = ((float)px - c.cx) / c.fx;
+        const float b = ((float)py - c.cy) / c.fy;
+        const float nr = sqrtf((a * a + b * b) + 1.0f);
+        const float rcx = a / nr, rcy = b / nr, rcz = 1.0f / nr;
+        const float dx = (c.Ri[0] * rcx + c.Ri[1] * rcy) + c.Ri[2] * rcz;
+        const float dy = (c.Ri[3] * rcx + c.Ri[4] * rcy) + c.Ri[5] * rcz;
+        const float dz = (c.Ri[6] * rcx + c.Ri[7] * rcy) + c.Ri[8] * rcz;
+        float tt = (zmin * nr) * inv_vs;
+        const float t_end = (zmax * nr) * inv_vs;
+        int state = M_COARSE;
+        float F = 1.0f;
+        int steps = 0;
+        while (tt < t_end && steps < kMaxRaySteps) {
+            ++steps;
+            const float P0 = ox + tt * dx, P1 = oy + tt * dy, P2 = oz + tt * dz;
+            const bool alloc = m_allocated(L, ns, P0, P1, P2);
+            if (state == M_COARSE) {
+                if (!alloc) {
+                    tt += 8.0f;
+                } else {
+                    tt -= 8.0f;
+                    state = M_FINE;
+                }
+            } else if (!alloc) {
+                state = M_FINE;
+                tt += mu_v;
+            } else {
+                F = m_field(L, ns, P0, P1, P2);
+                if (state == M_FINE) {
+                    state = (F < 0.0f) ? M_WRONG_SIDE : M_SURFACE;
+                } else if (state == M_SURFACE) {
+                    if (F < 0.0f) {
+                        state = M_BEHIND;
+                        break;
+                    }
+                    const float s = F * mu_v;
+                    tt += (s > 1.0f) ? s : 1.0f;
+                } else {
+                    if (F >= 0.0f) {
+                        state = M_SURFACE;
+                    } else {
+                        const float s = -F * mu_v;
+                        tt += (s > 1.0f) ? s : 1.0f;
+                    }
+                }
+            }
+        }
+        if (state == M_BEHIND) {
+            tt += F * mu_v;
+            float P0 = ox + tt * dx, P1 = oy + tt * dy, P2 = oz + tt * dz;
+            F = m_field(L, ns, P0, P1, P2);
+            tt += F * mu_v;
+            P0 = ox + tt * dx;
+            P1 = oy + tt * dy;
+            P2 = oz + tt * dz;
+            out_p = make_float4(P0 * voxel, P1 * voxel, P2 * voxel, 1.0f);
+            const float gx = (m_field(L, ns, P0 + 1.0f, P1, P2) - m_field(L, ns, P0 - 1.0f, P1, P2)) * 0.5f;
+            const float gy = (m_field(L, ns, P0, P1 + 1.0f, P2) - m_field(L, ns, P0, P1 - 1.0f, P2)) * 0.5f;
+            const float gz = (m_field(L, ns, P0, P1, P2 + 1.0f) - m_field(L, ns, P0, P1, P2 - 1.0f)) * 0.5f;
+            const float gn = sqrtf((gx * gx + gy * gy) + gz * gz);
+            if (gn > 0.0f) out_n = make_float4(gx / gn, gy / gn, gz / gn, 1.0f);
+        }
+    }
+    if (inside) {
+        const size_t p = (size_t)py * W + px;
+        V.pts[p] = out_p;
+        V.nrm[p] = out_n;
+        if (out_p.w == 1.0f) atomicAdd(&L.hits, 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && L.hits) t.acc_hits[g] += L.hits;
+}
+
+// search range of one view written as an image (parity of the range)
+template <int TW, int TH>
+__global__ __launch_bounds__(TW *TH) void k_m_range_write(const MSub *subs, const MFrame *f, MTiles t, int vi,
+                                                          float *zmin_out, float *zmax_out)
+{
+    constexpr int NT = TW * TH;
+    __shared__ MTileLds<NT> L;
+    const MView &V = f->view[vi];
+    const int g = V.tile_base + (int)blockIdx.x;
+    const int tile = (int)blockIdx.x;
+    const int q = (int)threadIdx.x >> 6, i = (int)threadIdx.x & 63;
+    const int px = (tile % V.ntx) * TW + (q % (TW / 8)) * 8 + (i & 7);
+    const int py = (tile / V.ntx) * TH + (q / (TW / 8)) * 8 + (i >> 3);
+    float zmin, zmax;
+    m_tile_setup<NT>(subs, t, (uint32_t)g, px, py, zmin, zmax, L);
+    if (px >= V.cam.W || py >= V.cam.H) return;
+    zmin_out[(size_t)py * V.cam.W + px] = zmin;
+    zmax_out[(size_t)py * V.cam.W + px] = zmax;
+}
+
+// ============================================================================
+// launchers
+// ============================================================================
+hipError_t launch_m_alloc(const Vol *vols, const MFrame *f, int w, int h, hipStream_t s)
+{
+    const int npix = w * h;
+    hipLaunchKernelGGL(k_m_alloc, dim3((npix + 255) / 256, kMaxSel), dim3(256), 0, s, vols, f);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    hipLaunchKernelGGL(k_m_insert, dim3(128, kMaxSel), dim3(256), 0, s, vols, f);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    hipLaunchKernelGGL(k_m_visible, dim3(256, kMaxSel), dim3(256), 0, s, vols, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_m_integrate(const Vol *vols, const MFrame *f, int nt, int grid, bool dry, hipStream_t s)
+{
+    if (grid < 1) grid = 1;
+    if (grid > kIntegrateGrid) grid = kIntegrateGrid;
+    const dim3 g(grid, kMaxSel);
+    switch (nt) {
+    case 64: hipLaunchKernelGGL(k_m_integrate<64>, g, dim3(64), 0, s, vols, f, dry ? 1 : 0); break;
+    case 128: hipLaunchKernelGGL(k_m_integrate<128>, g, dim3(128), 0, s, vols, f, dry ? 1 : 0); break;
+    case 512: hipLaunchKernelGGL(k_m_integrate<512>, g, dim3(512), 0, s, vols, f, dry ? 1 : 0); break;
+    default: hipLaunchKernelGGL(k_m_integrate<256>, g, dim3(256), 0, s, vols, f, dry ? 1 : 0); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_m_bin(const MSub *subs, const MFrame *f, const MTiles &t, int n_views, int grid, float voxel,
+                        hipStream_t s)
+{
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_m_bin<false>, dim3(grid, n_views), dim3(256), 0, s, subs, f, t, voxel);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    hipLaunchKernelGGL(k_m_scan, dim3(1), dim3(1024), 0, s, t);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    hipLaunchKernelGGL(k_m_bin<true>, dim3(grid, n_views), dim3(256), 0, s, subs, f, t, voxel);
+    return hipGetLastError();
+}
+
+hipError_t launch_m_raycast(const MSub *subs, const MFrame *f, const MTiles &t, float voxel, float mu, int tw, int th,
+                            hipStream_t s)
+{
+    const dim3 g(t.n_tiles);
+    if (tw == 32 && th == 8)
+        hipLaunchKernelGGL((k_m_raycast<32, 8>), g, dim3(256), 0, s, subs, f, t, voxel, mu);
+    else if (tw == 8 && th == 8)
+        hipLaunchKernelGGL((k_m_raycast<8, 8>), g, dim3(64), 0, s, subs, f, t, voxel, mu);
+    else if (tw == 16 && th == 8)
+        hipLaunchKernelGGL((k_m_raycast<16, 8>), g, dim3(128), 0, s, subs, f, t, voxel, mu);
+    else if (tw == 16 && th == 16)
+        hipLaunchKernelGGL((k_m_raycast<16, 16>), g, dim3(256), 0, s, subs, f, t, voxel, mu);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_m_range_write(const MSub *subs, const MFrame *f, const MTiles &t, int vi, int n_tiles_view,
+                                float *zmin, float *zmax, int tw, int th, hipStream_t s)
+{
+    const dim3 g(n_tiles_view);
+    if (tw == 32 && th == 8)
+        hipLaunchKernelGGL((k_m_range_write<32, 8>), g, dim3(256), 0, s, subs, f, t, vi, zmin, zmax);
+    else if (tw == 8 && th == 8)
+        hipLaunchKernelGGL((k_m_range_write<8, 8>), g, dim3(64), 0, s, subs, f, t, vi, zmin, zmax);
+    else if (tw == 16 && th == 8)
+        hipLaunchKernelGGL((k_m_range_write<16, 8>), g, dim3(128), 0, s, subs, f, t, vi, zmin, zmax);
+    else if (tw == 16 && th == 16)
+        hipLaunchKernelGGL((k_m_range_write<16, 16>), g, dim3(256), 0, s, subs, f, t, vi, zmin, zmax);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_m_clear(const MTiles &t, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_m_clear, dim3((t.n_tiles + 255) / 256 + 1), dim3(256), 0, s, t);
+    return hipGetLastError();
+}
+
+}  // namespace tsdf

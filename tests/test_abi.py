@@ -49,3 +49,34 @@ def test_workspace_size_and_validation():
                              ctypes.byref(ctx)) == T.TF_E_INVAL
     assert T.lib().tf_integrate(None, None, 0, None, None) == T.TF_E_INVAL
     assert T.lib().tf_status_string(T.TF_E_ORDER) == b"call order violated"
+
+
+def test_multi_workspace_size_and_validation():
+    import paper_1708_00783_amd as T
+    from synth import configs
+    p = T.make_params(configs.C1_VOLUME, 160, 120)
+    L = T.lib()
+    one = T.tf_workspace_bytes(p)
+    n3 = L.tf_multi_workspace_bytes(ctypes.byref(p), 3, 200, 150, 1 << 16)
+    # three submap workspaces, their block lists and the bins
+    assert 3 * one + 3 * 16 * p.n_blocks + (1 << 16) * 32 <= n3 < 3 * one + 3 * 16 * p.n_blocks + (1 << 16) * 32 + (8 << 20)
+    assert L.tf_multi_workspace_bytes(ctypes.byref(p), 0, 200, 150, 1 << 16) == 0
+    assert L.tf_multi_workspace_bytes(ctypes.byref(p), 65, 200, 150, 1 << 16) == 0
+    assert L.tf_multi_workspace_bytes(ctypes.byref(p), 3, 200, 150, 0) == 0
+    sw = T.make_params(configs.C1_VOLUME, 160, 120, swap_transfer_blocks=64)
+    assert L.tf_multi_workspace_bytes(ctypes.byref(sw), 3, 200, 150, 1 << 16) == 0   # submaps never swap
+    assert L.tf_multi_host_bytes() >= 2 * 24 * 1024
+    poses = (ctypes.c_float * 48)(*([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1] * 3))
+    m = ctypes.c_void_p()
+    hb = L.tf_multi_host_bytes()
+    # rejected on the host before any device work
+    assert L.tf_multi_create(ctypes.byref(p), 3, poses, 200, 150, 1 << 16, ctypes.c_void_p(256), 10,
+                             ctypes.c_void_p(256), hb, None, ctypes.byref(m)) == T.TF_E_SPACE
+    assert L.tf_multi_create(ctypes.byref(p), 3, None, 200, 150, 1 << 16, ctypes.c_void_p(256), n3,
+                             ctypes.c_void_p(256), hb, None, ctypes.byref(m)) == T.TF_E_INVAL
+    assert L.tf_multi_create(ctypes.byref(p), 3, poses, 200, 150, 1 << 16, ctypes.c_void_p(256), n3,
+                             ctypes.c_void_p(256), 16, None, ctypes.byref(m)) == T.TF_E_SPACE
+    cfg = T.tf_multi_config(24, 8, 256, 256, 256)
+    assert L.tf_multi_set_config(None, ctypes.byref(cfg)) == T.TF_E_INVAL
+    assert L.tf_multi_integrate(None, None, 0, None, None, None, 0, None) == T.TF_E_INVAL
+    assert L.tf_multi_raycast(None, None, 0, None) == T.TF_E_INVAL
