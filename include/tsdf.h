@@ -262,6 +262,7 @@ typedef struct {
     uint64_t total_integrated_blocks;   /* sum over submaps: blocks visited by integrations */
     uint64_t total_written_columns;     /* sum over submaps: 8-voxel columns written back */
     uint64_t total_bin_entries;         /* (block, tile) pairs binned by all raycasts */
+    uint64_t total_block_views;         /* (block, view) pairs binned by all raycasts */
     uint64_t total_rays_hit;            /* pixels with a hit over all raycasts and views */
     uint64_t raycast_calls;
 } tf_multi_stats;

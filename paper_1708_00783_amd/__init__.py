@@ -90,7 +90,7 @@ class tf_multi_config(ctypes.Structure):
 class tf_multi_stats(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("n_submaps", ctypes.c_uint32)] + [(n, ctypes.c_uint64) for n in (
         "allocated_blocks", "total_integrated_blocks", "total_written_columns", "total_bin_entries",
-        "total_rays_hit", "raycast_calls")]
+        "total_block_views", "total_rays_hit", "raycast_calls")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

@@ -185,6 +185,7 @@ struct alignas(256) MCtrl {
     uint32_t flags;                 // TF_FLAG_BIN_OVERFLOW
     uint32_t pad;
     unsigned long long tot_bin;     // bin entries (block x tile) of all raycasts
+    unsigned long long tot_blkview; // (block, view) pairs binned by all raycasts
     unsigned long long n_raycast;   // raycast launches
 };
 

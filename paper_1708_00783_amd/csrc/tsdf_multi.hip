@@ -87,8 +87,14 @@ __global__ __launch_bounds__(256) void k_m_bin(const MSub *subs, const MFrame *f
             const int4 b = al[i];
             const int bx = (int16_t)(b.x & 0xffff), by = (int16_t)((uint32_t)b.x >> 16), bz = b.y;
             Rec ex;
-            if (!cube_record(M, vc, voxel, 8 * bx - kExpand, 8 * by - kExpand, 8 * bz - kExpand, 8 + 2 * kExpand, ex))
-                continue;
+            const bool hit =
+                cube_record(M, vc, voxel, 8 * bx - kExpand, 8 * by - kExpand, 8 * bz - kExpand, 8 + 2 * kExpand, ex);
+            if (!FILL) {
+                const unsigned long long m = __ballot(hit);
+                if (lane_id() == (uint32_t)(__ffsll((long long)m) - 1))
+                    atomicAdd(&t.mc->tot_blkview, (unsigned long long)__popcll(m));
+            }
+            if (!hit) continue;
             const int tx0 = ex.x0 / tw, tx1 = ex.x1 / tw, ty0 = ex.y0 / th, ty1 = ex.y1 / th;
             if (!FILL) {
                 for (int ty = ty0; ty <= ty1; ++ty)

@@ -556,6 +556,7 @@ int tf_multi_get_stats(tf_multi *m, tf_multi_stats *out, tf_stream stream)
     if (e != hipSuccess) return TF_E_HIP;
     out->flags |= mc.flags;
     out->total_bin_entries = mc.tot_bin;
+    out->total_block_views = mc.tot_blkview;
     out->raycast_calls = mc.n_raycast;
     for (unsigned long long h : hits) out->total_rays_hit += h;
     return TF_OK;

@@ -5,6 +5,9 @@ C2 full     640x480 uint16 mm depth, 4x4x3 m room with 20 primitives, 300
             poses, Kinect-like noise.
 C3 large    640x480 uint16 mm depth, 12x12x3 m layout of 3x3 rooms with doors
             and 200 primitives, 1500 poses, same noise (host swapping).
+C4 batched  64 rigid submaps over the C3 layout with log-uniform block counts,
+            frames of the C3 walk fused into the 4-12 submaps they overlap,
+            8 views of mixed resolution per frame.
 Seeds: numpy PCG64, seed = 1000 * config + index.
 """
 from __future__ import annotations
@@ -254,3 +257,131 @@ def c3_frame(k: int, seed_index: int = 0, noise: bool = True, intr: Intrinsics =
     if noise:
         z = kinect_noise(z, rng_for(3, 100000 + 1000 * seed_index + k))
     return to_mm_u16(z)
+
+
+# ---- C4: batched rigid submaps ------------------------------------------------------
+C4_VOLUME = VolumeParams(0.005, 0.02, 100, 1 << 18, 1 << 16, 1 << 17)
+C4_N_SUBMAPS = 64
+C4_BLOCKS = (2000, 60000)                  # log-uniform target block counts
+C4_PREFILL_INTR = Intrinsics(262.5, 262.5, 159.5, 119.5, 320, 240)
+C4_VIEW_SIZES = ((320, 240), (320, 240), (640, 480), (640, 480), (960, 540), (960, 540), (1280, 720), (1280, 720))
+C4_N_FRAMES = 300                         # every 5th pose of the C3 walk
+C4_MAX_SEL, C4_MIN_SEL = 12, 4
+
+
+def random_rotation(rng) -> np.ndarray:
+    """uniform rotation from a normalised 4-d Gaussian quaternion"""
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+@dataclasses.dataclass(frozen=True)
+class Submap:
+    pose: np.ndarray       # 4x4 float32, world -> submap
+    centre: tuple          # region centre (world, m)
+    radius: float          # region radius (m)
+    target: int            # block count the prefill aims at
+
+
+@functools.lru_cache(maxsize=2)
+def c4_submaps(seed_index: int = 0) -> tuple:
+    """64 submaps: a uniform random rotation and a translation within the
+    layout for the pose, a region (ball) inside the layout, and a log-uniform
+    block-count target."""
+    rng = rng_for(4, seed_index)
+    lo, hi = math.log(C4_BLOCKS[0]), math.log(C4_BLOCKS[1])
+    out = []
+    for _ in range(C4_N_SUBMAPS):
+        R = random_rotation(rng)
+        origin = rng.uniform([0.0, 0.0, 0.0], [12.0, 12.0, 3.0])
+        P = np.eye(4)
+        P[:3, :3] = R
+        P[:3, 3] = -R @ origin                # X_submap = R (X_world - origin)
+        centre = tuple(rng.uniform([0.6, 0.6, 0.8], [11.4, 11.4, 2.2]))
+        radius = float(rng.uniform(1.0, 2.0))
+        target = int(round(math.exp(rng.uniform(lo, hi))))
+        out.append(Submap(P.astype(np.float32), centre, radius, target))
+    return tuple(out)
+
+
+def c4_prefill_pose(i: int, j: int, seed_index: int = 0) -> np.ndarray:
+    """j-th prefill viewpoint of submap i: a point of its region (kept inside
+    the layout), a random heading, a slight random pitch"""
+    sm = c4_submaps(seed_index)[i]
+    rng = rng_for(4, 10000 + 1000 * i + j)
+    c = np.asarray(sm.centre)
+    while True:
+        d = rng.uniform(-1.0, 1.0, size=3)
+        if np.dot(d, d) <= 1.0:
+            break
+    eye = np.clip(c + sm.radius * d, [0.25, 0.25, 0.4], [11.75, 11.75, 2.6])
+    yaw = rng.uniform(0.0, 2 * math.pi)
+    pitch = rng.uniform(-0.45, 0.2)
+    fwd = np.array([math.cos(yaw) * math.cos(pitch), math.sin(yaw) * math.cos(pitch), math.sin(pitch)])
+    return look_at(eye, eye + fwd)
+
+
+def c4_prefill_frame(i: int, j: int, seed_index: int = 0) -> np.ndarray:
+    """noiseless float32 depth (m) of prefill viewpoint j of submap i"""
+    scene, _ = c3_layout(seed_index)
+    return render_depth(scene, c4_prefill_pose(i, j, seed_index), C4_PREFILL_INTR).astype(np.float32)
+
+
+def c4_poses(seed_index: int = 0) -> list:
+    return [np.asarray(P, np.float32) for P in c3_poses(1500, seed_index)[::5]]
+
+
+def c4_frame(k: int, seed_index: int = 0) -> np.ndarray:
+    """640x480 uint16 mm depth with Kinect-like noise at the k-th C4 pose"""
+    scene, _ = c3_layout(seed_index)
+    P = c4_poses(seed_index)[k % C4_N_FRAMES]
+    z = kinect_noise(render_depth(scene, P, KINECT_INTR), rng_for(4, 200000 + 1000 * seed_index + k))
+    return to_mm_u16(z)
+
+
+def c4_select(pose_w2c, seed_index: int = 0, intr: Intrinsics = KINECT_INTR, near: float = 0.3,
+              far: float = 4.0) -> list:
+    """Submaps whose region meets the viewing frustum [near, far], nearest
+    first, at most 12; fewer than 4 are topped up with the nearest regions."""
+    subs = c4_submaps(seed_index)
+    M = np.asarray(pose_w2c, np.float64)
+    planes = []
+    for n in ((intr.fx, 0.0, intr.cx), (-intr.fx, 0.0, intr.width - 1 - intr.cx),
+              (0.0, intr.fy, intr.cy), (0.0, -intr.fy, intr.height - 1 - intr.cy)):
+        n = np.asarray(n)
+        planes.append(n / np.linalg.norm(n))
+    eye = -M[:3, :3].T @ M[:3, 3]
+    meet, dist = [], []
+    for i, sm in enumerate(subs):
+        c = M[:3, :3] @ np.asarray(sm.centre) + M[:3, 3]
+        r = sm.radius
+        ok = c[2] + r >= near and c[2] - r <= far and all(np.dot(n, c) >= -r for n in planes)
+        d = float(np.linalg.norm(np.asarray(sm.centre) - eye))
+        dist.append(d)
+        if ok:
+            meet.append((d, i))
+    meet.sort()
+    sel = [i for _, i in meet[:C4_MAX_SEL]]
+    if len(sel) < C4_MIN_SEL:
+        for i in np.argsort(dist):
+            if int(i) not in sel:
+                sel.append(int(i))
+            if len(sel) == C4_MIN_SEL:
+                break
+    return sel
+
+
+def c4_views(k: int, seed_index: int = 0) -> list:
+    """the 8 views of frame k: (intrinsics, pose); view j looks from the walk
+    pose 37 j frames ahead, at its own size (focal length scaled with width)"""
+    poses = c4_poses(seed_index)
+    out = []
+    for j, (W, H) in enumerate(C4_VIEW_SIZES):
+        f = 525.0 * W / 640.0
+        intr = Intrinsics(f, f, (W - 1) / 2.0, (H - 1) / 2.0, W, H)
+        out.append((intr, poses[(k + 37 * j) % C4_N_FRAMES]))
+    return out
