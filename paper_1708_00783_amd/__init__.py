@@ -36,6 +36,9 @@ EXPORTS = (
     "tf_multi_submap", "tf_multi_set_config", "tf_multi_get_config", "tf_multi_integrate",
     "tf_multi_raycast", "tf_multi_frame", "tf_multi_range_image", "tf_multi_autotune",
     "tf_multi_get_stats",
+    # include/tsdf_nn.h
+    "tf_nn_param_count", "tf_nn_workspace_bytes", "tf_nn_create", "tf_nn_destroy", "tf_nn_set_params",
+    "tf_nn_get_params", "tf_nn_forward", "tf_nn_backward", "tf_nn_adam_step", "tf_nn_tensor",
 )
 
 
@@ -155,6 +158,19 @@ def lib():
                                                  P(ctypes.c_uint32), ctypes.c_uint32, P(tf_view), ctypes.c_uint32,
                                                  ctypes.c_int, P(tf_multi_config), P(ctypes.c_float), _VP]),
             "tf_multi_get_stats": (ctypes.c_int, [_VP, P(tf_multi_stats), _VP]),
+            "tf_nn_param_count": (ctypes.c_uint32, []),
+            "tf_nn_workspace_bytes": (ctypes.c_size_t, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                                        ctypes.c_int]),
+            "tf_nn_create": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, _VP,
+                                            ctypes.c_size_t, P(_VP)]),
+            "tf_nn_destroy": (ctypes.c_int, [_VP]),
+            "tf_nn_set_params": (ctypes.c_int, [_VP, _VP, _VP]),
+            "tf_nn_get_params": (ctypes.c_int, [_VP, _VP, _VP]),
+            "tf_nn_forward": (ctypes.c_int, [_VP, _VP, ctypes.c_int, ctypes.c_uint32, _VP, _VP]),
+            "tf_nn_backward": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+            "tf_nn_adam_step": (ctypes.c_int, [_VP, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                               ctypes.c_float, _VP]),
+            "tf_nn_tensor": (ctypes.c_int, [_VP, ctypes.c_int, P(_VP), P(ctypes.c_int32)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -519,3 +535,114 @@ class MultiMap:
         st = tf_multi_stats()
         check(lib().tf_multi_get_stats(self.h, ctypes.byref(st), _stream_ptr(stream)), "tf_multi_get_stats")
         return st.as_dict()
+
+
+# ---- learned depth prefilter ------------------------------------------------------
+
+NN_T = dict(input=0, e1=1, e2=2, e3=3, e4=4, d3=5, d2=6, d1=7, grad_e1=8, grad_e2=9, grad_e3=10, grad_e4=11,
+            grad_d3=12, grad_d2=13, grad_d1=14, out=15, ddelta=16, depth=17, grads=18, params=19)
+NN_LAYERS = (("e1", 2, 32), ("e2", 32, 64), ("e3", 64, 64), ("e4", 64, 128), ("d3", 128, 64), ("d2", 64, 64),
+             ("d1", 64, 32), ("head", 32, 1))
+
+
+def nn_flatten(P: dict) -> np.ndarray:
+    """parameter dict {name.w: (cout, 3, 3, cin), name.b: (cout,)} -> fp32 vector"""
+    parts = []
+    for name, _, _ in NN_LAYERS:
+        parts += [np.asarray(P[name + ".w"], np.float32).reshape(-1), np.asarray(P[name + ".b"], np.float32)]
+    return np.concatenate(parts)
+
+
+def nn_unflatten(v) -> dict:
+    v = np.asarray(v, np.float32)
+    P, o = {}, 0
+    for name, cin, cout in NN_LAYERS:
+        n = cout * 9 * cin
+        P[name + ".w"] = v[o:o + n].reshape(cout, 3, 3, cin)
+        o += n
+        P[name + ".b"] = v[o:o + cout]
+        o += cout
+    assert o == v.size
+    return P
+
+
+class Denoiser:
+    """The learned depth prefilter on the current HIP device, for batches of
+    up to max_batch frames of height x width (multiples of 8)."""
+
+    def __init__(self, max_batch, height, width, training=False):
+        import torch
+        self.H, self.W, self.B = height, width, max_batch
+        nbytes = int(lib().tf_nn_workspace_bytes(max_batch, height, width, 1 if training else 0))
+        if nbytes == 0:
+            raise TsdfError("invalid denoiser shape")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        h = _VP()
+        check(lib().tf_nn_create(max_batch, height, width, 1 if training else 0,
+                                 ctypes.c_void_p(self.workspace.data_ptr()), nbytes, ctypes.byref(h)), "tf_nn_create")
+        self.h = h
+        self.n_params = int(lib().tf_nn_param_count())
+        self.loss = torch.zeros(2, dtype=torch.float32, device="cuda")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tf_nn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params, stream=None):
+        import torch
+        p = params if isinstance(params, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(params, np.float32))
+        p = p.to(device="cuda", dtype=torch.float32).contiguous()
+        assert p.numel() == self.n_params
+        check(lib().tf_nn_set_params(self.h, ctypes.c_void_p(p.data_ptr()), _stream_ptr(stream)), "tf_nn_set_params")
+        self._params_src = p      # the copy is asynchronous: keep the source alive
+
+    def get_params(self, stream=None):
+        import torch
+        p = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        check(lib().tf_nn_get_params(self.h, ctypes.c_void_p(p.data_ptr()), _stream_ptr(stream)), "tf_nn_get_params")
+        return p
+
+    def forward(self, depth, out=None, stream=None):
+        """depth: (N, H, W) uint16 mm or float32 m on the device -> float32 m"""
+        import torch
+        fmt = TF_DEPTH_U16_MM if depth.dtype.itemsize == 2 else TF_DEPTH_F32_M
+        n = depth.shape[0] if depth.dim() == 3 else 1
+        if out is None:
+            out = torch.empty((n, self.H, self.W), dtype=torch.float32, device="cuda")
+        check(lib().tf_nn_forward(self.h, ctypes.c_void_p(depth.data_ptr()), fmt, n, ctypes.c_void_p(out.data_ptr()),
+                                  _stream_ptr(stream)), "tf_nn_forward")
+        return out
+
+    def backward(self, target, stream=None):
+        """loss against target (N, H, W) float32 m; returns the (mean, count) device tensor"""
+        check(lib().tf_nn_backward(self.h, ctypes.c_void_p(target.data_ptr()), ctypes.c_void_p(self.loss.data_ptr()),
+                                   _stream_ptr(stream)), "tf_nn_backward")
+        return self.loss
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        check(lib().tf_nn_adam_step(self.h, lr, beta1, beta2, eps, _stream_ptr(stream)), "tf_nn_adam_step")
+
+    def tensor(self, name):
+        """a view of an internal tensor: bf16 activations/gradients as int16 bit patterns, else float32"""
+        import torch
+        ptr = _VP()
+        dims = (ctypes.c_int32 * 4)()
+        check(lib().tf_nn_tensor(self.h, NN_T[name], ctypes.byref(ptr), dims), "tf_nn_tensor")
+        off = ptr.value - self.workspace.data_ptr()
+        shape = tuple(int(d) for d in dims)
+        bf = NN_T[name] <= 14
+        n = int(np.prod(shape)) * (2 if bf else 4)
+        return self.workspace[off:off + n].view(torch.int16 if bf else torch.float32).reshape(shape)
+
+
+def bf16_bits_to_float(t):
+    """int16 bf16 bit patterns (torch) -> float32 numpy"""
+    a = t.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return a.view(np.float32)

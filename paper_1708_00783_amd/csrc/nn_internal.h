@@ -1,0 +1,71 @@
+// nn_internal.h -- layer table, tensor layout and launchers of the learned
+// depth prefilter (a small 3x3 convolutional encoder-decoder in front of
+// integration).  Internal to libtsdf.
+//
+// Tensors are NHWC bfloat16 (stored as uint16 bit patterns); the network
+// input has its 2 channels (depth / 4 m, valid mask) padded to 8.  Conv
+// weights are kept as fp32 master copies in the parameter vector (per layer
+// W[cout][3][3][cin] then b[cout], layers in forward order) and packed to
+// bf16 GEMM operands: G[cout][KP] with k = tap * CINP + ci (KP = 9 CINP
+// rounded up to 32) for the forward pass, T[cin][9 cout] with k = tap * cout
+// + co for the backward-data pass.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tsdf {
+namespace nn {
+
+constexpr int kLayers = 8;              // e1 e2 e3 e4 d3 d2 d1 head
+constexpr float kDepthScale = 4.0f;     // metres
+
+struct LayerDesc {
+    int cin, cinp, cout, stride, up;    // up: the conv reads up2(source)
+    int src;                            // activation index of the source (-1 = network input)
+    int skip;                           // activation index added before the relu (-1 none)
+    int w_off, b_off;                   // fp32 parameter offsets
+    int kp;                             // forward GEMM K (padded)
+    int g_off, t_off;                   // bf16 packed-weight offsets (elements)
+    int scale;                          // output resolution divisor (1, 2, 4, 8)
+};
+
+// activation indices: 0 = x (input), 1..7 = e1 e2 e3 e4 d3 d2 d1
+constexpr int kActs = 8;
+
+struct Net {
+    LayerDesc L[kLayers];
+    int n_params;
+    int g_elems, t_elems;
+};
+
+// layer table (host and device agree; computed once on the host)
+Net make_net();
+
+// activation buffer of a (N, H, W) problem: channels and scale per index
+inline int act_channels(int a) { static const int c[kActs] = {8, 32, 64, 64, 128, 64, 64, 32}; return c[a]; }
+inline int act_scale(int a) { static const int s[kActs] = {1, 1, 2, 4, 8, 4, 2, 1}; return s[a]; }
+
+hipError_t launch_make_input(const void *depth, int fmt, int n_pix, uint16_t *x, float *dm, hipStream_t s);
+hipError_t launch_pack(const Net &net, const float *params, uint16_t *g, uint16_t *t, hipStream_t s);
+hipError_t launch_conv_fwd(int layer, const uint16_t *in, int Hs, int Ws, const uint16_t *g, const float *bias,
+                           const uint16_t *skip, uint16_t *out, int N, int Ho, int Wo, hipStream_t s);
+hipError_t launch_head_fwd(const uint16_t *d1, const float *w, const float *b, const float *dm, float *out, int N,
+                           int H, int W, hipStream_t s);
+hipError_t launch_loss(const float *out, const float *dm, const float *target, int n_pix, float *ddelta,
+                       float *scratch, float *loss, hipStream_t s);
+hipError_t launch_head_bwd(const float *ddelta, const float *w, const uint16_t *d1, uint16_t *g_d1, int N, int H,
+                           int W, hipStream_t s);
+hipError_t launch_head_wgrad(const float *ddelta, const uint16_t *d1, int N, int H, int W, float *partial,
+                             int chunks, float *dw, float *db, hipStream_t s);
+hipError_t launch_conv_bwd_data(int layer, const uint16_t *gpre, int Ho, int Wo, const uint16_t *t,
+                                const uint16_t *skipg, const uint16_t *act, uint16_t *gout, int N, int Hq, int Wq,
+                                hipStream_t s);
+hipError_t launch_conv_wgrad(int layer, const uint16_t *gpre, const uint16_t *in, int Hs, int Ws, int N, int Ho,
+                             int Wo, float *partial, int chunks, float *dw, float *db, hipStream_t s);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t s);
+
+}  // namespace nn
+}  // namespace tsdf

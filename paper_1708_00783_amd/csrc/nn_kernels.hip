@@ -1,0 +1,659 @@
+// nn_kernels.hip -- gfx950 kernels of the learned depth prefilter.
+//
+// The 3x3 convolutions are implicit GEMMs on the bf16 matrix cores
+// (v_mfma_f32_16x16x32_bf16, fp32 accumulation):
+//   k_conv_fwd       M = output pixels, N = cout, K = (tap, ci); the operand
+//                    gather applies the stride and the nearest upsampling of
+//                    the decoder; bias, skip add and relu fused on the way out
+//   k_conv_bwd_data  M = input pixels, N = cin, K = (tap, co) -- stride-2
+//                    taps of the wrong parity read zero, and for an upsampled
+//                    input the four children of a source pixel are summed as
+//                    four more K blocks; skip gradient and relu mask fused
+//   k_conv_wgrad     M = cout, N = cin of one tap, K = pixels of one chunk:
+//                    both operands are staged transposed in LDS; per-chunk
+//                    partial sums are reduced in a fixed order
+// The 32->1 head, the loss, input packing and Adam are plain VALU kernels.
+//
+// MFMA 16x16x32 operand layout (per lane l of the wave): A row l%16, k
+// (l/16)*8 .. +7; B column l%16, same k; D column l%16, rows (l/16)*4 .. +3.
+#include "nn_internal.h"
+#include "tsdf.h"
+
+namespace tsdf {
+namespace nn {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;   // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                      // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ u32x4 ld16(const uint16_t *p)
+{
+    return *(const __attribute__((address_space(1))) u32x4 *)p;
+}
+
+__device__ __forceinline__ bf16x8 as_bf(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+}  // namespace
+
+// ============================================================================
+// input packing: depth -> metres and (d / 4, valid, 0 x 6) bf16
+// ============================================================================
+template <int FMT>
+__global__ __launch_bounds__(256) void k_make_input(const void *depth, int n, uint16_t *x, float *dm)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    float d;
+    if (FMT == TF_DEPTH_U16_MM)
+        d = (float)reinterpret_cast<const uint16_t *>(depth)[p] / 1000.0f;
+    else
+        d = reinterpret_cast<const float *>(depth)[p];
+    if (!(d > 0.0f)) d = 0.0f;
+    dm[p] = d;
+    u32x4 v = {(uint32_t)f2bf(d * 0.25f) | ((uint32_t)(d > 0.0f ? f2bf(1.0f) : 0u) << 16), 0u, 0u, 0u};
+    *reinterpret_cast<u32x4 *>(x + (size_t)p * 8) = v;
+}
+
+// ============================================================================
+// fp32 master weights -> bf16 GEMM operands of one layer
+// ============================================================================
+__global__ __launch_bounds__(256) void k_pack(const float *w, int cin, int cinp, int cout, int kp, uint16_t *g,
+                                              uint16_t *t)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < cout * kp) {
+        const int co = i / kp, k = i % kp, tap = k / cinp, ci = k % cinp;
+        g[i] = (tap < 9 && ci < cin) ? f2bf(w[(co * 9 + tap) * cin + ci]) : (uint16_t)0;
+    }
+    if (t && i < cinp * 9 * cout) {
+        const int ci = i / (9 * cout), k = i % (9 * cout), tap = k / cout, co = k % cout;
+        t[i] = ci < cin ? f2bf(w[(co * 9 + tap) * cin + ci]) : (uint16_t)0;
+    }
+}
+
+// ============================================================================
+// forward 3x3 convolution: each wave computes 32 output pixels x COUT
+// ============================================================================
+template <int CINP, int COUT, int STRIDE, bool UP, bool SKIP>
+__global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, int Ws, const uint16_t *g,
+                                                  const float *bias, const uint16_t *skip, uint16_t *out, int N,
+                                                  int Ho, int Wo)
+{
+    constexpr int KP = ((9 * CINP + 31) / 32) * 32;
+    constexpr int NT = COUT / 16;
+    const int lane = (int)threadIdx.x & 63;
+    const long P = (long)N * Ho * Wo;
+    const long p0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
+    if (p0 >= P) return;
+    const int r = lane & 15, gq = lane >> 4;
+    const int Hc = UP ? 2 * Hs : Hs, Wc = UP ? 2 * Ws : Ws;   // conv input size
+    int pn[2], py[2], px[2];
+    bool pv[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        long p = p0 + t * 16 + r;
+        pv[t] = p < P;
+        if (!pv[t]) p = 0;
+        pn[t] = (int)(p / ((long)Ho * Wo));
+        const int rem = (int)(p - (long)pn[t] * Ho * Wo);
+        py[t] = rem / Wo;
+        px[t] = rem - py[t] * Wo;
+    }
+    f32x4 acc[2][NT];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < KP; k0 += 32) {
+        const int k = k0 + gq * 8;
+        const int tap = k / CINP, ci = k - (k / CINP) * CINP;
+        const int ky = tap / 3, kx = tap - (tap / 3) * 3;
+        bf16x8 a[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int iy = STRIDE * py[t] + ky - 1, ix = STRIDE * px[t] + kx - 1;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (tap < 9 && pv[t] && iy >= 0 && iy < Hc && ix >= 0 && ix < Wc) {
+                const int sy = UP ? (iy >> 1) : iy, sx = UP ? (ix >> 1) : ix;
+                v = ld16(in + (((size_t)pn[t] * Hs + sy) * Ws + sx) * CINP + ci);
+            }
+            a[t] = as_bf(v);
+        }
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const bf16x8 b = as_bf(ld16(g + (size_t)(j * 16 + r) * KP + k));
+            acc[0][j] = mfma(a[0], b, acc[0][j]);
+            acc[1][j] = mfma(a[1], b, acc[1][j]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int co = j * 16 + r;
+            const float bb = bias[co];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long p = p0 + t * 16 + gq * 4 + i;
+                if (p >= P) continue;
+                float v = acc[t][j][i] + bb;
+                if (SKIP) v += bf2f(skip[(size_t)p * COUT + co]);
+                v = v > 0.0f ? v : 0.0f;
+                out[(size_t)p * COUT + co] = f2bf(v);
+            }
+        }
+}
+
+// ============================================================================
+// backward data: gradient at the conv input (or, for an upsampled input, at
+// its source), then + skip gradient, then the source's relu mask
+// ============================================================================
+template <int CIN, int COUT, int STRIDE, bool UPSUM, bool SKIP>
+__global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t *gpre, int Ho, int Wo, const uint16_t *tw,
+                                                       const uint16_t *skipg, const uint16_t *act, uint16_t *gout,
+                                                       int N, int Hq, int Wq)
+{
+    constexpr int K9 = 9 * COUT;
+    constexpr int KT = (UPSUM ? 4 : 1) * K9;
+    constexpr int NT = CIN / 16;
+    const int lane = (int)threadIdx.x & 63;
+    const long P = (long)N * Hq * Wq;
+    const long p0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
+    if (p0 >= P) return;
+    const int r = lane & 15, gq = lane >> 4;
+    int pn[2], py[2], px[2];
+    bool pv[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        long p = p0 + t * 16 + r;
+        pv[t] = p < P;
+        if (!pv[t]) p = 0;
+        pn[t] = (int)(p / ((long)Hq * Wq));
+        const int rem = (int)(p - (long)pn[t] * Hq * Wq);
+        py[t] = rem / Wq;
+        px[t] = rem - py[t] * Wq;
+    }
+    f32x4 acc[2][NT];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < KT; k0 += 32) {
+        const int k = k0 + gq * 8;
+        const int child = k / K9, rem = k - (k / K9) * K9;
+        const int tap = rem / COUT, co = rem - (rem / COUT) * COUT;
+        const int ky = tap / 3, kx = tap - (tap / 3) * 3;
+        bf16x8 a[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            // conv-input pixel, then the output pixel whose tap reads it
+            const int iy = UPSUM ? 2 * py[t] + (child >> 1) : py[t];
+            const int ix = UPSUM ? 2 * px[t] + (child & 1) : px[t];
+            int oy = iy - ky + 1, ox = ix - kx + 1;
+            bool ok = pv[t];
+            if (STRIDE == 2) {
+                ok = ok && !(oy & 1) && !(ox & 1);
+                oy >>= 1;
+                ox >>= 1;
+            }
+            ok = ok && oy >= 0 && oy < Ho && ox >= 0 && ox < Wo;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (ok) v = ld16(gpre + (((size_t)pn[t] * Ho + oy) * Wo + ox) * COUT + co);
+            a[t] = as_bf(v);
+        }
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const bf16x8 b = as_bf(ld16(tw + (size_t)(j * 16 + r) * K9 + rem));
+            acc[0][j] = mfma(a[0], b, acc[0][j]);
+            acc[1][j] = mfma(a[1], b, acc[1][j]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int c = j * 16 + r;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long p = p0 + t * 16 + gq * 4 + i;
+                if (p >= P) continue;
+                float v = acc[t][j][i];
+                if (SKIP) v += bf2f(skipg[(size_t)p * CIN + c]);
+                if (!(bf2f(act[(size_t)p * CIN + c]) > 0.0f)) v = 0.0f;
+                gout[(size_t)p * CIN + c] = f2bf(v);
+            }
+        }
+}
+
+// ============================================================================
+// weight gradient of one tap (blockIdx.x) over one pixel chunk (blockIdx.y):
+// partial[chunk][co][tap][ci] = sum_p gpre[p][co] * in_tap(p)[ci]; the bias
+// gradient partial[chunk][co] comes from the tap-0 workgroups
+// ============================================================================
+template <int CINP, int COUT, int STRIDE, bool UP>
+__global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *gpre, const uint16_t *in, int Hs, int Ws, int N,
+                                                    int Ho, int Wo, float *partial, float *partial_b, int chunk_pix)
+{
+    constexpr int CT = CINP < 16 ? 16 : CINP;
+    constexpr int MT = COUT / 16, NTT = CT / 16, TILES = MT * NTT, TPW = (TILES + 3) / 4;
+    constexpr int LD = 40;   // LDS row pitch in bf16 elements (80 bytes: 16-byte aligned rows)
+    __shared__ uint16_t gT[COUT][LD];
+    __shared__ uint16_t iT[CT][LD];
+    __shared__ float bsum[COUT];
+    const int tap = (int)blockIdx.x, chunk = (int)blockIdx.y;
+    const int ky = tap / 3, kx = tap - (tap / 3) * 3;
+    const long P = (long)N * Ho * Wo;
+    const long c0 = (long)chunk * chunk_pix;
+    const long c1 = c0 + chunk_pix < P ? c0 + chunk_pix : P;
+    const int w = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63, r = lane & 15, gq = lane >> 4;
+    const int Hc = UP ? 2 * Hs : Hs, Wc = UP ? 2 * Ws : Ws;
+    f32x4 acc[TPW];
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bpart = 0.0f;   // bias gradient: thread threadIdx.x < COUT owns channel threadIdx.x
+    for (long pb = c0; pb < c1; pb += 32) {
+        for (int v = threadIdx.x; v < 32 * (COUT / 8); v += 256) {
+            const int pi = v / (COUT / 8), cv = (v - pi * (COUT / 8)) * 8;
+            const long p = pb + pi;
+            u32x4 val = {0u, 0u, 0u, 0u};
+            if (p < c1) val = ld16(gpre + (size_t)p * COUT + cv);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) gT[cv + e][pi] = (uint16_t)(val[e >> 1] >> (16 * (e & 1)));
+        }
+        for (int v = threadIdx.x; v < 32 * (CT / 8); v += 256) {
+            const int pi = v / (CT / 8), cv = (v - pi * (CT / 8)) * 8;
+            const long p = pb + pi;
+            u32x4 val = {0u, 0u, 0u, 0u};
+            if (p < c1 && cv < CINP) {
+                const int n = (int)(p / ((long)Ho * Wo));
+                const int rem = (int)(p - (long)n * Ho * Wo);
+                const int oy = rem / Wo, ox = rem - (rem / Wo) * Wo;
+                const int iy = STRIDE * oy + ky - 1, ix = STRIDE * ox + kx - 1;
+                if (iy >= 0 && iy < Hc && ix >= 0 && ix < Wc) {
+                    const int sy = UP ? (iy >> 1) : iy, sx = UP ? (ix >> 1) : ix;
+                    val = ld16(in + (((size_t)n * Hs + sy) * Ws + sx) * CINP + cv);
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) iT[cv + e][pi] = (uint16_t)(val[e >> 1] >> (16 * (e & 1)));
+        }
+        __syncthreads();
+        if (tap == 0 && (int)threadIdx.x < COUT)
+            for (int k = 0; k < 32; ++k) bpart += bf2f(gT[threadIdx.x][k]);
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) {
+            const int tile = w * TPW + j;
+            if (tile < TILES) {
+                const int mt = tile / NTT, nt = tile - (tile / NTT) * NTT;
+                const bf16x8 a = as_bf(*reinterpret_cast<const u32x4 *>(&gT[mt * 16 + r][gq * 8]));
+                const bf16x8 b = as_bf(*reinterpret_cast<const u32x4 *>(&iT[nt * 16 + r][gq * 8]));
+                acc[j] = mfma(a, b, acc[j]);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+        const int tile = w * TPW + j;
+        if (tile >= TILES) continue;
+        const int mt = tile / NTT, nt = tile - (tile / NTT) * NTT;
+        const int ci = nt * 16 + r;
+        if (ci >= CINP) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int co = mt * 16 + gq * 4 + i;
+            partial[(((size_t)chunk * COUT + co) * 9 + tap) * CINP + ci] = acc[j][i];
+        }
+    }
+    if (tap == 0 && (int)threadIdx.x < COUT) {
+        bsum[threadIdx.x] = bpart;
+        partial_b[(size_t)chunk * COUT + threadIdx.x] = bpart;
+    }
+}
+
+// fixed-order sum of the chunk partials into the fp32 gradient vector
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float *partial, const float *partial_b, int chunks,
+                                                      int cout, int cin, int cinp, float *dw, float *db)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int nw = cout * 9 * cin;
+    if (i < nw) {
+        const int co = i / (9 * cin), rem = i - co * 9 * cin, tap = rem / cin, ci = rem - (rem / cin) * cin;
+        float s = 0.0f;
+        for (int c = 0; c < chunks; ++c) s += partial[(((size_t)c * cout + co) * 9 + tap) * cinp + ci];
+        dw[i] = s;
+    } else if (i < nw + cout) {
+        const int co = i - nw;
+        float s = 0.0f;
+        for (int c = 0; c < chunks; ++c) s += partial_b[(size_t)c * cout + co];
+        db[co] = s;
+    }
+}
+
+// ============================================================================
+// head: delta = conv(d1, 32 -> 1); out = d + 4 m delta on valid pixels
+// ============================================================================
+__global__ __launch_bounds__(256) void k_head_fwd(const uint16_t *d1, const float *w, const float *b,
+                                                  const float *dm, float *out, int N, int H, int W)
+{
+    __shared__ float ws[288];
+    for (int k = threadIdx.x; k < 288; k += 256) ws[k] = w[k];
+    __syncthreads();
+    const long P = (long)N * H * W;
+    const long p = (long)blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    const int n = (int)(p / ((long)H * W));
+    const int rem = (int)(p - (long)n * H * W);
+    const int y = rem / W, x = rem - (rem / W) * W;
+    float s = b[0];
+    for (int tap = 0; tap < 9; ++tap) {
+        const int iy = y + tap / 3 - 1, ix = x + tap % 3 - 1;
+        if (iy < 0 || iy >= H || ix < 0 || ix >= W) continue;
+        const uint16_t *src = d1 + (((size_t)n * H + iy) * W + ix) * 32;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const u32x4 v = ld16(src + 8 * q);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s += ws[tap * 32 + 8 * q + e] * bf2f((uint16_t)(v[e >> 1] >> (16 * (e & 1))));
+        }
+    }
+    const float d = dm[p];
+    out[p] = d > 0.0f ? d + kDepthScale * s : 0.0f;
+}
+
+// masked L1: count, then gradient and sum, then the mean
+__global__ __launch_bounds__(256) void k_loss_count(const float *dm, const float *target, int n, unsigned *cnt)
+{
+    __shared__ unsigned c;
+    if (threadIdx.x == 0) c = 0u;
+    __syncthreads();
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p < n && dm[p] > 0.0f && target[p] > 0.0f) atomicAdd(&c, 1u);
+    __syncthreads();
+    if (threadIdx.x == 0 && c) atomicAdd(cnt, c);
+}
+
+__global__ __launch_bounds__(256) void k_loss_grad(const float *out, const float *dm, const float *target, int n,
+                                                   const unsigned *cnt, float *ddelta, float *sum)
+{
+    __shared__ float s;
+    if (threadIdx.x == 0) s = 0.0f;
+    __syncthreads();
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const float inv_n = *cnt ? 1.0f / (float)*cnt : 0.0f;
+    if (p < n) {
+        float g = 0.0f;
+        if (dm[p] > 0.0f && target[p] > 0.0f) {
+            const float diff = out[p] - target[p];
+            g = diff > 0.0f ? inv_n : (diff < 0.0f ? -inv_n : 0.0f);
+            atomicAdd(&s, diff < 0.0f ? -diff : diff);
+        }
+        ddelta[p] = kDepthScale * g;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(sum, s);
+}
+
+__global__ void k_loss_final(unsigned *cnt, float *sum, float *loss)
+{
+    loss[0] = *cnt ? sum[0] / (float)*cnt : 0.0f;
+    loss[1] = (float)*cnt;
+    *cnt = 0u;
+    sum[0] = 0.0f;
+}
+
+// gradient at d1 through the head: g[p][c] = sum_tap ddelta[p - tap + 1] w[tap][c], relu mask of d1
+__global__ __launch_bounds__(256) void k_head_bwd(const float *ddelta, const float *w, const uint16_t *d1,
+                                                  uint16_t *g_d1, int N, int H, int W)
+{
+    __shared__ float ws[288];
+    for (int k = threadIdx.x; k < 288; k += 256) ws[k] = w[k];
+    __syncthreads();
+    const long P = (long)N * H * W;
+    const long p = (long)blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    const int n = (int)(p / ((long)H * W));
+    const int rem = (int)(p - (long)n * H * W);
+    const int y = rem / W, x = rem - (rem / W) * W;
+    float g[32];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) g[c] = 0.0f;
+    for (int tap = 0; tap < 9; ++tap) {
+        const int oy = y - tap / 3 + 1, ox = x - tap % 3 + 1;
+        if (oy < 0 || oy >= H || ox < 0 || ox >= W) continue;
+        const float dd = ddelta[((size_t)n * H + oy) * W + ox];
+        if (dd == 0.0f) continue;
+#pragma unroll
+        for (int c = 0; c < 32; ++c) g[c] += dd * ws[tap * 32 + c];
+    }
+    const uint16_t *a = d1 + (size_t)p * 32;
+    uint16_t *o = g_d1 + (size_t)p * 32;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const u32x4 av = ld16(a + 8 * q);
+        u32x4 ov;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint16_t a0 = (uint16_t)(av[e] & 0xffffu), a1 = (uint16_t)(av[e] >> 16);
+            const uint16_t v0 = bf2f(a0) > 0.0f ? f2bf(g[8 * q + 2 * e]) : (uint16_t)0;
+            const uint16_t v1 = bf2f(a1) > 0.0f ? f2bf(g[8 * q + 2 * e + 1]) : (uint16_t)0;
+            ov[e] = (uint32_t)v0 | ((uint32_t)v1 << 16);
+        }
+        *reinterpret_cast<u32x4 *>(o + 8 * q) = ov;
+    }
+}
+
+// head weight gradient of one pixel chunk: thread j < 288 owns w[j], thread 288 the bias
+__global__ __launch_bounds__(320) void k_head_wgrad(const float *ddelta, const uint16_t *d1, int N, int H, int W,
+                                                    float *partial, int chunk_pix)
+{
+    const long P = (long)N * H * W;
+    const long c0 = (long)blockIdx.x * chunk_pix;
+    const long c1 = c0 + chunk_pix < P ? c0 + chunk_pix : P;
+    const int j = (int)threadIdx.x;
+    if (j > 288) return;
+    const int tap = j / 32, c = j % 32;
+    const int ky = tap / 3, kx = tap % 3;
+    float s = 0.0f;
+    for (long p = c0; p < c1; ++p) {
+        const float dd = ddelta[p];
+        if (dd == 0.0f) continue;
+        if (j == 288) {
+            s += dd;
+            continue;
+        }
+        const int n = (int)(p / ((long)H * W));
+        const int rem = (int)(p - (long)n * H * W);
+        const int y = rem / W + ky - 1, x = rem % W + kx - 1;
+        if (y < 0 || y >= H || x < 0 || x >= W) continue;
+        s += dd * bf2f(d1[(((size_t)n * H + y) * W + x) * 32 + c]);
+    }
+    partial[(size_t)blockIdx.x * 289 + j] = s;
+}
+
+__global__ __launch_bounds__(320) void k_head_reduce(const float *partial, int chunks, float *dw, float *db)
+{
+    const int j = (int)threadIdx.x;
+    if (j > 288) return;
+    float s = 0.0f;
+    for (int c = 0; c < chunks; ++c) s += partial[(size_t)c * 289 + j];
+    if (j < 288)
+        dw[j] = s;
+    else
+        db[0] = s;
+}
+
+// Adam (Kingma & Ba, Algorithm 1); c1 = 1 - beta1^t, c2 = 1 - beta2^t
+__global__ __launch_bounds__(256) void k_adam(float *p, const float *g, float *m, float *v, int n, float lr,
+                                              float b1, float b2, float eps, float c1, float c2)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / c1, vh = vi / c2;
+    p[i] = p[i] - lr * mh / (sqrtf(vh) + eps);
+}
+
+// ============================================================================
+// launchers
+// ============================================================================
+static dim3 grid1(long n, int per) { return dim3((unsigned)((n + per - 1) / per)); }
+
+hipError_t launch_make_input(const void *depth, int fmt, int n_pix, uint16_t *x, float *dm, hipStream_t s)
+{
+    if (fmt == TF_DEPTH_U16_MM)
+        hipLaunchKernelGGL(k_make_input<TF_DEPTH_U16_MM>, grid1(n_pix, 256), dim3(256), 0, s, depth, n_pix, x, dm);
+    else
+        hipLaunchKernelGGL(k_make_input<TF_DEPTH_F32_M>, grid1(n_pix, 256), dim3(256), 0, s, depth, n_pix, x, dm);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const Net &net, const float *params, uint16_t *g, uint16_t *t, hipStream_t s)
+{
+    for (int l = 0; l < kLayers - 1; ++l) {
+        const LayerDesc &L = net.L[l];
+        const int n = L.cout * L.kp > L.cinp * 9 * L.cout ? L.cout * L.kp : L.cinp * 9 * L.cout;
+        hipLaunchKernelGGL(k_pack, grid1(n, 256), dim3(256), 0, s, params + L.w_off, L.cin, L.cinp, L.cout, L.kp,
+                           g + L.g_off, L.t_off >= 0 ? t + L.t_off : (uint16_t *)nullptr);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_conv_fwd(int layer, const uint16_t *in, int Hs, int Ws, const uint16_t *g, const float *bias,
+                           const uint16_t *skip, uint16_t *out, int N, int Ho, int Wo, hipStream_t s)
+{
+    const dim3 gr = grid1((long)N * Ho * Wo, 128), b(256);
+    switch (layer) {
+    case 0: hipLaunchKernelGGL((k_conv_fwd<8, 32, 1, false, false>), gr, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 1: hipLaunchKernelGGL((k_conv_fwd<32, 64, 2, false, false>), gr, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 2: hipLaunchKernelGGL((k_conv_fwd<64, 64, 2, false, false>), gr, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 3: hipLaunchKernelGGL((k_conv_fwd<64, 128, 2, false, false>), gr, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 4: hipLaunchKernelGGL((k_conv_fwd<128, 64, 1, true, true>), gr, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 5: hipLaunchKernelGGL((k_conv_fwd<64, 64, 1, true, true>), gr, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 6: hipLaunchKernelGGL((k_conv_fwd<64, 32, 1, true, true>), gr, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_head_fwd(const uint16_t *d1, const float *w, const float *b, const float *dm, float *out, int N,
+                           int H, int W, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_head_fwd, grid1((long)N * H * W, 256), dim3(256), 0, s, d1, w, b, dm, out, N, H, W);
+    return hipGetLastError();
+}
+
+// scratch: [0] count (uint32), [1] sum; loss: [0] mean, [1] count
+hipError_t launch_loss(const float *out, const float *dm, const float *target, int n_pix, float *ddelta,
+                       float *scratch, float *loss, hipStream_t s)
+{
+    unsigned *cnt = reinterpret_cast<unsigned *>(scratch);
+    hipLaunchKernelGGL(k_loss_count, grid1(n_pix, 256), dim3(256), 0, s, dm, target, n_pix, cnt);
+    hipLaunchKernelGGL(k_loss_grad, grid1(n_pix, 256), dim3(256), 0, s, out, dm, target, n_pix, cnt, ddelta,
+                       scratch + 1);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1), 0, s, cnt, scratch + 1, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_head_bwd(const float *ddelta, const float *w, const uint16_t *d1, uint16_t *g_d1, int N, int H,
+                           int W, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_head_bwd, grid1((long)N * H * W, 256), dim3(256), 0, s, ddelta, w, d1, g_d1, N, H, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_head_wgrad(const float *ddelta, const uint16_t *d1, int N, int H, int W, float *partial,
+                             int chunks, float *dw, float *db, hipStream_t s)
+{
+    const long P = (long)N * H * W;
+    const int per = (int)((P + chunks - 1) / chunks);
+    const int nc = (int)((P + per - 1) / per);
+    hipLaunchKernelGGL(k_head_wgrad, dim3(nc), dim3(320), 0, s, ddelta, d1, N, H, W, partial, per);
+    hipLaunchKernelGGL(k_head_reduce, dim3(1), dim3(320), 0, s, partial, nc, dw, db);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_bwd_data(int layer, const uint16_t *gpre, int Ho, int Wo, const uint16_t *t,
+                                const uint16_t *skipg, const uint16_t *act, uint16_t *gout, int N, int Hq, int Wq,
+                                hipStream_t s)
+{
+    const dim3 gr = grid1((long)N * Hq * Wq, 128), b(256);
+    switch (layer) {
+    case 1: hipLaunchKernelGGL((k_conv_bwd_data<32, 64, 2, false, true>), gr, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
+    case 2: hipLaunchKernelGGL((k_conv_bwd_data<64, 64, 2, false, true>), gr, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
+    case 3: hipLaunchKernelGGL((k_conv_bwd_data<64, 128, 2, false, true>), gr, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
+    case 4: hipLaunchKernelGGL((k_conv_bwd_data<128, 64, 1, true, false>), gr, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
+    case 5: hipLaunchKernelGGL((k_conv_bwd_data<64, 64, 1, true, false>), gr, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
+    case 6: hipLaunchKernelGGL((k_conv_bwd_data<64, 32, 1, true, false>), gr, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_wgrad(int layer, const uint16_t *gpre, const uint16_t *in, int Hs, int Ws, int N, int Ho,
+                             int Wo, float *partial, int chunks, float *dw, float *db, hipStream_t s)
+{
+    const long P = (long)N * Ho * Wo;
+    int per = (int)((P + chunks - 1) / chunks);
+    per = ((per + 31) / 32) * 32;
+    const int nc = (int)((P + per - 1) / per);
+    float *pb = partial;   // bias partials after the weight partials
+    const dim3 gr(9, nc), b(256);
+    int cout = 0, cin = 0, cinp = 0;
+    switch (layer) {
+    case 0: cout = 32; cin = 2; cinp = 8; pb += (size_t)nc * 32 * 9 * 8;
+        hipLaunchKernelGGL((k_conv_wgrad<8, 32, 1, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per); break;
+    case 1: cout = 64; cin = cinp = 32; pb += (size_t)nc * 64 * 9 * 32;
+        hipLaunchKernelGGL((k_conv_wgrad<32, 64, 2, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per); break;
+    case 2: cout = 64; cin = cinp = 64; pb += (size_t)nc * 64 * 9 * 64;
+        hipLaunchKernelGGL((k_conv_wgrad<64, 64, 2, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per); break;
+    case 3: cout = 128; cin = cinp = 64; pb += (size_t)nc * 128 * 9 * 64;
+        hipLaunchKernelGGL((k_conv_wgrad<64, 128, 2, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per); break;
+    case 4: cout = 64; cin = cinp = 128; pb += (size_t)nc * 64 * 9 * 128;
+        hipLaunchKernelGGL((k_conv_wgrad<128, 64, 1, true>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per); break;
+    case 5: cout = 64; cin = cinp = 64; pb += (size_t)nc * 64 * 9 * 64;
+        hipLaunchKernelGGL((k_conv_wgrad<64, 64, 1, true>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per); break;
+    case 6: cout = 32; cin = cinp = 64; pb += (size_t)nc * 32 * 9 * 64;
+        hipLaunchKernelGGL((k_conv_wgrad<64, 32, 1, true>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wgrad_reduce, grid1((long)cout * 9 * cin + cout, 256), dim3(256), 0, s, partial, pb, nc,
+                       cout, cin, cinp, dw, db);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t s)
+{
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, grid1(n, 256), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace tsdf

@@ -248,7 +248,7 @@ int run(tf_multi *m, const void *d_depth, int fmt, const tf_intrinsics *K, const
         GraphKey k = {1, do_int, do_ray, fw, fh, do_ray ? (int)n_views : 0, tiles, m->cfg};
         if (!m->gkey[h].valid || memcmp(&k, &m->gkey[h], sizeof(GraphKey)) != 0) {
             if (m->gexec[h]) {
-                hipGraphExecDestroy(m->gexec[h]);
+                (void)hipGraphExecDestroy(m->gexec[h]);
                 m->gexec[h] = nullptr;
             }
             m->gkey[h].valid = 0;
@@ -260,7 +260,7 @@ int run(tf_multi *m, const void *d_depth, int fmt, const tf_intrinsics *K, const
                 if (e == hipSuccess) e = e2;
             }
             if (e == hipSuccess) e = hipGraphInstantiate(&m->gexec[h], g, nullptr, nullptr, 0);
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             if (e == hipSuccess) m->gkey[h] = k;
         }
         if (e == hipSuccess) e = hipGraphLaunch(m->gexec[h], s);
@@ -380,10 +380,10 @@ int tf_multi_destroy(tf_multi *m)
 {
     if (!m) return TF_E_INVAL;
     for (int h = 0; h < 2; ++h) {
-        if (m->gexec[h]) hipGraphExecDestroy(m->gexec[h]);
-        if (m->done[h]) hipEventDestroy(m->done[h]);
+        if (m->gexec[h]) (void)hipGraphExecDestroy(m->gexec[h]);
+        if (m->done[h]) (void)hipEventDestroy(m->done[h]);
     }
-    if (m->cap_stream) hipStreamDestroy(m->cap_stream);
+    if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
     for (tf_ctx *c : m->subs) tf_destroy(c);
     delete m;
     return TF_OK;
@@ -520,8 +520,8 @@ int tf_multi_autotune(tf_multi *m, const void *d_depth, int fmt, const tf_intrin
             }
         }
     ms_ray = br;
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st != TF_OK) {
         m->cfg = keep;
         return st;

@@ -1,0 +1,206 @@
+"""GPU parity of the learned depth prefilter (BF16 matrix-core kernels with
+fp32 accumulation) against the oracle.
+
+Per layer, the oracle recomputes the GPU's result from the GPU's own bf16
+operands (inputs, bf16-rounded weights, upstream gradients) in float64, so
+the only differences are accumulation order and the final bf16 rounding:
+outputs within 1 bf16 ulp-scale (0.8% relative plus a small absolute floor),
+weight gradients within 1e-3 relative.  End to end against the float64
+oracle on bf16-rounded weights and input: per-layer gradient cosine >= 0.999.
+Adam matches the oracle's update; a zero head is the identity exactly."""
+import numpy as np
+import pytest
+
+from oracle import denoise as D
+
+pytestmark = pytest.mark.gpu
+
+N, H, W = 2, 32, 48
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+def _setup(seed=0):
+    import torch
+    import paper_1708_00783_amd as T
+    rng = np.random.default_rng(seed)
+    P = D.init_params(seed, np.float64)
+    for k in P:
+        if k.endswith(".b"):
+            P[k] = rng.standard_normal(P[k].shape) * 0.05
+    P["head.w"] = rng.standard_normal(P["head.w"].shape) * 0.05
+    P = {k: v.astype(np.float32).astype(np.float64) for k, v in P.items()}
+    depth = rng.uniform(0.4, 3.8, (N, H, W)).astype(np.float32)
+    depth[0, 5:9, 10:20] = 0.0
+    depth[1, :, :3] = 0.0
+    target = (depth + rng.normal(0, 0.02, depth.shape)).astype(np.float32)
+    target[0, 20:24] = 0.0
+    net = T.Denoiser(N, H, W, training=True)
+    net.set_params(T.nn_flatten(P))
+    d_depth = torch.from_numpy(depth).cuda()
+    out = net.forward(d_depth)
+    return T, net, P, depth, target, out
+
+
+def _bf(net, name):
+    import paper_1708_00783_amd as T
+    return T.bf16_bits_to_float(net.tensor(name)).astype(np.float64)
+
+
+def _close(gpu, ref, tag, rel=8e-3, floor=None):
+    floor = floor if floor is not None else 1e-3 * max(1e-6, np.abs(ref).max())
+    err = np.abs(gpu - ref)
+    bad = err > rel * np.abs(ref) + floor
+    assert not bad.any(), f"{tag}: {bad.sum()} of {bad.size} off, max err {err.max():.3g} (ref max {np.abs(ref).max():.3g})"
+
+
+def _rb(w):
+    return D.to_bf16(w.astype(np.float32)).astype(np.float64)
+
+
+LAYER_IO = {"e1": ("input", 1, False, None), "e2": ("e1", 2, False, None), "e3": ("e2", 2, False, None),
+            "e4": ("e3", 2, False, None), "d3": ("e4", 1, True, "e3"), "d2": ("d3", 1, True, "e2"),
+            "d1": ("d2", 1, True, "e1")}
+
+
+def test_forward_layers_match_oracle():
+    T, net, P, depth, target, out = _setup(1)
+    x = _bf(net, "input")
+    assert np.array_equal(x[..., 0], D.to_bf16(depth * 0.25)) and np.array_equal(x[..., 1], (depth > 0) * 1.0)
+    assert not x[..., 2:].any()
+    for name, (src, stride, up, skip) in LAYER_IO.items():
+        a = _bf(net, src)
+        if name == "e1":
+            a = a[..., :2]
+        if up:
+            a = D.up2(a)
+        ref = D.conv(a, _rb(P[name + ".w"]), P[name + ".b"], stride)
+        if skip:
+            ref = ref + _bf(net, skip)
+        ref = np.maximum(ref, 0)
+        _close(_bf(net, name), ref, name)
+        _log(f"{name}: ok, {ref.shape}, max {ref.max():.3g}")
+    d1 = _bf(net, "d1")
+    delta = D.conv(d1, P["head.w"], P["head.b"])[..., 0]
+    ref = np.where(depth > 0, depth + 4.0 * delta, 0.0)
+    got = out.cpu().numpy()
+    assert np.abs(got - ref).max() < 1e-5
+    assert np.all(got[depth == 0] == 0)
+
+
+def test_backward_layers_match_oracle():
+    import torch
+    T, net, P, depth, target, out = _setup(2)
+    loss = net.backward(torch.from_numpy(target).cuda()).cpu().numpy()
+    o = out.cpu().numpy().astype(np.float64)
+    l_ref, g_ref, n_ref = D.loss_and_grad_out(o, depth, target)
+    assert int(loss[1]) == n_ref and abs(loss[0] - l_ref) < 1e-5 * max(1.0, l_ref)
+    dd = net.tensor("ddelta").cpu().numpy().astype(np.float64)
+    assert np.allclose(dd, np.where(depth > 0, 4.0 * g_ref, 0), rtol=1e-6, atol=1e-12)
+    grads = T.nn_unflatten(net.tensor("grads").cpu().numpy().reshape(-1))
+    # head: gradient at d1 and head parameters
+    d1 = _bf(net, "d1")
+    dd1, dwh, dbh = D.conv_backward(d1, P["head.w"], dd[..., None])
+    _close(_bf(net, "grad_d1"), dd1 * (d1 > 0), "grad_d1")
+    assert np.allclose(grads["head.w"], dwh, rtol=1e-3, atol=1e-6 * np.abs(dwh).max())
+    assert np.allclose(grads["head.b"], dbh, rtol=1e-4, atol=1e-9)
+    # conv layers, from the GPU's own upstream gradients
+    skip_to = {"e1": "d1", "e2": "d2", "e3": "d3"}
+    for name, (src, stride, up, _) in reversed(list(LAYER_IO.items())):
+        g = _bf(net, "grad_" + name)
+        a = _bf(net, src)
+        if name == "e1":
+            a = a[..., :2]
+        a_in = D.up2(a) if up else a
+        wb = _rb(P[name + ".w"])
+        dx, dw, db = D.conv_backward(a_in, wb, g, stride)
+        cos = float(np.sum(grads[name + ".w"] * dw) / (np.linalg.norm(grads[name + ".w"]) * np.linalg.norm(dw)))
+        rel = float(np.linalg.norm(grads[name + ".w"] - dw) / np.linalg.norm(dw))
+        assert rel < 1e-3, (name, rel)
+        assert np.allclose(grads[name + ".b"], db, rtol=1e-3, atol=1e-6 * max(1e-9, np.abs(db).max()))
+        _log(f"{name}: dW rel {rel:.2e} cos {cos:.6f}")
+        if name == "e1":
+            continue
+        if up:
+            dx = D.up2_backward(dx)
+        if src in skip_to:
+            dx = dx + _bf(net, "grad_" + skip_to[src])
+        _close(_bf(net, "grad_" + src), dx * (a > 0), "grad_" + src)
+
+
+def test_end_to_end_gradient_cosine():
+    import torch
+    T, net, P, depth, target, out = _setup(3)
+    net.backward(torch.from_numpy(target).cuda())
+    torch.cuda.synchronize()
+    grads = T.nn_unflatten(net.tensor("grads").cpu().numpy().reshape(-1))
+    Pb = {k: (_rb(v) if k.endswith(".w") and not k.startswith("head") else v) for k, v in P.items()}
+    o, c = D.forward(Pb, depth.astype(np.float64))
+    _, g, _ = D.loss_and_grad_out(o, depth, target)
+    G = D.backward(Pb, c, g)
+    for k in G:
+        a, b = grads[k].reshape(-1).astype(np.float64), G[k].reshape(-1)
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30))
+        _log(f"{k}: cosine {cos:.6f}")
+        assert cos >= 0.999, (k, cos)
+
+
+def test_adam_matches_oracle():
+    import torch
+    T, net, P, depth, target, out = _setup(4)
+    net.backward(torch.from_numpy(target).cuda())
+    torch.cuda.synchronize()
+    g = net.tensor("grads").cpu().numpy().reshape(-1).astype(np.float64)
+    p0 = net.get_params().cpu().numpy().astype(np.float64)
+    net.adam_step(1e-3, 0.9, 0.999, 1e-8)
+    p1 = net.get_params().cpu().numpy().astype(np.float64)
+    Po, st = {"p": p0.copy()}, {}
+    D.adam_step(Po, {"p": g}, st, 1)
+    assert np.abs(p1 - Po["p"]).max() < 1e-6
+    # the forward pass uses the updated weights
+    net.forward(torch.from_numpy(depth).cuda())
+    assert not np.array_equal(net.tensor("out").cpu().numpy(), out.cpu().numpy())
+
+
+def test_zero_head_is_identity_and_fuses_like_raw_depth():
+    import torch
+    import paper_1708_00783_amd as T
+    from synth import configs
+    d, p, K, _ = configs.c1_frames(3)
+    net = T.Denoiser(1, K.height, K.width)
+    net.set_params(T.nn_flatten(D.init_params(0)))
+    raw = T.Volume(configs.C1_VOLUME, K.width, K.height)
+    den = T.Volume(configs.C1_VOLUME, K.width, K.height)
+    for k in range(3):
+        dk = torch.from_numpy(d[k]).cuda()
+        o = net.forward(dk[None])[0]
+        assert torch.equal(o, torch.where(dk > 0, dk, torch.zeros_like(dk)))
+        raw.frame(dk, K, p[k])
+        den.frame(o.contiguous(), K, p[k])
+    a, b = raw.voxels_by_position(), den.voxels_by_position()
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_training_reduces_loss():
+    """Adam on one fixed batch (noisy planes -> clean planes): the loss falls."""
+    import torch
+    import paper_1708_00783_amd as T
+    rng = np.random.default_rng(5)
+    net = T.Denoiser(4, 64, 64, training=True)
+    net.set_params(T.nn_flatten(D.init_params(5)))
+    yy, xx = np.mgrid[0:64, 0:64]
+    base = np.stack([1.0 + 0.01 * (xx * rng.uniform(-1, 1) + yy * rng.uniform(-1, 1)) + rng.uniform(0, 1)
+                     for _ in range(4)]).astype(np.float32)
+    noisy = torch.from_numpy((base + rng.normal(0, 0.01, base.shape)).astype(np.float32)).cuda()
+    clean = torch.from_numpy(base).cuda()
+    losses = []
+    for it in range(100):
+        net.forward(noisy)
+        loss = net.backward(clean)
+        net.adam_step(1e-3)
+        losses.append(float(loss[0].item()))
+    _log("loss", losses[:3], losses[-3:])
+    assert np.isfinite(losses).all()
+    assert np.mean(losses[-10:]) < 0.8 * losses[0]
