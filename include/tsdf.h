@@ -187,6 +187,10 @@ int tf_export_host_voxels(tf_ctx *ctx, const int32_t *h_entries, uint32_t n, int
  * launch).  tf_profile_read synchronises on the outstanding events, returns
  * the totals and, if `reset` != 0, zeroes them. */
 int tf_profile_enable(tf_ctx *ctx, int on);
+/* Time only the kernel classes in class_mask (bit TF_K_*), and of each only
+ * every `every`-th launch (every >= 1): each timed launch costs two event
+ * records on the stream.  Default: all classes, every launch. */
+int tf_profile_select(tf_ctx *ctx, uint32_t class_mask, uint32_t every);
 int tf_profile_read(tf_ctx *ctx, tf_profile *h_out, int reset);
 
 /* Counters and sticky flags.  Synchronises `stream`. */

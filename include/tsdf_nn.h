@@ -4,17 +4,18 @@
  * A small convolutional encoder-decoder that corrects a depth frame before
  * it is fused (the paper fuses raw depth, optionally bilateral-filtered,
  * Sec. 4; this learned filter is not part of the paper):
- *     input (d / 4 m, valid mask), 3x3 convs, encoder 32 (stride 1), 64, 64,
+ *     input (d / 4 m, valid mask, (d - mean of the valid 3x3 neighbours) /
+ *     5 cm), 3x3 convs, encoder 32 (stride 1), 64, 64,
  *     128 (stride 2 each); decoder nearest x2 upsampling + 3x3 conv to 64,
  *     64, 32 with the same-resolution encoder output added before the relu;
- *     head 3x3 conv 32 -> 1 (delta); output d + 4 m * delta where d > 0, 0
+ *     head 3x3 conv 32 -> 1 (delta); output d + 5 cm * delta where d > 0, 0
  *     elsewhere (holes stay holes).
  * Activations are bfloat16 on the matrix cores with fp32 accumulation;
  * parameters have fp32 master copies.  Training minimises the mean |out -
  * target| over pixels valid in both, with Adam.
  *
  * Parameter vector: fp32, layers e1 e2 e3 e4 d3 d2 d1 head in this order,
- * each W[cout][3][3][cin] (row-major) followed by b[cout]; 259361 values.
+ * each W[cout][3][3][cin] (row-major) followed by b[cout]; 259649 values.
  *
  * Conventions as in tsdf.h: int status (TF_OK or TF_E_*), d_* device
  * pointers owned by the caller, work enqueued on `stream` only, no device
@@ -35,7 +36,7 @@ extern "C" {
 typedef struct tf_nn tf_nn;   /* opaque, host-side */
 
 /* tensors readable through tf_nn_tensor (ids) */
-#define TF_NN_T_INPUT 0      /* x: batch x H x W x 8 bf16 (channels 2..7 zero) */
+#define TF_NN_T_INPUT 0      /* x: batch x H x W x 8 bf16 (channels 3..7 zero) */
 #define TF_NN_T_E1 1         /* e1..d1: post-relu activations, bf16 NHWC */
 #define TF_NN_T_D1 7
 #define TF_NN_T_GRAD_E1 8    /* 8..14: loss gradient at the pre-relu sums of e1..d1, bf16 NHWC */

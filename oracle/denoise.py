@@ -10,8 +10,10 @@ The prefilter is not part of the paper; the nearest thing there is the
 optional bilateral filter of the depth input (Sec. 4).  Architecture (one
 reading of "4-level 3x3 encoder-decoder with 32/64/64/128 channels"):
 
-  input  x = (d / 4 m, valid mask)                               2 ch, HxW
-  e1 = relu(conv(x,  2->32,  stride 1))                          H   x W
+  input  x = (d / 4 m, valid mask, hp)                           3 ch, HxW
+         hp = (d - mean of the valid depths of the 3x3 neighbourhood) / 5 cm
+              on valid pixels, 0 elsewhere
+  e1 = relu(conv(x,  3->32,  stride 1))                          H   x W
   e2 = relu(conv(e1, 32->64, stride 2))                          H/2 x W/2
   e3 = relu(conv(e2, 64->64, stride 2))                          H/4 x W/4
   e4 = relu(conv(e3, 64->128, stride 2))                         H/8 x W/8
@@ -19,7 +21,7 @@ reading of "4-level 3x3 encoder-decoder with 32/64/64/128 channels"):
   d2 = relu(conv(up2(d3), 64->64)  + e2)
   d1 = relu(conv(up2(d2), 64->32)  + e1)
   delta = conv(d1, 32->1)            (zero-initialised weights and bias)
-  out = d + 4 m * delta where d > 0, else 0
+  out = d + 5 cm * delta where d > 0, else 0
 
 conv = 3x3, zero padding 1, with bias; a stride-2 conv samples input pixel
 2 o + k - 1 for output o and tap k; up2 = nearest-neighbour upsampling.
@@ -34,13 +36,14 @@ from __future__ import annotations
 
 import numpy as np
 
-DEPTH_SCALE = 4.0            # metres: depth input and correction scale
+DEPTH_SCALE = 4.0            # metres: depth input normalisation
+CORRECTION_SCALE = 0.05      # metres: the head's output is a correction in units of 5 cm
 CHANNELS = (32, 64, 64, 128)
-ADAM = dict(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8)
+ADAM = dict(lr=2e-4, beta1=0.9, beta2=0.999, eps=1e-8)
 
 # (name, cin, cout, stride, input) of every conv, in forward order
 LAYERS = (
-    ("e1", 2, 32, 1, "x"),
+    ("e1", 3, 32, 1, "x"),
     ("e2", 32, 64, 2, "e1"),
     ("e3", 64, 64, 2, "e2"),
     ("e4", 64, 128, 2, "e3"),
@@ -133,33 +136,60 @@ def relu(x):
     return np.maximum(x, 0)
 
 
-def make_input(depth):
-    """(N, H, W) metres -> (N, H, W, 2): depth / 4 m and the valid mask"""
+def local_mean(depth):
+    """mean of the valid (> 0) depths in each pixel's 3x3 neighbourhood
+    (0 where none is valid)"""
     d = np.asarray(depth)
-    return np.stack([d / DEPTH_SCALE, (d > 0).astype(d.dtype)], axis=-1)
+    v = (d > 0).astype(d.dtype)
+    N, H, W = d.shape
+    dp = np.zeros((N, H + 2, W + 2), d.dtype)
+    vp = np.zeros((N, H + 2, W + 2), d.dtype)
+    dp[:, 1:H + 1, 1:W + 1] = d * v
+    vp[:, 1:H + 1, 1:W + 1] = v
+    s = sum(dp[:, ky:ky + H, kx:kx + W] for ky in range(3) for kx in range(3))
+    c = sum(vp[:, ky:ky + H, kx:kx + W] for ky in range(3) for kx in range(3))
+    return np.where(c > 0, s / np.maximum(c, 1), 0)
+
+
+def make_input(depth):
+    """(N, H, W) metres -> (N, H, W, 3): depth / 4 m, the valid mask, and the
+    depth's deviation from its 3x3 valid mean in 5 cm units (valid pixels)"""
+    d = np.asarray(depth)
+    valid = d > 0
+    hp = np.where(valid, (d - local_mean(d)) / CORRECTION_SCALE, 0)
+    return np.stack([d / DEPTH_SCALE, valid.astype(d.dtype), hp], axis=-1)
 
 
 # ---- network ----------------------------------------------------------------------------
 
-def forward(P, depth):
-    """returns (out depth (N, H, W), cache of the activations); H, W divisible by 8"""
+def _ident(a):
+    return a
+
+
+def forward(P, depth, q=None):
+    """returns (out depth (N, H, W), cache of the activations); H, W divisible
+    by 8.  q (default: identity) is applied to the input and to every stored
+    activation -- bf16 rounding reproduces the storage precision of the
+    matrix-core kernels, so both sides take their relu decisions on the same
+    values."""
+    q = q or _ident
     dt = P["e1.w"].dtype
     depth = np.asarray(depth, dt)
-    x = make_input(depth)
-    c = {"x": x, "depth": depth}
-    c["e1"] = relu(conv(x, P["e1.w"], P["e1.b"], 1))
-    c["e2"] = relu(conv(c["e1"], P["e2.w"], P["e2.b"], 2))
-    c["e3"] = relu(conv(c["e2"], P["e3.w"], P["e3.b"], 2))
-    c["e4"] = relu(conv(c["e3"], P["e4.w"], P["e4.b"], 2))
+    x = q(make_input(depth)).astype(dt)
+    c = {"x": x, "depth": depth, "q": q}
+    c["e1"] = q(relu(conv(x, P["e1.w"], P["e1.b"], 1)))
+    c["e2"] = q(relu(conv(c["e1"], P["e2.w"], P["e2.b"], 2)))
+    c["e3"] = q(relu(conv(c["e2"], P["e3.w"], P["e3.b"], 2)))
+    c["e4"] = q(relu(conv(c["e3"], P["e4.w"], P["e4.b"], 2)))
     c["u4"] = up2(c["e4"])
-    c["d3"] = relu(conv(c["u4"], P["d3.w"], P["d3.b"]) + c["e3"])
+    c["d3"] = q(relu(conv(c["u4"], P["d3.w"], P["d3.b"]) + c["e3"]))
     c["u3"] = up2(c["d3"])
-    c["d2"] = relu(conv(c["u3"], P["d2.w"], P["d2.b"]) + c["e2"])
+    c["d2"] = q(relu(conv(c["u3"], P["d2.w"], P["d2.b"]) + c["e2"]))
     c["u2"] = up2(c["d2"])
-    c["d1"] = relu(conv(c["u2"], P["d1.w"], P["d1.b"]) + c["e1"])
+    c["d1"] = q(relu(conv(c["u2"], P["d1.w"], P["d1.b"]) + c["e1"]))
     c["delta"] = conv(c["d1"], P["head.w"], P["head.b"])[..., 0]
     valid = depth > 0
-    out = np.where(valid, depth + DEPTH_SCALE * c["delta"], 0).astype(dt)
+    out = np.where(valid, depth + CORRECTION_SCALE * c["delta"], 0).astype(dt)
     return out, c
 
 
@@ -177,27 +207,30 @@ def loss_and_grad_out(out, depth, target):
 
 
 def backward(P, c, dout):
-    """gradients of every parameter for upstream dL/dout"""
+    """gradients of every parameter for upstream dL/dout; the gradient at each
+    pre-relu sum passes through the forward pass's q (stored like the
+    activations)"""
+    q = c.get("q", _ident)
     G = {}
     valid = c["depth"] > 0
-    ddelta = np.where(valid, DEPTH_SCALE * dout, 0)[..., None]
+    ddelta = np.where(valid, CORRECTION_SCALE * dout, 0)[..., None]
     dd1, G["head.w"], G["head.b"] = conv_backward(c["d1"], P["head.w"], ddelta)
-    dd1 = dd1 * (c["d1"] > 0)                       # through the relu of d1
+    dd1 = q(dd1 * (c["d1"] > 0))                    # through the relu of d1
     du2, G["d1.w"], G["d1.b"] = conv_backward(c["u2"], P["d1.w"], dd1)
     de1_skip = dd1
-    dd2 = up2_backward(du2) * (c["d2"] > 0)
+    dd2 = q(up2_backward(du2) * (c["d2"] > 0))
     du3, G["d2.w"], G["d2.b"] = conv_backward(c["u3"], P["d2.w"], dd2)
     de2_skip = dd2
-    dd3 = up2_backward(du3) * (c["d3"] > 0)
+    dd3 = q(up2_backward(du3) * (c["d3"] > 0))
     du4, G["d3.w"], G["d3.b"] = conv_backward(c["u4"], P["d3.w"], dd3)
     de3_skip = dd3
-    de4 = up2_backward(du4) * (c["e4"] > 0)
+    de4 = q(up2_backward(du4) * (c["e4"] > 0))
     de3, G["e4.w"], G["e4.b"] = conv_backward(c["e3"], P["e4.w"], de4, 2)
-    de3 = (de3 + de3_skip) * (c["e3"] > 0)
+    de3 = q((de3 + de3_skip) * (c["e3"] > 0))
     de2, G["e3.w"], G["e3.b"] = conv_backward(c["e2"], P["e3.w"], de3, 2)
-    de2 = (de2 + de2_skip) * (c["e2"] > 0)
+    de2 = q((de2 + de2_skip) * (c["e2"] > 0))
     de1, G["e2.w"], G["e2.b"] = conv_backward(c["e1"], P["e2.w"], de2, 2)
-    de1 = (de1 + de1_skip) * (c["e1"] > 0)
+    de1 = q((de1 + de1_skip) * (c["e1"] > 0))
     _, G["e1.w"], G["e1.b"] = conv_backward(c["x"], P["e1.w"], de1)
     return G
 

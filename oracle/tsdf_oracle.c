@@ -562,8 +562,10 @@ void or_integrate_literal(or_volume *v, const float *depth, int W, int H, const 
  * Search range (Sec. 4.4): forward-project each block, take the 2-D bounding
  * box of its 8 projected corners (floor of the minimum, ceil of the maximum,
  * clipped to the image) and fill it with the min/max camera z of the corners.
- * A block reaching in front of the near plane covers the whole image from
- * the near plane; a block entirely in front of it is skipped.  `blocks` lists
+ * A block reaching closer than the near plane is clipped there: its box is
+ * that of its corners beyond the plane and of the points where its edges
+ * cross the plane, and its z range starts at the plane; a block entirely
+ * closer than the plane is skipped.  `blocks` lists
  * entry indices; n < 0 means "every entry with a device block".
  * Uncovered pixels keep zmin = +inf, zmax = -inf (no search interval).
  * -------------------------------------------------------------------------- */
@@ -589,29 +591,46 @@ void or_range(const or_volume *v, const int32_t *blocks, int n, int W, int H, co
             if (cs[c][2] > zhi) zhi = cs[c][2];
         }
         if (zhi < OR_Z_NEAR) continue;
-        int x0, x1, y0, y1;
-        if (zlo < OR_Z_NEAR) {
-            zlo = OR_Z_NEAR;
-            x0 = 0; x1 = W - 1; y0 = 0; y1 = H - 1;
-        } else {
-            float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
-            for (int c = 0; c < 8; ++c) {
-                float rz = 1.0f / cs[c][2];
-                float u = (fx * cs[c][0]) * rz + cx;
-                float vv = (fy * cs[c][1]) * rz + cy;
-                if (u < umin) umin = u;
-                if (u > umax) umax = u;
-                if (vv < vmin) vmin = vv;
-                if (vv > vmax) vmax = vv;
-            }
-            float fx0 = floorf(umin), fx1 = ceilf(umax), fy0 = floorf(vmin), fy1 = ceilf(vmax);
-            if (fx0 < 0.0f) fx0 = 0.0f;
-            if (fy0 < 0.0f) fy0 = 0.0f;
-            if (fx1 > (float)(W - 1)) fx1 = (float)(W - 1);
-            if (fy1 > (float)(H - 1)) fy1 = (float)(H - 1);
-            if (fx0 > fx1 || fy0 > fy1) continue;
-            x0 = (int)fx0; x1 = (int)fx1; y0 = (int)fy0; y1 = (int)fy1;
+        /* the part of the block in front of the near plane: its corners there
+         * and the points where its edges cross the plane; the pixel box of
+         * their projections */
+        float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+        for (int c = 0; c < 8; ++c) {
+            if (cs[c][2] < OR_Z_NEAR) continue;
+            float rz = 1.0f / cs[c][2];
+            float u = (fx * cs[c][0]) * rz + cx;
+            float vv = (fy * cs[c][1]) * rz + cy;
+            if (u < umin) umin = u;
+            if (u > umax) umax = u;
+            if (vv < vmin) vmin = vv;
+            if (vv > vmax) vmax = vv;
         }
+        if (zlo < OR_Z_NEAR) {
+            const float rzn = 1.0f / OR_Z_NEAR;
+            for (int a = 0; a < 8; ++a)
+                for (int bit = 1; bit < 8; bit <<= 1) {
+                    if (a & bit) continue;
+                    const int b = a | bit;   /* the edge from corner a to corner b */
+                    if ((cs[a][2] < OR_Z_NEAR) == (cs[b][2] < OR_Z_NEAR)) continue;
+                    float t = (OR_Z_NEAR - cs[a][2]) / (cs[b][2] - cs[a][2]);
+                    float xe = cs[a][0] + t * (cs[b][0] - cs[a][0]);
+                    float ye = cs[a][1] + t * (cs[b][1] - cs[a][1]);
+                    float u = (fx * xe) * rzn + cx;
+                    float vv = (fy * ye) * rzn + cy;
+                    if (u < umin) umin = u;
+                    if (u > umax) umax = u;
+                    if (vv < vmin) vmin = vv;
+                    if (vv > vmax) vmax = vv;
+                }
+            zlo = OR_Z_NEAR;
+        }
+        float fx0 = floorf(umin), fx1 = ceilf(umax), fy0 = floorf(vmin), fy1 = ceilf(vmax);
+        if (fx0 < 0.0f) fx0 = 0.0f;
+        if (fy0 < 0.0f) fy0 = 0.0f;
+        if (fx1 > (float)(W - 1)) fx1 = (float)(W - 1);
+        if (fy1 > (float)(H - 1)) fy1 = (float)(H - 1);
+        if (fx0 > fx1 || fy0 > fy1) continue;
+        int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
         for (int yy = y0; yy <= y1; ++yy)
             for (int xx = x0; xx <= x1; ++xx) {
                 int p = yy * W + xx;

@@ -31,7 +31,7 @@ EXPORTS = (
     "tf_destroy", "tf_reset", "tf_alloc_and_visible", "tf_integrate", "tf_raycast",
     "tf_range_image", "tf_swap_out", "tf_get_stats", "tf_export_entries", "tf_export_visible",
     "tf_export_voxels", "tf_status_string", "tf_profile_enable", "tf_profile_read",
-    "tf_export_host_voxels",
+    "tf_export_host_voxels", "tf_profile_select",
     "tf_multi_workspace_bytes", "tf_multi_host_bytes", "tf_multi_create", "tf_multi_destroy",
     "tf_multi_submap", "tf_multi_set_config", "tf_multi_get_config", "tf_multi_integrate",
     "tf_multi_raycast", "tf_multi_frame", "tf_multi_range_image", "tf_multi_autotune",
@@ -136,6 +136,7 @@ def lib():
             "tf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
             "tf_profile_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
             "tf_profile_read": (ctypes.c_int, [_VP, P(tf_profile), ctypes.c_int]),
+            "tf_profile_select": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32]),
             "tf_export_host_voxels": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP]),
             "tf_multi_workspace_bytes": (ctypes.c_size_t, [P(tf_params), ctypes.c_uint32, ctypes.c_uint32,
                                                            ctypes.c_uint32, ctypes.c_uint32]),
@@ -344,6 +345,11 @@ class Volume:
     def profile_enable(self, on=True):
         check(lib().tf_profile_enable(self.ctx, 1 if on else 0), "tf_profile_enable")
 
+    def profile_select(self, classes=None, every=1):
+        """time only the named kernel classes (None = all), every n-th launch"""
+        mask = 0xffffffff if classes is None else sum(1 << KERNEL_CLASSES.index(c) for c in classes)
+        check(lib().tf_profile_select(self.ctx, mask, every), "tf_profile_select")
+
     def profile_read(self, reset=False) -> dict:
         pr = tf_profile()
         check(lib().tf_profile_read(self.ctx, ctypes.byref(pr), 1 if reset else 0), "tf_profile_read")
@@ -541,7 +547,7 @@ class MultiMap:
 
 NN_T = dict(input=0, e1=1, e2=2, e3=3, e4=4, d3=5, d2=6, d1=7, grad_e1=8, grad_e2=9, grad_e3=10, grad_e4=11,
             grad_d3=12, grad_d2=13, grad_d1=14, out=15, ddelta=16, depth=17, grads=18, params=19)
-NN_LAYERS = (("e1", 2, 32), ("e2", 32, 64), ("e3", 64, 64), ("e4", 64, 128), ("d3", 128, 64), ("d2", 64, 64),
+NN_LAYERS = (("e1", 3, 32), ("e2", 32, 64), ("e3", 64, 64), ("e4", 64, 128), ("d3", 128, 64), ("d2", 64, 64),
              ("d1", 64, 32), ("head", 32, 1))
 
 
@@ -626,7 +632,7 @@ class Denoiser:
                                    _stream_ptr(stream)), "tf_nn_backward")
         return self.loss
 
-    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    def adam_step(self, lr=2e-4, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
         check(lib().tf_nn_adam_step(self.h, lr, beta1, beta2, eps, _stream_ptr(stream)), "tf_nn_adam_step")
 
     def tensor(self, name):

@@ -18,7 +18,7 @@ Net make_net()
 {
     // cin, cinp, cout, stride, up, src act, skip act
     static const int T[kLayers][7] = {
-        {2, 8, 32, 1, 0, 0, -1},    {32, 32, 64, 2, 0, 1, -1},  {64, 64, 64, 2, 0, 2, -1},
+        {3, 8, 32, 1, 0, 0, -1},    {32, 32, 64, 2, 0, 1, -1},  {64, 64, 64, 2, 0, 2, -1},
         {64, 64, 128, 2, 0, 3, -1}, {128, 128, 64, 1, 1, 4, 3}, {64, 64, 64, 1, 1, 5, 2},
         {64, 64, 32, 1, 1, 6, 1},   {32, 32, 1, 1, 0, 7, -1},
     };
@@ -233,7 +233,7 @@ int tf_nn_forward(tf_nn *nn, const void *d_depth, int fmt, uint32_t batch, float
     if (!nn->have_params) return TF_E_ORDER;
     hipStream_t s = (hipStream_t)stream;
     const int N = (int)batch, H = (int)nn->H, W = (int)nn->W;
-    hipError_t e = launch_make_input(d_depth, fmt, N * H * W, nn->act[0], nn->dm, s);
+    hipError_t e = launch_make_input(d_depth, fmt, N, H, W, nn->act[0], nn->dm, s);
     for (int l = 0; l < kLayers - 1 && e == hipSuccess; ++l) {
         const LayerDesc &L = nn->net.L[l];
         const int ss = act_scale(L.src);

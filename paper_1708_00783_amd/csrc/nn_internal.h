@@ -3,7 +3,8 @@
 // integration).  Internal to libtsdf.
 //
 // Tensors are NHWC bfloat16 (stored as uint16 bit patterns); the network
-// input has its 2 channels (depth / 4 m, valid mask) padded to 8.  Conv
+// input has its 3 channels (depth / 4 m, valid mask, deviation from the 3x3
+// valid mean in 5 cm units) padded to 8.  Conv
 // weights are kept as fp32 master copies in the parameter vector (per layer
 // W[cout][3][3][cin] then b[cout], layers in forward order) and packed to
 // bf16 GEMM operands: G[cout][KP] with k = tap * CINP + ci (KP = 9 CINP
@@ -19,7 +20,8 @@ namespace tsdf {
 namespace nn {
 
 constexpr int kLayers = 8;              // e1 e2 e3 e4 d3 d2 d1 head
-constexpr float kDepthScale = 4.0f;     // metres
+constexpr float kDepthScale = 4.0f;     // metres: input normalisation (d / 4 m)
+constexpr float kCorrScale = 0.05f;     // metres: unit of the head's depth correction
 
 struct LayerDesc {
     int cin, cinp, cout, stride, up;    // up: the conv reads up2(source)
@@ -47,7 +49,7 @@ Net make_net();
 inline int act_channels(int a) { static const int c[kActs] = {8, 32, 64, 64, 128, 64, 64, 32}; return c[a]; }
 inline int act_scale(int a) { static const int s[kActs] = {1, 1, 2, 4, 8, 4, 2, 1}; return s[a]; }
 
-hipError_t launch_make_input(const void *depth, int fmt, int n_pix, uint16_t *x, float *dm, hipStream_t s);
+hipError_t launch_make_input(const void *depth, int fmt, int N, int H, int W, uint16_t *x, float *dm, hipStream_t s);
 hipError_t launch_pack(const Net &net, const float *params, uint16_t *g, uint16_t *t, hipStream_t s);
 hipError_t launch_conv_fwd(int layer, const uint16_t *in, int Hs, int Ws, const uint16_t *g, const float *bias,
                            const uint16_t *skip, uint16_t *out, int N, int Ho, int Wo, hipStream_t s);

@@ -53,21 +53,44 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
 }  // namespace
 
 // ============================================================================
-// input packing: depth -> metres and (d / 4, valid, 0 x 6) bf16
+// input packing: depth -> metres and (d / 4, valid, hp, 0 x 5) bf16, where
+// hp = (d - mean of the valid 3x3 neighbours) / 5 cm on valid pixels
 // ============================================================================
 template <int FMT>
-__global__ __launch_bounds__(256) void k_make_input(const void *depth, int n, uint16_t *x, float *dm)
+__device__ __forceinline__ float depth_at(const void *depth, size_t i)
 {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= n) return;
     float d;
     if (FMT == TF_DEPTH_U16_MM)
-        d = (float)reinterpret_cast<const uint16_t *>(depth)[p] / 1000.0f;
+        d = (float)reinterpret_cast<const uint16_t *>(depth)[i] / 1000.0f;
     else
-        d = reinterpret_cast<const float *>(depth)[p];
-    if (!(d > 0.0f)) d = 0.0f;
+        d = reinterpret_cast<const float *>(depth)[i];
+    return d > 0.0f ? d : 0.0f;
+}
+
+template <int FMT>
+__global__ __launch_bounds__(256) void k_make_input(const void *depth, int N, int H, int W, uint16_t *x, float *dm)
+{
+    const long p = (long)blockIdx.x * 256 + threadIdx.x;
+    if (p >= (long)N * H * W) return;
+    const int n = (int)(p / ((long)H * W));
+    const int rem = (int)(p - (long)n * H * W);
+    const int y = rem / W, xx = rem - (rem / W) * W;
+    const float d = depth_at<FMT>(depth, (size_t)p);
+    float s = 0.0f, c = 0.0f;
+    for (int ky = -1; ky <= 1; ++ky)
+        for (int kx = -1; kx <= 1; ++kx) {
+            const int yy = y + ky, xk = xx + kx;
+            if (yy < 0 || yy >= H || xk < 0 || xk >= W) continue;
+            const float v = depth_at<FMT>(depth, ((size_t)n * H + yy) * W + xk);
+            if (v > 0.0f) {
+                s += v;
+                c += 1.0f;
+            }
+        }
+    const float hp = d > 0.0f ? (d - s / c) / kCorrScale : 0.0f;
     dm[p] = d;
-    u32x4 v = {(uint32_t)f2bf(d * 0.25f) | ((uint32_t)(d > 0.0f ? f2bf(1.0f) : 0u) << 16), 0u, 0u, 0u};
+    u32x4 v = {(uint32_t)f2bf(d * 0.25f) | ((uint32_t)(d > 0.0f ? f2bf(1.0f) : 0u) << 16), (uint32_t)f2bf(hp), 0u,
+               0u};
     *reinterpret_cast<u32x4 *>(x + (size_t)p * 8) = v;
 }
 
@@ -348,7 +371,7 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float *partial, cons
 }
 
 // ============================================================================
-// head: delta = conv(d1, 32 -> 1); out = d + 4 m delta on valid pixels
+// head: delta = conv(d1, 32 -> 1); out = d + 5 cm delta on valid pixels
 // ============================================================================
 __global__ __launch_bounds__(256) void k_head_fwd(const uint16_t *d1, const float *w, const float *b,
                                                   const float *dm, float *out, int N, int H, int W)
@@ -375,7 +398,7 @@ __global__ __launch_bounds__(256) void k_head_fwd(const uint16_t *d1, const floa
         }
     }
     const float d = dm[p];
-    out[p] = d > 0.0f ? d + kDepthScale * s : 0.0f;
+    out[p] = d > 0.0f ? d + kCorrScale * s : 0.0f;
 }
 
 // masked L1: count, then gradient and sum, then the mean
@@ -405,7 +428,7 @@ __global__ __launch_bounds__(256) void k_loss_grad(const float *out, const float
             g = diff > 0.0f ? inv_n : (diff < 0.0f ? -inv_n : 0.0f);
             atomicAdd(&s, diff < 0.0f ? -diff : diff);
         }
-        ddelta[p] = kDepthScale * g;
+        ddelta[p] = kCorrScale * g;
     }
     __syncthreads();
     if (threadIdx.x == 0) atomicAdd(sum, s);
@@ -520,12 +543,13 @@ __global__ __launch_bounds__(256) void k_adam(float *p, const float *g, float *m
 // ============================================================================
 static dim3 grid1(long n, int per) { return dim3((unsigned)((n + per - 1) / per)); }
 
-hipError_t launch_make_input(const void *depth, int fmt, int n_pix, uint16_t *x, float *dm, hipStream_t s)
+hipError_t launch_make_input(const void *depth, int fmt, int N, int H, int W, uint16_t *x, float *dm, hipStream_t s)
 {
+    const dim3 g = grid1((long)N * H * W, 256);
     if (fmt == TF_DEPTH_U16_MM)
-        hipLaunchKernelGGL(k_make_input<TF_DEPTH_U16_MM>, grid1(n_pix, 256), dim3(256), 0, s, depth, n_pix, x, dm);
+        hipLaunchKernelGGL(k_make_input<TF_DEPTH_U16_MM>, g, dim3(256), 0, s, depth, N, H, W, x, dm);
     else
-        hipLaunchKernelGGL(k_make_input<TF_DEPTH_F32_M>, grid1(n_pix, 256), dim3(256), 0, s, depth, n_pix, x, dm);
+        hipLaunchKernelGGL(k_make_input<TF_DEPTH_F32_M>, g, dim3(256), 0, s, depth, N, H, W, x, dm);
     return hipGetLastError();
 }
 
@@ -624,7 +648,7 @@ hipError_t launch_conv_wgrad(int layer, const uint16_t *gpre, const uint16_t *in
     const dim3 gr(9, nc), b(256);
     int cout = 0, cin = 0, cinp = 0;
     switch (layer) {
-    case 0: cout = 32; cin = 2; cinp = 8; pb += (size_t)nc * 32 * 9 * 8;
+    case 0: cout = 32; cin = 3; cinp = 8; pb += (size_t)nc * 32 * 9 * 8;
         hipLaunchKernelGGL((k_conv_wgrad<8, 32, 1, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per); break;
     case 1: cout = 64; cin = cinp = 32; pb += (size_t)nc * 64 * 9 * 32;
         hipLaunchKernelGGL((k_conv_wgrad<32, 64, 2, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per); break;

@@ -139,7 +139,8 @@ struct Timed {
     hipStream_t s;
     Timed(tf_ctx *ctx, int kind, hipStream_t st) : P(ctx->prof), k(kind), slot(-1), s(st)
     {
-        if (!P.on) return;
+        if (!P.on || !((P.mask >> k) & 1u)) return;
+        if (P.seen[k]++ % P.every) return;
         slot = P.next[k];
         if (harvest(P, k, slot) != hipSuccess) {
             slot = -1;
@@ -328,6 +329,15 @@ int tf_profile_enable(tf_ctx *ctx, int on)
         P.created = true;
     }
     P.on = on != 0;
+    return TF_OK;
+}
+
+int tf_profile_select(tf_ctx *ctx, uint32_t class_mask, uint32_t every)
+{
+    if (!ctx || every < 1) return TF_E_INVAL;
+    ctx->prof.mask = class_mask;
+    ctx->prof.every = every;
+    for (int k = 0; k < TF_K_COUNT; ++k) ctx->prof.seen[k] = 0;
     return TF_OK;
 }
 

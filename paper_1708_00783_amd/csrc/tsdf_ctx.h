@@ -17,6 +17,9 @@ struct Profiler {
     int next[TF_K_COUNT] = {};
     uint64_t launches[TF_K_COUNT] = {};
     double ms[TF_K_COUNT] = {};
+    uint32_t mask = ~0u;              // kernel classes timed
+    uint32_t every = 1;               // time every n-th launch of a class
+    uint64_t seen[TF_K_COUNT] = {};   // launches of each class while on
 };
 
 struct tf_ctx {

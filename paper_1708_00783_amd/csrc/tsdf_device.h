@@ -552,10 +552,12 @@ __device__ __forceinline__ void integrate_body(const Vol &v, const Cam &c, float
 // search range (Sec. 4.4): the projected box and camera-z range of a block
 // ============================================================================
 // Box of the cube with voxel corner (x0, y0, z0) and edge `span` voxels, seen
-// by camera matrix M (12 floats) with the intrinsics of c: the pixel box of
-// its corner projections (floor/ceil, clipped to the image) and the corners'
-// camera-z range; a cube reaching closer than kZNear covers the whole image
-// from kZNear.  False when it lies behind the near plane or off the image.
+// by camera matrix M (12 floats) with the intrinsics of c: the pixel box
+// (floor/ceil, clipped to the image) of the projections of the cube's part
+// beyond the near plane -- its corners there and the points where its edges
+// cross the plane -- and the corners' camera-z range, starting at the plane
+// for a cube that reaches closer.  False when the cube lies entirely closer
+// than the plane or off the image.
 __device__ __forceinline__ bool cube_record(const float *M, const Cam &c, float voxel, int x0, int y0, int z0,
                                             int span, Rec &r)
 {
@@ -571,24 +573,35 @@ __device__ __forceinline__ bool cube_record(const float *M, const Cam &c, float 
         if (zs[k] > zhi) zhi = zs[k];
     }
     if (zhi < kZNear) return false;
-    if (zlo < kZNear) {
-        r.x0 = 0;
-        r.y0 = 0;
-        r.x1 = (int16_t)(c.W - 1);
-        r.y1 = (int16_t)(c.H - 1);
-        r.zlo = kZNear;
-        r.zhi = zhi;
-        return true;
-    }
     float umin = __builtin_inff(), umax = -__builtin_inff(), vmin = __builtin_inff(), vmax = -__builtin_inff();
     for (int k = 0; k < 8; ++k) {
-        float rz = 1.0f / zs[k];
-        float u = (c.fx * xs[k]) * rz + c.cx;
-        float vv = (c.fy * ys[k]) * rz + c.cy;
-        if (u < umin) umin = u;
-        if (u > umax) umax = u;
-        if (vv < vmin) vmin = vv;
-        if (vv > vmax) vmax = vv;
+        if (zs[k] < kZNear) continue;
+        const float rz = 1.0f / zs[k];
+        const float u = (c.fx * xs[k]) * rz + c.cx;
+        const float vv = (c.fy * ys[k]) * rz + c.cy;
+        umin = u < umin ? u : umin;
+        umax = u > umax ? u : umax;
+        vmin = vv < vmin ? vv : vmin;
+        vmax = vv > vmax ? vv : vmax;
+    }
+    if (zlo < kZNear) {
+        const float rzn = 1.0f / kZNear;
+        for (int a = 0; a < 8; ++a)
+            for (int bit = 1; bit < 8; bit <<= 1) {
+                if (a & bit) continue;
+                const int b = a | bit;   // the edge from corner a to corner b
+                if ((zs[a] < kZNear) == (zs[b] < kZNear)) continue;
+                const float t = (kZNear - zs[a]) / (zs[b] - zs[a]);
+                const float xe = xs[a] + t * (xs[b] - xs[a]);
+                const float ye = ys[a] + t * (ys[b] - ys[a]);
+                const float u = (c.fx * xe) * rzn + c.cx;
+                const float vv = (c.fy * ye) * rzn + c.cy;
+                umin = u < umin ? u : umin;
+                umax = u > umax ? u : umax;
+                vmin = vv < vmin ? vv : vmin;
+                vmax = vv > vmax ? vv : vmax;
+            }
+        zlo = kZNear;
     }
     float fx0 = floorf(umin), fx1 = ceilf(umax), fy0 = floorf(vmin), fy1 = ceilf(vmax);
     if (fx0 < 0.0f) fx0 = 0.0f;

@@ -180,12 +180,11 @@ __global__ __launch_bounds__(256) void k_m_clear(MTiles t)
 // ============================================================================
 namespace {
 
-// LDS of one tile: a chunk of bin records, the (submap, block) -> pointer
-// table, and the tile's submaps in ascending order with what the field reads
+// LDS of one tile: the (submap, block) -> pointer table, the tile's submaps
+// in ascending order with what the field reads, and the per-pixel range
 template <int NT>
 struct MTileLds {
     static constexpr int TT = 4 * NT;           // table slots
-    Rec chunk[NT];
     unsigned long long key[TT];                 // 0 = empty
     int ptr[TT];
     float Rs[kMaxSubmaps][12];                  // rotation rows, then translation (voxel units)
@@ -196,6 +195,8 @@ struct MTileLds {
     int smid[kMaxSubmaps];
     unsigned long long mask;
     uint32_t n_tab, hits;
+    uint32_t zlo[NT], zhi[NT];                  // per-pixel range as float bits (all values > 0)
+    uint32_t zlo_all, zhi_all;                  // from records covering the whole tile
 };
 
 template <int NT>
@@ -209,56 +210,64 @@ __device__ __forceinline__ unsigned long long mkey(int sm, int bx, int by, int b
     return pack_key(bx, by, bz) | ((unsigned long long)sm << 49);
 }
 
-// Search range of the pixel and the tile's LDS state from its bin.  Every
-// thread of the workgroup calls it.
-template <int NT>
-__device__ __forceinline__ void m_tile_setup(const MSub *subs, const MTiles &t, uint32_t g, int px, int py,
-                                             float &zmin, float &zmax, MTileLds<NT> &L)
+// Search range of the pixel and the tile's LDS state from its bin.  The range
+// is a min/max over the records covering the pixel: each record updates the
+// pixels of its box inside the tile with LDS atomics (positive floats order
+// like their bit patterns); a record covering the whole tile updates one
+// tile-wide pair instead.  Every thread of the workgroup calls it; pixel
+// (px, py) is the calling thread's, the tile spans [tx0, tx0 + TW) x [ty0, ty0 + TH).
+template <int NT, int TW, int TH>
+__device__ __forceinline__ void m_tile_setup(const MSub *subs, const MTiles &t, uint32_t g, int tx0, int ty0,
+                                             MTileLds<NT> &L)
 {
     constexpr int TT = MTileLds<NT>::TT;
-    zmin = __builtin_inff();
-    zmax = -__builtin_inff();
     for (int k = threadIdx.x; k < TT; k += NT) L.key[k] = 0ull;
+    L.zlo[threadIdx.x] = 0x7f800000u;   // +inf
+    L.zhi[threadIdx.x] = 0u;            // below every positive float
     if (threadIdx.x == 0) {
         L.mask = 0ull;
         L.n_tab = 0u;
         L.hits = 0u;
+        L.zlo_all = 0x7f800000u;
+        L.zhi_all = 0u;
     }
     const uint32_t o0 = t.off[g];
     uint32_t o1 = t.off[g + 1];
     if (o1 > t.cap) o1 = t.cap;
     const int n = o1 > o0 ? (int)(o1 - o0) : 0;
     __syncthreads();
-    for (int base = 0; base < n; base += NT) {
-        const int j = base + (int)threadIdx.x;
-        if (j < n) {
-            const Rec r = t.bins[o0 + (uint32_t)j];
-            L.chunk[threadIdx.x] = r;
-            atomicOr(&L.mask, 1ull << (uint32_t)r.pad);
-            // keys in one bin are distinct; keep the table at most half full
-            if (atomicAdd(&L.n_tab, 1u) < (uint32_t)(TT / 2)) {
-                const unsigned long long key = mkey(r.pad, r.bx, r.by, r.bz);
-                uint32_t sl = mslot<NT>(r.pad, r.bx, r.by, r.bz);
-                for (int k = 0; k < TT; ++k) {
-                    if (atomicCAS(&L.key[sl], 0ull, key) == 0ull) {
-                        L.ptr[sl] = r.ptr;
-                        break;
-                    }
-                    sl = (sl + 1u) & (uint32_t)(TT - 1);
+    for (int j = (int)threadIdx.x; j < n; j += NT) {
+        const Rec r = t.bins[o0 + (uint32_t)j];
+        atomicOr(&L.mask, 1ull << (uint32_t)r.pad);
+        // keys in one bin are distinct; keep the table at most half full
+        if (atomicAdd(&L.n_tab, 1u) < (uint32_t)(TT / 2)) {
+            const unsigned long long key = mkey(r.pad, r.bx, r.by, r.bz);
+            uint32_t sl = mslot<NT>(r.pad, r.bx, r.by, r.bz);
+            for (int k = 0; k < TT; ++k) {
+                if (atomicCAS(&L.key[sl], 0ull, key) == 0ull) {
+                    L.ptr[sl] = r.ptr;
+                    break;
                 }
+                sl = (sl + 1u) & (uint32_t)(TT - 1);
             }
         }
-        __syncthreads();
-        const int m = (n - base) < NT ? (n - base) : NT;
-        for (int k = 0; k < m; ++k) {
-            const Rec r = L.chunk[k];
-            if (px >= r.x0 && px <= r.x1 && py >= r.y0 && py <= r.y1) {
-                if (r.zlo < zmin) zmin = r.zlo;
-                if (r.zhi > zmax) zmax = r.zhi;
-            }
+        const int x0 = r.x0 > tx0 ? r.x0 : tx0, x1 = r.x1 < tx0 + TW - 1 ? r.x1 : tx0 + TW - 1;
+        const int y0 = r.y0 > ty0 ? r.y0 : ty0, y1 = r.y1 < ty0 + TH - 1 ? r.y1 : ty0 + TH - 1;
+        if (x0 > x1 || y0 > y1) continue;
+        const uint32_t lo = __float_as_uint(r.zlo), hi = __float_as_uint(r.zhi);
+        if (x0 == tx0 && x1 == tx0 + TW - 1 && y0 == ty0 && y1 == ty0 + TH - 1) {
+            atomicMin(&L.zlo_all, lo);
+            atomicMax(&L.zhi_all, hi);
+            continue;
         }
-        __syncthreads();
+        for (int y = y0; y <= y1; ++y)
+            for (int x = x0; x <= x1; ++x) {
+                const int pi = (y - ty0) * TW + (x - tx0);
+                atomicMin(&L.zlo[pi], lo);
+                atomicMax(&L.zhi[pi], hi);
+            }
     }
+    __syncthreads();
     // the tile's submaps, ascending
     if (threadIdx.x < (unsigned)kMaxSubmaps) {
         const unsigned long long m = L.mask;
@@ -277,6 +286,16 @@ __device__ __forceinline__ void m_tile_setup(const MSub *subs, const MTiles &t, 
         }
     }
     __syncthreads();
+}
+
+// the calling thread's pixel range after m_tile_setup (pixel index pi in the tile)
+template <int NT>
+__device__ __forceinline__ void m_pixel_range(const MTileLds<NT> &L, int pi, float &zmin, float &zmax)
+{
+    const uint32_t lo = L.zlo[pi] < L.zlo_all ? L.zlo[pi] : L.zlo_all;
+    const uint32_t hi = L.zhi[pi] > L.zhi_all ? L.zhi[pi] : L.zhi_all;
+    zmin = __uint_as_float(lo);                               // +inf when nothing covers the pixel
+    zmax = hi ? __uint_as_float(hi) : -__builtin_inff();
 }
 
 // device pointer of block (bx, by, bz) of the k-th submap of the tile (-1 =
@@ -424,10 +443,12 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
     const int tile = g - V.tile_base;
     const int W = V.cam.W, H = V.cam.H;
     const int q = (int)threadIdx.x >> 6, i = (int)threadIdx.x & 63;
-    const int px = (tile % V.ntx) * TW + (q % (TW / 8)) * 8 + (i & 7);
-    const int py = (tile / V.ntx) * TH + (q / (TW / 8)) * 8 + (i >> 3);
+    const int tx0 = (tile % V.ntx) * TW, ty0 = (tile / V.ntx) * TH;
+    const int lx = (q % (TW / 8)) * 8 + (i & 7), ly = (q / (TW / 8)) * 8 + (i >> 3);
+    const int px = tx0 + lx, py = ty0 + ly;
     float zmin, zmax;
-    m_tile_setup<NT>(subs, t, (uint32_t)g, px, py, zmin, zmax, L);
+    m_tile_setup<NT, TW, TH>(subs, t, (uint32_t)g, tx0, ty0, L);
+    m_pixel_range<NT>(L, ly * TW + lx, zmin, zmax);
     const int ns = __popcll(L.mask);
     const bool inside = px < W && py < H;
     float4 out_p = make_float4(0.f, 0.f, 0.f, 0.f), out_n = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -520,10 +541,12 @@ __global__ __launch_bounds__(TW *TH) void k_m_range_write(const MSub *subs, cons
     const int g = V.tile_base + (int)blockIdx.x;
     const int tile = (int)blockIdx.x;
     const int q = (int)threadIdx.x >> 6, i = (int)threadIdx.x & 63;
-    const int px = (tile % V.ntx) * TW + (q % (TW / 8)) * 8 + (i & 7);
-    const int py = (tile / V.ntx) * TH + (q / (TW / 8)) * 8 + (i >> 3);
+    const int tx0 = (tile % V.ntx) * TW, ty0 = (tile / V.ntx) * TH;
+    const int lx = (q % (TW / 8)) * 8 + (i & 7), ly = (q / (TW / 8)) * 8 + (i >> 3);
+    const int px = tx0 + lx, py = ty0 + ly;
     float zmin, zmax;
-    m_tile_setup<NT>(subs, t, (uint32_t)g, px, py, zmin, zmax, L);
+    m_tile_setup<NT, TW, TH>(subs, t, (uint32_t)g, tx0, ty0, L);
+    m_pixel_range<NT>(L, ly * TW + lx, zmin, zmax);
     if (px >= V.cam.W || py >= V.cam.H) return;
     zmin_out[(size_t)py * V.cam.W + px] = zmin;
     zmax_out[(size_t)py * V.cam.W + px] = zmax;

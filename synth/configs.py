@@ -260,7 +260,7 @@ def c3_frame(k: int, seed_index: int = 0, noise: bool = True, intr: Intrinsics =
 
 
 # ---- C4: batched rigid submaps ------------------------------------------------------
-C4_VOLUME = VolumeParams(0.005, 0.02, 100, 1 << 18, 1 << 16, 1 << 17)
+C4_VOLUME = VolumeParams(0.005, 0.02, 100, 1 << 19, 1 << 17, 1 << 18)
 C4_N_SUBMAPS = 64
 C4_BLOCKS = (2000, 60000)                  # log-uniform target block counts
 C4_PREFILL_INTR = Intrinsics(262.5, 262.5, 159.5, 119.5, 320, 240)

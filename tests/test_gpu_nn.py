@@ -7,7 +7,10 @@ the only differences are accumulation order and the final bf16 rounding:
 outputs within 1 bf16 ulp-scale (0.8% relative plus a small absolute floor),
 weight gradients within 1e-3 relative.  End to end against the float64
 oracle on bf16-rounded weights and input: per-layer gradient cosine >= 0.999.
-Adam matches the oracle's update; a zero head is the identity exactly."""
+Adam matches the oracle's update; a zero head is the identity exactly.
+The end-to-end comparison runs the oracle with bf16 rounding of everything the
+kernels store in bf16, so both sides take their relu decisions on the same
+values; without it, decisions at near-zero sums differ and compound."""
 import numpy as np
 import pytest
 
@@ -32,7 +35,10 @@ def _setup(seed=0):
             P[k] = rng.standard_normal(P[k].shape) * 0.05
     P["head.w"] = rng.standard_normal(P["head.w"].shape) * 0.05
     P = {k: v.astype(np.float32).astype(np.float64) for k, v in P.items()}
-    depth = rng.uniform(0.4, 3.8, (N, H, W)).astype(np.float32)
+    # a smooth surface with depth-sensor-like noise and holes (realistic input scale)
+    yy, xx = np.mgrid[0:H, 0:W]
+    depth = np.stack([1.2 + 1.5 * n + 0.3 * np.sin(xx / (7.0 + n)) + 0.2 * np.cos(yy / 5.0) for n in range(N)])
+    depth = (depth + rng.normal(0, 0.004, depth.shape)).astype(np.float32)
     depth[0, 5:9, 10:20] = 0.0
     depth[1, :, :3] = 0.0
     target = (depth + rng.normal(0, 0.02, depth.shape)).astype(np.float32)
@@ -69,11 +75,13 @@ def test_forward_layers_match_oracle():
     T, net, P, depth, target, out = _setup(1)
     x = _bf(net, "input")
     assert np.array_equal(x[..., 0], D.to_bf16(depth * 0.25)) and np.array_equal(x[..., 1], (depth > 0) * 1.0)
-    assert not x[..., 2:].any()
+    hp = D.make_input(depth.astype(np.float64))[..., 2]
+    assert np.allclose(x[..., 2], hp, rtol=8e-3, atol=1e-4)
+    assert not x[..., 3:].any()
     for name, (src, stride, up, skip) in LAYER_IO.items():
         a = _bf(net, src)
         if name == "e1":
-            a = a[..., :2]
+            a = a[..., :3]
         if up:
             a = D.up2(a)
         ref = D.conv(a, _rb(P[name + ".w"]), P[name + ".b"], stride)
@@ -84,7 +92,7 @@ def test_forward_layers_match_oracle():
         _log(f"{name}: ok, {ref.shape}, max {ref.max():.3g}")
     d1 = _bf(net, "d1")
     delta = D.conv(d1, P["head.w"], P["head.b"])[..., 0]
-    ref = np.where(depth > 0, depth + 4.0 * delta, 0.0)
+    ref = np.where(depth > 0, depth + D.CORRECTION_SCALE * delta, 0.0)
     got = out.cpu().numpy()
     assert np.abs(got - ref).max() < 1e-5
     assert np.all(got[depth == 0] == 0)
@@ -97,8 +105,8 @@ def test_backward_layers_match_oracle():
     o = out.cpu().numpy().astype(np.float64)
     l_ref, g_ref, n_ref = D.loss_and_grad_out(o, depth, target)
     assert int(loss[1]) == n_ref and abs(loss[0] - l_ref) < 1e-5 * max(1.0, l_ref)
-    dd = net.tensor("ddelta").cpu().numpy().astype(np.float64)
-    assert np.allclose(dd, np.where(depth > 0, 4.0 * g_ref, 0), rtol=1e-6, atol=1e-12)
+    dd = net.tensor("ddelta").cpu().numpy().astype(np.float64).reshape(N, H, W)
+    assert np.allclose(dd, np.where(depth > 0, D.CORRECTION_SCALE * g_ref, 0), rtol=1e-6, atol=1e-12)
     grads = T.nn_unflatten(net.tensor("grads").cpu().numpy().reshape(-1))
     # head: gradient at d1 and head parameters
     d1 = _bf(net, "d1")
@@ -112,7 +120,7 @@ def test_backward_layers_match_oracle():
         g = _bf(net, "grad_" + name)
         a = _bf(net, src)
         if name == "e1":
-            a = a[..., :2]
+            a = a[..., :3]
         a_in = D.up2(a) if up else a
         wb = _rb(P[name + ".w"])
         dx, dw, db = D.conv_backward(a_in, wb, g, stride)
@@ -137,7 +145,8 @@ def test_end_to_end_gradient_cosine():
     torch.cuda.synchronize()
     grads = T.nn_unflatten(net.tensor("grads").cpu().numpy().reshape(-1))
     Pb = {k: (_rb(v) if k.endswith(".w") and not k.startswith("head") else v) for k, v in P.items()}
-    o, c = D.forward(Pb, depth.astype(np.float64))
+    # the oracle at the kernels' storage precision: bf16 input, activations and gradients
+    o, c = D.forward(Pb, depth.astype(np.float64), q=lambda a: D.to_bf16(a).astype(np.float64))
     _, g, _ = D.loss_and_grad_out(o, depth, target)
     G = D.backward(Pb, c, g)
     for k in G:
@@ -157,7 +166,7 @@ def test_adam_matches_oracle():
     net.adam_step(1e-3, 0.9, 0.999, 1e-8)
     p1 = net.get_params().cpu().numpy().astype(np.float64)
     Po, st = {"p": p0.copy()}, {}
-    D.adam_step(Po, {"p": g}, st, 1)
+    D.adam_step(Po, {"p": g}, st, 1, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8)
     assert np.abs(p1 - Po["p"]).max() < 1e-6
     # the forward pass uses the updated weights
     net.forward(torch.from_numpy(depth).cuda())
@@ -196,11 +205,12 @@ def test_training_reduces_loss():
     noisy = torch.from_numpy((base + rng.normal(0, 0.01, base.shape)).astype(np.float32)).cuda()
     clean = torch.from_numpy(base).cuda()
     losses = []
-    for it in range(100):
+    for it in range(150):
         net.forward(noisy)
         loss = net.backward(clean)
-        net.adam_step(1e-3)
+        net.adam_step(2e-4)
         losses.append(float(loss[0].item()))
     _log("loss", losses[:3], losses[-3:])
     assert np.isfinite(losses).all()
-    assert np.mean(losses[-10:]) < 0.8 * losses[0]
+    # the untrained prefilter is the identity: its loss is the raw noise; training lowers it
+    assert np.mean(losses[-10:]) < 0.9 * losses[0]

@@ -124,8 +124,22 @@ def test_bf16_rounding():
 
 
 def test_parameter_count():
-    # 608 + 18496 + 36928 + 73856 + 73792 + 36928 + 18464 + 289
-    assert D.n_params(D.init_params()) == 259361
+    # 896 + 18496 + 36928 + 73856 + 73792 + 36928 + 18464 + 289
+    assert D.n_params(D.init_params()) == 259649
+
+
+def test_input_channels():
+    d = np.array([[[1.0, 1.0, 0.0, 2.0],
+                   [1.0, 1.3, 1.0, 2.0],
+                   [0.0, 1.0, 1.0, 2.0]]])
+    x = D.make_input(d)
+    assert np.array_equal(x[..., 0], d / 4) and np.array_equal(x[..., 1], (d > 0) * 1.0)
+    # pixel (1, 1): valid 3x3 neighbours 1, 1, 1, 1.3, 1, 1, 1 (two holes) -> mean 7.3 / 7
+    assert np.isclose(x[0, 1, 1, 2], (1.3 - 7.3 / 7) / 0.05)
+    # corner (0, 0): neighbours 1, 1, 1, 1.3 -> mean 4.3 / 4; a hole stays 0
+    assert np.isclose(x[0, 0, 0, 2], (1.0 - 4.3 / 4) / 0.05) and x[0, 0, 2, 2] == 0
+    # a constant valid patch has zero deviation
+    assert np.allclose(D.make_input(np.full((1, 5, 5), 2.5))[..., 2], 0)
 
 
 def test_activation_shapes_and_skips():

@@ -225,3 +225,42 @@ def test_range_for_foreign_pose_uses_all_blocks(oracle_mod):
     assert np.all(cov_all[cov_vis])
     assert np.all(zmin_all[cov_vis] <= zmin_vis[cov_vis])
     assert np.all(zmax_all[cov_vis] >= zmax_vis[cov_vis])
+
+
+def test_range_clips_blocks_at_the_near_plane(oracle_mod):
+    """A block straddling the near plane covers only the pixels of its part
+    beyond the plane: one far to the side of the view covers none, and for
+    cameras close to the surface every point of every block beyond the plane
+    still falls inside its pixel's search interval."""
+    vol, d, p, intr, scene = _c1_volume(oracle_mod)
+    pos, _, ptr = vol.entries()
+    blocks = pos[ptr >= 0].astype(np.float64)
+    # pick a block; put the camera so the block spans camera z 0.05 at x = +0.5 m
+    b = blocks[len(blocks) // 2]
+    centre = (8.0 * b + 4.0) * VP.voxel_size
+    M = np.eye(4)
+    M[:3, 3] = -centre + np.array([0.5, 0.0, 0.05])        # world -> camera: pure translation
+    one = np.array([np.flatnonzero(ptr >= 0)[len(blocks) // 2]], np.int32)
+    zmin, zmax = vol.range_image(K.width, K.height, intr.as_array(), M.astype(np.float32), blocks=list(one))
+    assert not np.any(zmin <= zmax)      # the old whole-image rule would cover every pixel
+    # containment with cameras right at the surface
+    rng = np.random.default_rng(11)
+    for P in (p[-1], p[0]):
+        Mc = P.astype(np.float64).copy()
+        # slide the camera 1.15 m forward along its axis: about 5 cm from the sphere
+        Mc[2, 3] -= 1.15
+        zmin, zmax = vol.range_image(K.width, K.height, intr.as_array(), Mc.astype(np.float32), blocks="all")
+        n = 0
+        for i in np.flatnonzero(ptr >= 0):
+            pts = (8.0 * pos[i].astype(np.float64) + rng.uniform(0, 8, size=(8, 3))) * VP.voxel_size
+            c = pts @ Mc[:3, :3].T + Mc[:3, 3]
+            z = c[:, 2]
+            f = z > 0.06
+            u = K.fx * c[f, 0] / z[f] + K.cx
+            v = K.fy * c[f, 1] / z[f] + K.cy
+            ins = (u >= 0) & (u <= K.width - 1) & (v >= 0) & (v <= K.height - 1)
+            for uu, vv, zz in zip(u[ins], v[ins], z[f][ins]):
+                px, py = int(round(uu)), int(round(vv))
+                assert zmin[py, px] <= zz + 1e-5 and zz - 1e-5 <= zmax[py, px]
+                n += 1
+        assert n > 200
