@@ -35,6 +35,30 @@ N_TRAJ = 300
 PROFILE_EVERY = 8
 
 
+KERNEL_SOURCES = ("paper_1708_00783_amd/csrc/tsdf_device.h", "paper_1708_00783_amd/csrc/tsdf_kernels.hip",
+                  "paper_1708_00783_amd/csrc/tsdf_internal.h", "paper_1708_00783_amd/csrc/tsdf_multi.hip")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summaries
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), only if they were taken with
+    the current kernel sources; else None"""
+    import glob
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    sha = h.hexdigest()[:16]
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(f):
+            m = re.match(r"traffic (\S+) ([0-9a-f]{16}) (\d+)", line.strip())
+            if m and m.group(1) == kernel and m.group(2) == sha:
+                return int(m.group(3))
+    return None
+
+
 def _gen(k):
     from synth import configs
     return configs.c2_frame(k)
@@ -50,11 +74,20 @@ def _gen_prefill(ij):
     return configs.c4_prefill_frame(*ij)
 
 
+def _one_thread():
+    """render workers: one BLAS/OpenMP thread each (the pool supplies the parallelism)"""
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
 def pmap(fn, items, workers):
     if workers <= 1:
         return [fn(x) for x in items]
     import multiprocessing as mp
-    with mp.get_context("fork").Pool(workers) as pool:
+    with mp.get_context("fork").Pool(workers, initializer=_one_thread) as pool:
         return pool.map(fn, items, chunksize=max(1, len(items) // (4 * workers)))
 
 
@@ -227,7 +260,7 @@ def render_rooms(seeds, n, workers, tag):
     import multiprocessing as mp
     items = [(s, k) for s in seeds for k in range(n)]
     out = []
-    with mp.get_context("fork").Pool(max(1, workers)) as pool:
+    with mp.get_context("fork").Pool(max(1, workers), initializer=_one_thread) as pool:
         for i, f in enumerate(pool.imap(_render_c5, items, chunksize=8)):
             out.append(f)
             if (i + 1) % 500 == 0:
@@ -239,8 +272,9 @@ def render_rooms(seeds, n, workers, tag):
 def run_c5(args):
     """Train the prefilter on pairs the method makes itself (fused-model
     raycasts as targets), then fuse held-out rooms with raw and with denoised
-    depth: e* = raw surface RMS after all frames; N_d = the first checkpoint
-    at which the denoised RMS <= e*; report the time each path takes."""
+    depth: e* = raw surface RMS with all frames fused; N_d = the smallest
+    frame count (every k-th frame of the whole trajectory) at which the
+    denoised RMS <= e*; report the time each path takes."""
     from synth import configs
     tr_seeds = list(range(5000, 5000 + args.c5_rooms))
     ev_seeds = list(range(6000, 6000 + args.c5_eval_rooms))
@@ -286,27 +320,25 @@ def run_c5(args):
     del inputs, targets
     inf = T.Denoiser(1, K.height, K.width)
     inf.set_params(params)
-    # held-out rooms
-    cps = sorted(set(list(range(25, ne + 1, 25)) + [ne]))
-    curves = {"raw": [], "denoised": []}
-    times = {"raw": [], "denoised": []}
+    # held-out rooms, equal-coverage protocol (every k-th frame of the whole trajectory)
+    res = {"raw": [], "denoised": []}
     for i, s in enumerate(ev_seeds):
         d = torch.from_numpy(eval_frames[i]).cuda()
         for name, nn in (("raw", None), ("denoised", inf)):
-            rms, tcum = PF.evaluate_room(s, d, nn, cps)
-            curves[name].append([rms[c] for c in cps])
-            times[name].append([tcum[c] for c in cps])
-        print(f"[bench] c5: room {s}: raw {curves['raw'][-1][-1] * 1e3:.3f} mm, denoised "
-              f"{curves['denoised'][-1][-1] * 1e3:.3f} mm after {ne} frames", file=sys.stderr, flush=True)
-    raw = np.mean(curves["raw"], axis=0)
-    den = np.mean(curves["denoised"], axis=0)
-    traw = np.mean(times["raw"], axis=0)
-    tden = np.mean(times["denoised"], axis=0)
+            res[name].append(PF.evaluate_room(s, d, nn))
+        print(f"[bench] c5: room {s}: raw {res['raw'][-1][ne][0] * 1e3:.3f} mm, denoised "
+              f"{res['denoised'][-1][ne][0] * 1e3:.3f} mm with all {ne} frames", file=sys.stderr, flush=True)
+    ns = sorted(res["raw"][0])
+    raw = np.array([np.mean([r[n][0] for r in res["raw"]]) for n in ns])
+    den = np.array([np.mean([r[n][0] for r in res["denoised"]]) for n in ns])
+    traw = np.array([np.mean([r[n][1] for r in res["raw"]]) for n in ns])
+    tden = np.array([np.mean([r[n][1] for r in res["denoised"]]) for n in ns])
     e_star = float(raw[-1])
     reach = [j for j, v in enumerate(den) if v <= e_star]
-    nd = cps[reach[0]] if reach else None
+    nd = ns[reach[0]] if reach else None
     t_plain = float(traw[-1])
     t_den = float(tden[reach[0]]) if reach else None
+    cps = ns
     out = {
         "metric": "denoised vs plain at equal surface RMS error (time to reach the plain path's error)",
         "value": round(t_plain / t_den, 4) if t_den else None, "unit": "x (T_plain(300) / T_denoised(N_d))",
@@ -321,9 +353,11 @@ def run_c5(args):
         "e_star_mm": round(e_star * 1e3, 4), "n_d": nd, "t_plain_s": round(t_plain, 4),
         "t_denoised_s": round(t_den, 4) if t_den else None,
         "frames_per_s_plain": round(ne / t_plain, 2),
-        "frames_per_s_denoised": round(float(cps[-1] / tden[-1]), 2),
-        "rms_mm": {"checkpoints": cps, "raw": [round(v * 1e3, 4) for v in raw],
+        "frames_per_s_denoised": round(float(ns[-1] / tden[-1]), 2),
+        "rms_mm": {"frames_fused": cps, "raw": [round(v * 1e3, 4) for v in raw],
                    "denoised": [round(v * 1e3, 4) for v in den]},
+        "protocol": "each N fuses every (300/N)-th frame of the whole trajectory into a fresh volume (equal "
+                    "coverage); RMS of the analytic SDF at the hits of every 10th pose, every 4th pixel",
         "train": {"loss_curve": [(a, round(b, 6)) for a, b, _ in losses], "seconds": round(t_train, 2),
                   "pairs_seconds": round(t_pairs, 2), "render_seconds": round(t_render, 2)},
     }
@@ -433,7 +467,8 @@ def main():
     dominant = max(("integrate", "raycast"), key=lambda k: total_ms[k])
     rk = kern[dominant]
     roofline = {"bound": "hbm", "achieved": round(rk["gbs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(rk["gbs"] / HBM_PEAK_GBS, 5), "traffic": None, "kernel": dominant,
+                "frac": round(rk["gbs"] / HBM_PEAK_GBS, 5), "traffic": measured_traffic("k_" + dominant),
+                "kernel": dominant,
                 "algorithmic_bytes_per_launch": int(rk["bytes"]),
                 "avg_launch_ms": round(rk["avg_ms"], 5)}
 

@@ -299,9 +299,13 @@ __device__ __forceinline__ void m_pixel_range(const MTileLds<NT> &L, int pi, flo
 }
 
 // device pointer of block (bx, by, bz) of the k-th submap of the tile (-1 =
-// absent): the LDS table first, then the submap's bucket bitmap and hash table
+// absent): the LDS table first; unless `local`, then the submap's bucket
+// bitmap and hash table.  `local` holds when the table has every record of
+// the tile's bin and the read belongs to a ray point at or beyond the near
+// plane: every block within 3 voxels of such a point is in the bin (blocks
+// are binned by their cube grown by 3 voxels), so a miss proves absence.
 template <int NT>
-__device__ __forceinline__ int m_lookup(const MTileLds<NT> &L, int k, int bx, int by, int bz)
+__device__ __forceinline__ int m_lookup(const MTileLds<NT> &L, int k, int bx, int by, int bz, bool local)
 {
     constexpr int TT = MTileLds<NT>::TT;
     if (!in_short_range(bx) || !in_short_range(by) || !in_short_range(bz)) return -1;
@@ -314,6 +318,7 @@ __device__ __forceinline__ int m_lookup(const MTileLds<NT> &L, int k, int bx, in
         if (kk == 0ull) break;
         sl = (sl + 1u) & (uint32_t)(TT - 1);
     }
+    if (local) return -1;
     const uint32_t h = hash_index(bx, by, bz, L.nb[k] - 1u);
     if (!((gload(L.occ[k] + (h >> 5)) >> (h & 31u)) & 1u)) return -1;
     int ptr = -1;
@@ -333,19 +338,19 @@ __device__ __forceinline__ void to_sub(const MTileLds<NT> &L, int k, float P0, f
 
 // "allocated" of the combined map: some submap has a device block at floor(P_i X)
 template <int NT>
-__device__ __forceinline__ bool m_allocated(const MTileLds<NT> &L, int ns, float P0, float P1, float P2)
+__device__ __forceinline__ bool m_allocated(const MTileLds<NT> &L, int ns, float P0, float P1, float P2, bool local)
 {
     for (int k = 0; k < ns; ++k) {
         float Q0, Q1, Q2;
         to_sub(L, k, P0, P1, P2, Q0, Q1, Q2);
-        if (m_lookup(L, k, block_of(Q0), block_of(Q1), block_of(Q2)) >= 0) return true;
+        if (m_lookup(L, k, block_of(Q0), block_of(Q1), block_of(Q2), local) >= 0) return true;
     }
     return false;
 }
 
 // combined field at world voxel-unit P
 template <int NT>
-__device__ __forceinline__ float m_field(const MTileLds<NT> &L, int ns, float P0, float P1, float P2)
+__device__ __forceinline__ float m_field(const MTileLds<NT> &L, int ns, float P0, float P1, float P2, bool local)
 {
     int cnt = 0;
     float first = 1.0f, num = 0.0f, den = 0.0f;
@@ -360,16 +365,16 @@ __device__ __forceinline__ float m_field(const MTileLds<NT> &L, int ns, float P0
         const int ix = (int)fbx, iy = (int)fby, iz = (int)fbz;
         const int Bx = ix >> 3, By = iy >> 3, Bz = iz >> 3;
         const bool sx = (ix & 7) == 7, sy = (iy & 7) == 7, sz = (iz & 7) == 7;
-        const int p000 = m_lookup(L, k, Bx, By, Bz);
+        const int p000 = m_lookup(L, k, Bx, By, Bz, local);
         int p100 = p000, p010 = p000, p001 = p000, p110 = p000, p101 = p000, p011 = p000, p111 = p000;
         if (sx | sy | sz) {
-            if (sx) p100 = m_lookup(L, k, Bx + 1, By, Bz);
-            if (sy) p010 = m_lookup(L, k, Bx, By + 1, Bz);
-            if (sz) p001 = m_lookup(L, k, Bx, By, Bz + 1);
-            p110 = (sx & sy) ? m_lookup(L, k, Bx + 1, By + 1, Bz) : (sx ? p100 : p010);
-            p101 = (sx & sz) ? m_lookup(L, k, Bx + 1, By, Bz + 1) : (sx ? p100 : p001);
-            p011 = (sy & sz) ? m_lookup(L, k, Bx, By + 1, Bz + 1) : (sy ? p010 : p001);
-            p111 = (sx & sy & sz) ? m_lookup(L, k, Bx + 1, By + 1, Bz + 1)
+            if (sx) p100 = m_lookup(L, k, Bx + 1, By, Bz, local);
+            if (sy) p010 = m_lookup(L, k, Bx, By + 1, Bz, local);
+            if (sz) p001 = m_lookup(L, k, Bx, By, Bz + 1, local);
+            p110 = (sx & sy) ? m_lookup(L, k, Bx + 1, By + 1, Bz, local) : (sx ? p100 : p010);
+            p101 = (sx & sz) ? m_lookup(L, k, Bx + 1, By, Bz + 1, local) : (sx ? p100 : p001);
+            p011 = (sy & sz) ? m_lookup(L, k, Bx, By + 1, Bz + 1, local) : (sy ? p010 : p001);
+            p111 = (sx & sy & sz) ? m_lookup(L, k, Bx + 1, By + 1, Bz + 1, local)
                                   : (sx & sy) ? p110 : (sx & sz) ? p101 : (sy & sz) ? p011 : sx ? p100 : sy ? p010 : p001;
         }
         C.p[0] = p000;
@@ -450,6 +455,7 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
     m_tile_setup<NT, TW, TH>(subs, t, (uint32_t)g, tx0, ty0, L);
     m_pixel_range<NT>(L, ly * TW + lx, zmin, zmax);
     const int ns = __popcll(L.mask);
+    const bool full = L.n_tab <= (uint32_t)(MTileLds<NT>::TT / 2);   // the table holds the whole bin
     const bool inside = px < W && py < H;
     float4 out_p = make_float4(0.f, 0.f, 0.f, 0.f), out_n = make_float4(0.f, 0.f, 0.f, 0.f);
     if (inside && zmin <= zmax) {
@@ -461,6 +467,7 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
         const float b = ((float)py - c.cy) / c.fy;
         const float nr = sqrtf((a * a + b * b) + 1.0f);
         const float rcx = a / nr, rcy = b / nr, rcz = 1.0f / nr;
+        const float zscale = voxel * rcz;   // camera z of ray parameter t (voxel units)
         const float dx = (c.Ri[0] * rcx + c.Ri[1] * rcy) + c.Ri[2] * rcz;
         const float dy = (c.Ri[3] * rcx + c.Ri[4] * rcy) + c.Ri[5] * rcz;
         const float dz = (c.Ri[6] * rcx + c.Ri[7] * rcy) + c.Ri[8] * rcz;
@@ -472,7 +479,8 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
         while (tt < t_end && steps < kMaxRaySteps) {
             ++steps;
             const float P0 = ox + tt * dx, P1 = oy + tt * dy, P2 = oz + tt * dz;
-            const bool alloc = m_allocated(L, ns, P0, P1, P2);
+            const bool local = full && tt * zscale >= kZNear;
+            const bool alloc = m_allocated(L, ns, P0, P1, P2, local);
             if (state == M_COARSE) {
                 if (!alloc) {
                     tt += 8.0f;
@@ -484,7 +492,7 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
                 state = M_FINE;
                 tt += mu_v;
             } else {
-                F = m_field(L, ns, P0, P1, P2);
+                F = m_field(L, ns, P0, P1, P2, local);
                 if (state == M_FINE) {
                     state = (F < 0.0f) ? M_WRONG_SIDE : M_SURFACE;
                 } else if (state == M_SURFACE) {
@@ -507,15 +515,16 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
         if (state == M_BEHIND) {
             tt += F * mu_v;
             float P0 = ox + tt * dx, P1 = oy + tt * dy, P2 = oz + tt * dz;
-            F = m_field(L, ns, P0, P1, P2);
+            F = m_field(L, ns, P0, P1, P2, full && tt * zscale >= kZNear);
             tt += F * mu_v;
             P0 = ox + tt * dx;
             P1 = oy + tt * dy;
             P2 = oz + tt * dz;
             out_p = make_float4(P0 * voxel, P1 * voxel, P2 * voxel, 1.0f);
-            const float gx = (m_field(L, ns, P0 + 1.0f, P1, P2) - m_field(L, ns, P0 - 1.0f, P1, P2)) * 0.5f;
-            const float gy = (m_field(L, ns, P0, P1 + 1.0f, P2) - m_field(L, ns, P0, P1 - 1.0f, P2)) * 0.5f;
-            const float gz = (m_field(L, ns, P0, P1, P2 + 1.0f) - m_field(L, ns, P0, P1, P2 - 1.0f)) * 0.5f;
+            const bool lh = full && tt * zscale >= kZNear;   // the taps lie within 2 voxels of the hit
+            const float gx = (m_field(L, ns, P0 + 1.0f, P1, P2, lh) - m_field(L, ns, P0 - 1.0f, P1, P2, lh)) * 0.5f;
+            const float gy = (m_field(L, ns, P0, P1 + 1.0f, P2, lh) - m_field(L, ns, P0, P1 - 1.0f, P2, lh)) * 0.5f;
+            const float gz = (m_field(L, ns, P0, P1, P2 + 1.0f, lh) - m_field(L, ns, P0, P1, P2 - 1.0f, lh)) * 0.5f;
             const float gn = sqrtf((gx * gx + gy * gy) + gz * gz);
             if (gn > 0.0f) out_n = make_float4(gx / gn, gy / gn, gz / gn, 1.0f);
         }

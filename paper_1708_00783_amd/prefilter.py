@@ -143,12 +143,16 @@ def surface_rms(vol: Volume, scene, poses, intr, stride: int = 4):
     return (np.sqrt(s2 / n) if n else float("nan")), n
 
 
-def evaluate_room(seed_index: int, frames, net: Denoiser | None, checkpoints, vp=None, eval_every: int = 10,
-                  stride: int = 4):
-    """Fuse the room's frames (raw, or through `net`) and record the surface
-    RMS after each checkpoint frame count, plus the device time of the fusion
-    (prefilter + allocation + integration + raycast per frame) accumulated
-    up to each checkpoint."""
+EVAL_STRIDES = (60, 30, 20, 15, 10, 6, 5, 4, 3, 2, 1)   # every k-th frame: N = 300 / k frames
+
+
+def evaluate_room(seed_index: int, frames, net: Denoiser | None, strides=EVAL_STRIDES, vp=None,
+                  eval_every: int = 10, stride: int = 4):
+    """Equal-coverage evaluation: for each k, fuse every k-th frame of the
+    whole trajectory (raw, or through `net`) into a fresh volume and record
+    the surface RMS at every `eval_every`-th trajectory pose and the
+    device-synchronised wall time of the fusion (prefilter + allocation +
+    integration + raycast per frame).  Returns {N: (rms, seconds)}."""
     import torch
     from synth import configs
     vp = vp or configs.C2_VOLUME
@@ -157,22 +161,20 @@ def evaluate_room(seed_index: int, frames, net: Denoiser | None, checkpoints, vp
     poses = room_poses(seed_index, n)
     scene = configs.c2_scene(seed_index)
     eval_poses = poses[::eval_every]
-    vol = Volume(vp, K.width, K.height)
     pts = torch.empty((K.height, K.width, 4), dtype=torch.float32, device="cuda")
     nrm = torch.empty_like(pts)
     den = torch.empty((1, K.height, K.width), dtype=torch.float32, device="cuda") if net is not None else None
-    rms, tcum, t_fuse = {}, {}, 0.0
-    done = 0
-    for c in sorted(checkpoints):
+    out = {}
+    vol = Volume(vp, K.width, K.height)
+    for k in strides:
+        vol.reset()
+        idx = list(range(0, n, k))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in range(done, c):
-            fuse_frame(vol, frames[k], K, poses[k], net, den)
-            vol.raycast(poses[k], K, pts, nrm)
+        for i in idx:
+            fuse_frame(vol, frames[i], K, poses[i], net, den)
+            vol.raycast(poses[i], K, pts, nrm)
         torch.cuda.synchronize()
-        t_fuse += time.perf_counter() - t0
-        done = c
-        tcum[c] = t_fuse
-        rms[c] = surface_rms(vol, scene, eval_poses, K, stride)[0]
+        out[len(idx)] = (surface_rms(vol, scene, eval_poses, K, stride)[0], time.perf_counter() - t0)
     vol.close()
-    return rms, tcum
+    return out
