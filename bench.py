@@ -364,6 +364,72 @@ def run_c5(args):
     print(json.dumps(out), flush=True)
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def prefilter_flop(h, w, n):
+    """forward multiply-add flops of the conv stack for n frames of h x w"""
+    convs = ((3, 32, 1), (32, 64, 2), (64, 64, 4), (64, 128, 8), (128, 64, 4), (64, 64, 2), (64, 32, 1), (32, 1, 1))
+    return n * sum(2.0 * 9 * ci * co * (h // s) * (w // s) for ci, co, s in convs)
+
+
+def run_prefilter(args):
+    """The prefilter's kernels alone: 640x480 inference and batch-8 256x256
+    training steps (forward, loss, backward, Adam) on seeded inputs."""
+    import torch
+    import paper_1708_00783_amd as T
+    from paper_1708_00783_amd import prefilter as PF
+    from synth import configs
+    torch.cuda.set_device(0)
+    frames = make_frames(8, args.workers, args.frames_cache)
+    d = torch.from_numpy(frames).cuda()
+    inf = T.Denoiser(1, 480, 640)
+    inf.set_params(PF.init_params(0))
+    out = torch.empty((1, 480, 640), dtype=torch.float32, device="cuda")
+    for k in range(args.warmup):
+        inf.forward(d[k % 8][None], out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(args.steps):
+        inf.forward(d[k % 8][None], out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_inf = e0.elapsed_time(e1) / args.steps
+    tr = T.Denoiser(8, 256, 256, training=True)
+    tr.set_params(PF.init_params(0))
+    xin = torch.stack([d[k, 100:356, 200:456] for k in range(8)]).contiguous()
+    tgt = xin.to(torch.float32) / 1000.0
+    for _ in range(args.warmup):
+        tr.forward(xin)
+        tr.backward(tgt)
+        tr.adam_step()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        tr.forward(xin)
+        tr.backward(tgt)
+        tr.adam_step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_tr = e0.elapsed_time(e1) / args.steps
+    f_inf = prefilter_flop(480, 640, 1)
+    f_tr = 3.0 * prefilter_flop(256, 256, 8)     # forward + backward-data + weight gradient
+    tf_inf = f_inf / (ms_inf * 1e-3) / 1e12
+    out = {
+        "metric": "prefilter inference ms per 640x480 frame (bf16 matrix cores)", "value": round(ms_inf, 4),
+        "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": False,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "learned prefilter kernels: 640x480 inference; training steps at batch 8 of 256x256"},
+        "roofline": {"bound": "mfma", "achieved": round(tf_inf, 2), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tf_inf / MFMA_BF16_PEAK_TFLOPS, 5), "traffic": None,
+                     "kernel": "whole forward pass", "flop_per_launch": int(f_inf)},
+        "extra": {"train_step_ms": round(ms_tr, 4), "train_tflops": round(f_tr / (ms_tr * 1e-3) / 1e12, 2),
+                  "train_flop_per_step": int(f_tr)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -373,7 +439,7 @@ def main():
     ap.add_argument("--workers", type=int, default=min(16, cpu_cores()))
     ap.add_argument("--frames-cache", default=None,
                     help="npy file holding the generated depth frames (written if absent)")
-    ap.add_argument("--workload", choices=("c2", "c4", "c5"), default="c2",
+    ap.add_argument("--workload", choices=("c2", "c4", "c5", "prefilter"), default="c2",
                     help="c2: one volume, the headline metric; c4: 64 batched submaps, 8 views; "
                          "c5: train the depth prefilter, then denoised vs plain at equal surface error")
     ap.add_argument("--c5-rooms", type=int, default=50, help="training rooms (seeds 5000..)")
@@ -406,6 +472,8 @@ def main():
         return run_c4(args)
     if args.workload == "c5":
         return run_c5(args)
+    if args.workload == "prefilter":
+        return run_prefilter(args)
     from synth import configs
     K = configs.KINECT_INTR
     n_frames = min(N_TRAJ, args.warmup + args.steps)
