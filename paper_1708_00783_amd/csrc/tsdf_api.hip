@@ -444,13 +444,14 @@ int tf_raycast(tf_ctx *ctx, const float pose_w2c[16], const tf_intrinsics *intr,
     Cam c;
     make_cam(pose_w2c, intr, c);
     hipError_t e;
+    const bool all = !same_view(ctx, pose_w2c, intr);
     {
         Timed t(ctx, TF_K_RANGE_BIN, s);
-        e = launch_range_bin(ctx->v, c, !same_view(ctx, pose_w2c, intr), s);
+        e = launch_range_bin(ctx->v, c, all, s);
     }
     if (e != hipSuccess) return TF_E_HIP;
     Timed t(ctx, TF_K_RAYCAST, s);
-    return hip_status(launch_raycast(ctx->v, c, (float4 *)d_points, (float4 *)d_normals, s));
+    return hip_status(launch_raycast(ctx->v, c, all, (float4 *)d_points, (float4 *)d_normals, s));
 }
 
 int tf_range_image(tf_ctx *ctx, const float pose_w2c[16], const tf_intrinsics *intr, float *d_zmin, float *d_zmax,

@@ -133,7 +133,8 @@ hipError_t launch_visible(const Vol &v, hipStream_t s);
 hipError_t launch_depth_convert(const Vol &v, const void *depth, int fmt, int n, hipStream_t s);
 hipError_t launch_integrate(const Vol &v, const Cam &c, hipStream_t s);
 hipError_t launch_range_bin(const Vol &v, const Cam &c, bool all_blocks, hipStream_t s);
-hipError_t launch_raycast(const Vol &v, const Cam &c, float4 *pts, float4 *nrm, hipStream_t s);
+// all_blocks: the bins hold every allocated block (not only the visible list)
+hipError_t launch_raycast(const Vol &v, const Cam &c, bool all_blocks, float4 *pts, float4 *nrm, hipStream_t s);
 
 hipError_t launch_range_write(const Vol &v, const Cam &c, float *zmin, float *zmax, hipStream_t s);
 constexpr int kSwapChunk = 4096;        // entries per workgroup of the ordered swap-out selection

@@ -94,11 +94,21 @@ __global__ __launch_bounds__(256) void k_depth_convert(float *dst, const void *s
 
 
 // ============================================================================
-// search range (Sec. 4.4): project blocks, bin their boxes by 16x16 tile
+// search range (Sec. 4.4): project blocks, bin them by 16x16 tile
 // ============================================================================
+constexpr int kExpandV = 3;   // voxels added around a block when binning it
+
+// One lane per block: its record (search-range box and z range of the block
+// itself, key, device pointer) goes to every tile its cube covers -- grown by
+// kExpandV voxels when every block is binned, so that a tile's bin then holds
+// every block any trilinear read of the tile's rays can touch.  The (record,
+// tile) writes of a wave are spread evenly over its lanes.
 __global__ __launch_bounds__(256) void k_range_bin(Vol v, Cam c, int all)
 {
-    const uint32_t lane = lane_id();
+    __shared__ Rec wrec[4][kWave];
+    __shared__ uint32_t wexcl[4][kWave + 1];
+    __shared__ int16_t wrect[4][kWave][3];   // tx0, ty0, nx
+    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
     const uint32_t gwave = (blockIdx.x * 256u + threadIdx.x) / kWave;
     const uint32_t nwaves = gridDim.x * (256u / kWave);
     const uint32_t n = all ? v.n_entries : v.ctrl->n_vis;
@@ -107,12 +117,26 @@ __global__ __launch_bounds__(256) void k_range_bin(Vol v, Cam c, int all)
         const uint32_t i = base + lane;
         bool emit = false;
         Rec r;
+        Rec ex;
         if (i < n) {
             const uint32_t e = all ? i : (uint32_t)v.vlist[i];
             const int4 w = load_entry(v.entries, e);
             if (w.w >= 0) {
                 const int bx = (int16_t)(w.x & 0xffff), by = (int16_t)((uint32_t)w.x >> 16), bz = (int16_t)(w.y & 0xffff);
-                emit = block_record(v, c, bx, by, bz, r);
+                // bins of every block (foreign views) grow the cubes so that a
+                // complete tile table answers every lookup of the tile's rays;
+                // bins of the visible list cannot, so they use the plain cube
+                const int g = all ? kExpandV : 0;
+                emit = cube_record(c.M, c, v.voxel, 8 * bx - g, 8 * by - g, 8 * bz - g, 8 + 2 * g, ex);
+                if (emit && !block_record(v, c, bx, by, bz, r)) {
+                    // only the grown cube reaches the image: a table entry with no range
+                    r.x0 = 1;
+                    r.x1 = 0;
+                    r.y0 = 1;
+                    r.y1 = 0;
+                    r.zlo = __builtin_inff();
+                    r.zhi = -__builtin_inff();
+                }
                 r.bx = (int16_t)bx;
                 r.by = (int16_t)by;
                 r.bz = (int16_t)bz;
@@ -127,24 +151,55 @@ __global__ __launch_bounds__(256) void k_range_bin(Vol v, Cam c, int all)
         uint32_t rb = 0;
         if ((int)lane == leader) rb = atomicAdd(&v.ctrl->n_rec, (uint32_t)__popcll(m));
         rb = __shfl(rb, leader);
+        uint32_t cnt = 0;
         if (emit) {
-            const uint32_t idx = rb + rank_in(m);
-            v.recs[idx] = r;
-            const int tx0 = r.x0 / kTile, tx1 = r.x1 / kTile, ty0 = r.y0 / kTile, ty1 = r.y1 / kTile;
-            for (int ty = ty0; ty <= ty1; ++ty)
-                for (int tx = tx0; tx <= tx1; ++tx) {
-                    const int t = ty * ntx + tx;
-                    const int s = atomicAdd(&v.bin_count[t], 1);
-                    if (s < kBinCap) v.bins[(size_t)t * kBinCap + s] = r;
-                }
+            v.recs[rb + rank_in(m)] = r;
+            const int tx0 = ex.x0 / kTile, tx1 = ex.x1 / kTile, ty0 = ex.y0 / kTile, ty1 = ex.y1 / kTile;
+            cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+            wrec[wv][lane] = r;
+            wrect[wv][lane][0] = (int16_t)tx0;
+            wrect[wv][lane][1] = (int16_t)ty0;
+            wrect[wv][lane][2] = (int16_t)(tx1 - tx0 + 1);
         }
+        // lanes of one wave exchange through their own LDS slice: a wave-level fence suffices
+        // exclusive scan of the lanes' tile counts
+        uint32_t incl = cnt;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t t = __shfl_up(incl, d);
+            if ((int)lane >= d) incl += t;
+        }
+        wexcl[wv][lane] = incl - cnt;
+        const uint32_t total = __shfl(incl, kWave - 1);
+        if (lane == 0) wexcl[wv][kWave] = total;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t item = lane; item < total; item += kWave) {
+            // owner lane: the last j with excl[j] <= item (lanes without tiles have empty ranges)
+            int j = 0;
+#pragma unroll
+            for (int b = 32; b; b >>= 1)
+                if (wexcl[wv][j + b] <= item) j += b;
+            while (wexcl[wv][j + 1] <= item) ++j;
+            const uint32_t li = item - wexcl[wv][j];
+            const int nx = wrect[wv][j][2];
+            const int t = (wrect[wv][j][1] + (int)(li / (uint32_t)nx)) * ntx + wrect[wv][j][0] + (int)(li % (uint32_t)nx);
+            const int sl = atomicAdd(&v.bin_count[t], 1);
+            if (sl < kBinCap) v.bins[(size_t)t * kBinCap + sl] = wrec[wv][j];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
-// LDS table of (block key -> device pointer) for the blocks of a raycast tile
+// LDS of a raycast tile: the (block key -> device pointer) table of the bin's
+// blocks and the per-pixel search range as float bits (all values > 0)
 struct TileTable {
     unsigned long long key[kTileTable];   // 0 = empty slot
     int ptr[kTileTable];
+    uint32_t zlo[256], zhi[256];
+    uint32_t zlo_all, zhi_all;            // records covering the whole tile
+    int complete;                         // the table holds the whole bin
 };
 
 __device__ __forceinline__ uint32_t table_slot(int bx, int by, int bz)
@@ -152,49 +207,66 @@ __device__ __forceinline__ uint32_t table_slot(int bx, int by, int bz)
     return hash_index(bx, by, bz, (uint32_t)kTileTable - 1u);
 }
 
-// per-pixel min/max over the records of a tile's bin (all records if the bin
-// overflowed); with `tt` the bin's blocks also go into the tile's LDS table.
-// Every thread of the workgroup must call it.
-__device__ __forceinline__ void tile_range(const Vol &v, int tile, int px, int py, float &zmin, float &zmax, Rec *lds,
-                           TileTable *tt)
+// The tile's search range and block table from its bin (all records if the
+// bin overflowed, then without a table).  Each record updates the pixels of
+// its box inside the tile with LDS atomic min/max (order-free, so the result
+// is that of a per-pixel loop); a record covering the whole tile updates one
+// tile-wide pair.  The tile spans [tx0, tx0 + 16) x [ty0, ty0 + 16); every
+// thread of the workgroup calls it; read a pixel with tile_pixel_range.
+__device__ __forceinline__ void tile_range(const Vol &v, int tile, int tx0, int ty0, TileTable *tt, bool table)
 {
-    zmin = __builtin_inff();
-    zmax = -__builtin_inff();
-    if (tt)
-        for (int k = threadIdx.x; k < kTileTable; k += 256) tt->key[k] = 0ull;
+    for (int k = threadIdx.x; k < kTileTable; k += 256) tt->key[k] = 0ull;
+    tt->zlo[threadIdx.x] = 0x7f800000u;   // +inf
+    tt->zhi[threadIdx.x] = 0u;            // below every positive float
     const int cnt = v.bin_count[tile];
     const bool fallback = cnt > kBinCap;
     const int n = fallback ? (int)v.ctrl->n_rec : cnt;
-    __syncthreads();
-    for (int base = 0; base < n; base += 256) {
-        const int j = base + (int)threadIdx.x;
-        if (j < n) {
-            const Rec r = fallback ? v.recs[j] : v.bins[(size_t)tile * kBinCap + j];
-            lds[threadIdx.x] = r;
-            if (tt && !fallback) {
-                // keys in one bin are distinct; the table is at most half full
-                const unsigned long long key = pack_key(r.bx, r.by, r.bz);
-                uint32_t sl = table_slot(r.bx, r.by, r.bz);
-                for (int k = 0; k < kTileTable; ++k) {
-                    if (atomicCAS(&tt->key[sl], 0ull, key) == 0ull) {
-                        tt->ptr[sl] = r.ptr;
-                        break;
-                    }
-                    sl = (sl + 1u) & (uint32_t)(kTileTable - 1);
-                }
-            }
-        }
-        __syncthreads();
-        const int m = (n - base) < 256 ? (n - base) : 256;
-        for (int k = 0; k < m; ++k) {
-            const Rec r = lds[k];
-            if (px >= r.x0 && px <= r.x1 && py >= r.y0 && py <= r.y1) {
-                if (r.zlo < zmin) zmin = r.zlo;
-                if (r.zhi > zmax) zmax = r.zhi;
-            }
-        }
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        tt->zlo_all = 0x7f800000u;
+        tt->zhi_all = 0u;
+        tt->complete = table && !fallback;
     }
+    __syncthreads();
+    for (int j = (int)threadIdx.x; j < n; j += 256) {
+        const Rec r = fallback ? v.recs[j] : v.bins[(size_t)tile * kBinCap + j];
+        if (table && !fallback) {
+            // keys in one bin are distinct; the table is at most half full
+            const unsigned long long key = pack_key(r.bx, r.by, r.bz);
+            uint32_t sl = table_slot(r.bx, r.by, r.bz);
+            for (int k = 0; k < kTileTable; ++k) {
+                if (atomicCAS(&tt->key[sl], 0ull, key) == 0ull) {
+                    tt->ptr[sl] = r.ptr;
+                    break;
+                }
+                sl = (sl + 1u) & (uint32_t)(kTileTable - 1);
+            }
+        }
+        const int x0 = r.x0 > tx0 ? r.x0 : tx0, x1 = r.x1 < tx0 + kTile - 1 ? r.x1 : tx0 + kTile - 1;
+        const int y0 = r.y0 > ty0 ? r.y0 : ty0, y1 = r.y1 < ty0 + kTile - 1 ? r.y1 : ty0 + kTile - 1;
+        if (x0 > x1 || y0 > y1) continue;
+        const uint32_t lo = __float_as_uint(r.zlo), hi = __float_as_uint(r.zhi);
+        if (x0 == tx0 && x1 == tx0 + kTile - 1 && y0 == ty0 && y1 == ty0 + kTile - 1) {
+            atomicMin(&tt->zlo_all, lo);
+            atomicMax(&tt->zhi_all, hi);
+            continue;
+        }
+        for (int y = y0; y <= y1; ++y)
+            for (int x = x0; x <= x1; ++x) {
+                const int pi = (y - ty0) * kTile + (x - tx0);
+                atomicMin(&tt->zlo[pi], lo);
+                atomicMax(&tt->zhi[pi], hi);
+            }
+    }
+    __syncthreads();
+}
+
+// search range of pixel pi of the tile after tile_range (+inf / -inf: none)
+__device__ __forceinline__ void tile_pixel_range(const TileTable *tt, int pi, float &zmin, float &zmax)
+{
+    const uint32_t lo = tt->zlo[pi] < tt->zlo_all ? tt->zlo[pi] : tt->zlo_all;
+    const uint32_t hi = tt->zhi[pi] > tt->zhi_all ? tt->zhi[pi] : tt->zhi_all;
+    zmin = __uint_as_float(lo);
+    zmax = hi ? __uint_as_float(hi) : -__builtin_inff();
 }
 
 // last workgroup of a raycast-kind launch clears the record counter
@@ -220,15 +292,19 @@ namespace {
 
 
 // one-entry block cache (the paper's IndexCache, Sec. 3.3): the last block
-// key looked up and its device pointer (-1 = absent or not on the device)
+// key looked up and its device pointer (-1 = absent or not on the device);
+// `local`: lookups of this ray may trust a miss in the tile's table
 struct BlockCache {
     int bx, by, bz, ptr;
+    bool local;
 };
 
 // device pointer of a block (-1 = absent or not on the device): the tile's
-// LDS table first (blocks behind the tile's search range), then the bucket
-// bitmap and the hash table itself (any other block)
-__device__ __forceinline__ int lookup_block(const Vol &v, const TileTable *tt, int bx, int by, int bz)
+// LDS table first; unless `local`, then the bucket bitmap and the hash table.
+// `local` holds for a ray whose points all lie at or beyond the near plane in
+// a tile whose table holds its whole bin: every block within kExpandV voxels
+// of such a point is in the bin, so a miss proves absence.
+__device__ __forceinline__ int lookup_block(const Vol &v, const TileTable *tt, int bx, int by, int bz, bool local)
 {
     if (!in_short_range(bx) || !in_short_range(by) || !in_short_range(bz)) return -1;
     const unsigned long long key = pack_key(bx, by, bz);
@@ -239,6 +315,7 @@ __device__ __forceinline__ int lookup_block(const Vol &v, const TileTable *tt, i
         if (kk == 0ull) break;
         sl = (sl + 1u) & (uint32_t)(kTileTable - 1);
     }
+    if (local) return -1;
     int ptr = -1, e = -1;
 #if TSDF_RAY_BITMAP
     const uint32_t h = hash_index(bx, by, bz, v.n_buckets - 1u);
@@ -256,7 +333,7 @@ __device__ __forceinline__ int cached_block(const Vol &v, const TileTable *tt, i
     cc.bx = bx;
     cc.by = by;
     cc.bz = bz;
-    cc.ptr = lookup_block(v, tt, bx, by, bz);
+    cc.ptr = lookup_block(v, tt, bx, by, bz, cc.local);
     return cc.ptr;
 }
 
@@ -276,13 +353,14 @@ __device__ __forceinline__ void cell_setup(const Vol &v, const TileTable *tt, fl
     const int p000 = cached_block(v, tt, Bx, By, Bz, cc);
     int p100 = p000, p010 = p000, p001 = p000, p110 = p000, p101 = p000, p011 = p000, p111 = p000;
     if (sx | sy | sz) {
-        if (sx) p100 = lookup_block(v, tt, Bx + 1, By, Bz);
-        if (sy) p010 = lookup_block(v, tt, Bx, By + 1, Bz);
-        if (sz) p001 = lookup_block(v, tt, Bx, By, Bz + 1);
-        p110 = (sx & sy) ? lookup_block(v, tt, Bx + 1, By + 1, Bz) : (sx ? p100 : p010);
-        p101 = (sx & sz) ? lookup_block(v, tt, Bx + 1, By, Bz + 1) : (sx ? p100 : p001);
-        p011 = (sy & sz) ? lookup_block(v, tt, Bx, By + 1, Bz + 1) : (sy ? p010 : p001);
-        p111 = (sx & sy & sz) ? lookup_block(v, tt, Bx + 1, By + 1, Bz + 1)
+        const bool lc = cc.local;
+        if (sx) p100 = lookup_block(v, tt, Bx + 1, By, Bz, lc);
+        if (sy) p010 = lookup_block(v, tt, Bx, By + 1, Bz, lc);
+        if (sz) p001 = lookup_block(v, tt, Bx, By, Bz + 1, lc);
+        p110 = (sx & sy) ? lookup_block(v, tt, Bx + 1, By + 1, Bz, lc) : (sx ? p100 : p010);
+        p101 = (sx & sz) ? lookup_block(v, tt, Bx + 1, By, Bz + 1, lc) : (sx ? p100 : p001);
+        p011 = (sy & sz) ? lookup_block(v, tt, Bx, By + 1, Bz + 1, lc) : (sy ? p010 : p001);
+        p111 = (sx & sy & sz) ? lookup_block(v, tt, Bx + 1, By + 1, Bz + 1, lc)
                               : (sx & sy) ? p110 : (sx & sz) ? p101 : (sy & sz) ? p011 : sx ? p100 : sy ? p010 : p001;
     }
     C.p[0] = p000;
@@ -346,13 +424,15 @@ enum { SEARCH_BLOCK_COARSE, SEARCH_BLOCK_FINE, SEARCH_SURFACE, BEHIND_SURFACE, W
 // search range on its own, written as an image (tf_range_image)
 __global__ __launch_bounds__(256) void k_range_write(Vol v, Cam c, float *zmin_out, float *zmax_out)
 {
-    __shared__ Rec lds[256];
+    __shared__ TileTable tbl;
     const int ntx = (c.W + kTile - 1) / kTile;
     const int tile = blockIdx.x;
-    const int px = (tile % ntx) * kTile + (int)(threadIdx.x % kTile);
-    const int py = (tile / ntx) * kTile + (int)(threadIdx.x / kTile);
+    const int tx0 = (tile % ntx) * kTile, ty0 = (tile / ntx) * kTile;
+    const int px = tx0 + (int)(threadIdx.x % kTile);
+    const int py = ty0 + (int)(threadIdx.x / kTile);
+    tile_range(v, tile, tx0, ty0, &tbl, false);
     float zmin, zmax;
-    tile_range(v, tile, px, py, zmin, zmax, lds, nullptr);
+    tile_pixel_range(&tbl, (int)threadIdx.x, zmin, zmax);
     finish_tile(v, tile, false);
     if (px >= c.W || py >= c.H) return;
     zmin_out[(size_t)py * c.W + px] = zmin;
@@ -364,9 +444,8 @@ __global__ __launch_bounds__(256) void k_range_write(Vol v, Cam c, float *zmin_o
 // from its bin (LDS), the state machine per pixel, then the two refinement
 // steps and the normal for the hits of the wave together
 // ============================================================================
-__global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, float4 *pts, float4 *nrm)
+__global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, float4 *pts, float4 *nrm)
 {
-    __shared__ Rec lds[256];
     __shared__ TileTable tbl;
     const int ntx = (c.W + kTile - 1) / kTile, nty = (c.H + kTile - 1) / kTile;
     const int ntiles = ntx * nty;
@@ -380,10 +459,14 @@ __global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, float4 *pts, floa
 #endif
     const bool real = tile < ntiles;
     const int q = (int)threadIdx.x >> 6, i = (int)threadIdx.x & 63;
-    const int px = real ? (tile % ntx) * kTile + (q & 1) * 8 + (i & 7) : 0;
-    const int py = real ? (tile / ntx) * kTile + (q >> 1) * 8 + (i >> 3) : 0;
+    const int lx = (q & 1) * 8 + (i & 7), ly = (q >> 1) * 8 + (i >> 3);
+    const int tx0 = real ? (tile % ntx) * kTile : 0, ty0 = real ? (tile / ntx) * kTile : 0;
+    const int px = tx0 + lx, py = ty0 + ly;
     float zmin = __builtin_inff(), zmax = -__builtin_inff();
-    if (real) tile_range(v, tile, px, py, zmin, zmax, lds, &tbl);
+    if (real) {
+        tile_range(v, tile, tx0, ty0, &tbl, true);
+        tile_pixel_range(&tbl, ly * kTile + lx, zmin, zmax);
+    }
     finish_tile(v, real ? tile : -1, true);
     const bool inside = real && px < c.W && py < c.H;
     float4 out_p = make_float4(0.f, 0.f, 0.f, 0.f), out_n = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -403,7 +486,14 @@ __global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, float4 *pts, floa
         const float t_end = (zmax * nr) * inv_vs;
         int state = SEARCH_BLOCK_COARSE;
         float F = 1.0f;
-        BlockCache cc = {0x7fffffff, 0, 0, -1};
+        // with bins of every allocated block, and every point of this ray
+        // (march from t - 8, two refinement steps of at most mu back) at or
+        // beyond the near plane, a table miss proves absence.  Bins of the
+        // visible list alone do not: trilinear reads may reach allocated
+        // blocks outside it.
+        const float zscale = vs * rcz;
+        const bool local = all_blocks && tbl.complete && (t - 8.0f - 2.0f * mu_v) * zscale >= kZNear;
+        BlockCache cc = {0x7fffffff, 0, 0, -1, local};
         int steps = 0;
         while (t < t_end && steps < kMaxRaySteps) {
 #if TSDF_RAY_BITMAP
@@ -771,7 +861,7 @@ hipError_t launch_range_bin(const Vol &v, const Cam &c, bool all_blocks, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_raycast(const Vol &v, const Cam &c, float4 *pts, float4 *nrm, hipStream_t s)
+hipError_t launch_raycast(const Vol &v, const Cam &c, bool all_blocks, float4 *pts, float4 *nrm, hipStream_t s)
 {
     const int ntiles = ((c.W + kTile - 1) / kTile) * ((c.H + kTile - 1) / kTile);
 #if TSDF_RAY_XCD_BANDS
@@ -779,7 +869,7 @@ hipError_t launch_raycast(const Vol &v, const Cam &c, float4 *pts, float4 *nrm, 
 #else
     const int grid = ntiles;
 #endif
-    hipLaunchKernelGGL(k_raycast, dim3(grid), dim3(256), 0, s, v, c, pts, nrm);
+    hipLaunchKernelGGL(k_raycast, dim3(grid), dim3(256), 0, s, v, c, all_blocks ? 1 : 0, pts, nrm);
     return hipGetLastError();
 }
 

@@ -184,9 +184,8 @@ namespace {
 // in ascending order with what the field reads, and the per-pixel range
 template <int NT>
 struct MTileLds {
-    static constexpr int TT = 4 * NT;           // table slots
-    unsigned long long key[TT];                 // 0 = empty
-    int ptr[TT];
+    static constexpr int TT = NT >= 128 ? 4096 : 2048;   // table slots (8 bytes each)
+    unsigned long long slot[TT];                // 0 = empty, else mkey(...) | device pointer
     float Rs[kMaxSubmaps][12];                  // rotation rows, then translation (voxel units)
     const DEntry *ent[kMaxSubmaps];
     const uint32_t *occ[kMaxSubmaps];
@@ -194,7 +193,7 @@ struct MTileLds {
     uint32_t nb[kMaxSubmaps], ne[kMaxSubmaps];
     int smid[kMaxSubmaps];
     unsigned long long mask;
-    uint32_t n_tab, hits;
+    uint32_t n_tab, hits, unfit;                // unfit: a record whose key or pointer does not pack
     uint32_t zlo[NT], zhi[NT];                  // per-pixel range as float bits (all values > 0)
     uint32_t zlo_all, zhi_all;                  // from records covering the whole tile
 };
@@ -205,9 +204,17 @@ __device__ __forceinline__ uint32_t mslot(int sm, int bx, int by, int bz)
     return (hash_index(bx, by, bz, 0xffffffffu) ^ ((uint32_t)sm * 0x9e3779b1u)) & (uint32_t)(MTileLds<NT>::TT - 1);
 }
 
+// packed table slot: valid bit 63, submap (6 bits), bz, by, bx (11-bit
+// two's complement each) above the 24-bit device block pointer
+__device__ __forceinline__ bool mfits(int bx, int by, int bz)
+{
+    return bx >= -1024 && bx < 1024 && by >= -1024 && by < 1024 && bz >= -1024 && bz < 1024;
+}
+
 __device__ __forceinline__ unsigned long long mkey(int sm, int bx, int by, int bz)
 {
-    return pack_key(bx, by, bz) | ((unsigned long long)sm << 49);
+    return (1ull << 63) | ((unsigned long long)sm << 57) | ((unsigned long long)(bz & 0x7ff) << 46) |
+           ((unsigned long long)(by & 0x7ff) << 35) | ((unsigned long long)(bx & 0x7ff) << 24);
 }
 
 // Search range of the pixel and the tile's LDS state from its bin.  The range
@@ -221,13 +228,14 @@ __device__ __forceinline__ void m_tile_setup(const MSub *subs, const MTiles &t, 
                                              MTileLds<NT> &L)
 {
     constexpr int TT = MTileLds<NT>::TT;
-    for (int k = threadIdx.x; k < TT; k += NT) L.key[k] = 0ull;
+    for (int k = threadIdx.x; k < TT; k += NT) L.slot[k] = 0ull;
     L.zlo[threadIdx.x] = 0x7f800000u;   // +inf
     L.zhi[threadIdx.x] = 0u;            // below every positive float
     if (threadIdx.x == 0) {
         L.mask = 0ull;
         L.n_tab = 0u;
         L.hits = 0u;
+        L.unfit = 0u;
         L.zlo_all = 0x7f800000u;
         L.zhi_all = 0u;
     }
@@ -240,14 +248,13 @@ __device__ __forceinline__ void m_tile_setup(const MSub *subs, const MTiles &t, 
         const Rec r = t.bins[o0 + (uint32_t)j];
         atomicOr(&L.mask, 1ull << (uint32_t)r.pad);
         // keys in one bin are distinct; keep the table at most half full
-        if (atomicAdd(&L.n_tab, 1u) < (uint32_t)(TT / 2)) {
-            const unsigned long long key = mkey(r.pad, r.bx, r.by, r.bz);
+        if (!mfits(r.bx, r.by, r.bz) || r.ptr >= (1 << 24)) {
+            L.unfit = 1u;
+        } else if (atomicAdd(&L.n_tab, 1u) < (uint32_t)(TT / 2)) {
+            const unsigned long long val = mkey(r.pad, r.bx, r.by, r.bz) | (unsigned long long)r.ptr;
             uint32_t sl = mslot<NT>(r.pad, r.bx, r.by, r.bz);
             for (int k = 0; k < TT; ++k) {
-                if (atomicCAS(&L.key[sl], 0ull, key) == 0ull) {
-                    L.ptr[sl] = r.ptr;
-                    break;
-                }
+                if (atomicCAS(&L.slot[sl], 0ull, val) == 0ull) break;
                 sl = (sl + 1u) & (uint32_t)(TT - 1);
             }
         }
@@ -310,13 +317,15 @@ __device__ __forceinline__ int m_lookup(const MTileLds<NT> &L, int k, int bx, in
     constexpr int TT = MTileLds<NT>::TT;
     if (!in_short_range(bx) || !in_short_range(by) || !in_short_range(bz)) return -1;
     const int sm = L.smid[k];
-    const unsigned long long key = mkey(sm, bx, by, bz);
-    uint32_t sl = mslot<NT>(sm, bx, by, bz);
-    for (int it = 0; it < TT; ++it) {
-        const unsigned long long kk = L.key[sl];
-        if (kk == key) return L.ptr[sl];
-        if (kk == 0ull) break;
-        sl = (sl + 1u) & (uint32_t)(TT - 1);
+    if (mfits(bx, by, bz)) {
+        const unsigned long long key = mkey(sm, bx, by, bz) >> 24;
+        uint32_t sl = mslot<NT>(sm, bx, by, bz);
+        for (int it = 0; it < TT; ++it) {
+            const unsigned long long kk = L.slot[sl];
+            if ((kk >> 24) == key) return (int)(kk & 0xffffffull);
+            if (kk == 0ull) break;
+            sl = (sl + 1u) & (uint32_t)(TT - 1);
+        }
     }
     if (local) return -1;
     const uint32_t h = hash_index(bx, by, bz, L.nb[k] - 1u);
@@ -455,7 +464,7 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
     m_tile_setup<NT, TW, TH>(subs, t, (uint32_t)g, tx0, ty0, L);
     m_pixel_range<NT>(L, ly * TW + lx, zmin, zmax);
     const int ns = __popcll(L.mask);
-    const bool full = L.n_tab <= (uint32_t)(MTileLds<NT>::TT / 2);   // the table holds the whole bin
+    const bool full = L.n_tab <= (uint32_t)(MTileLds<NT>::TT / 2) && !L.unfit;   // the table holds the whole bin
     const bool inside = px < W && py < H;
     float4 out_p = make_float4(0.f, 0.f, 0.f, 0.f), out_n = make_float4(0.f, 0.f, 0.f, 0.f);
     if (inside && zmin <= zmax) {
