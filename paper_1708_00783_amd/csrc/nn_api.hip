@@ -100,7 +100,7 @@ bool nlayout(const Net &net, uint32_t B, uint32_t H, uint32_t W, int training, N
             if (e > mx) mx = e;
         }
         L.partial = take(4 * (size_t)kChunks * mx);
-        L.hpartial = take(4 * (size_t)kChunks * 289);
+        L.hpartial = take(4 * (size_t)kHeadChunks * 289);
         L.scratch = take(16);
         L.loss = take(16);
     }
@@ -263,7 +263,7 @@ int tf_nn_backward(tf_nn *nn, const float *d_target, float *d_loss, tf_stream st
     hipError_t e = launch_loss(nn->out, nn->dm, d_target, N * H * W, nn->ddelta, nn->scratch, d_loss, s);
     if (e == hipSuccess) e = launch_head_bwd(nn->ddelta, nn->params + Hd.w_off, nn->act[7], nn->grad[7], N, H, W, s);
     if (e == hipSuccess)
-        e = launch_head_wgrad(nn->ddelta, nn->act[7], N, H, W, nn->hpartial, kChunks, nn->grads + Hd.w_off,
+        e = launch_head_wgrad(nn->ddelta, nn->act[7], N, H, W, nn->hpartial, kHeadChunks, nn->grads + Hd.w_off,
                               nn->grads + Hd.b_off, s);
     // conv layers from the last to the first: weight gradient, then the
     // gradient at the source (skip gradient and relu mask fused)

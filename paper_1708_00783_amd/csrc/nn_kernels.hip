@@ -483,32 +483,43 @@ __global__ __launch_bounds__(256) void k_head_bwd(const float *ddelta, const flo
     }
 }
 
-// head weight gradient of one pixel chunk: thread j < 288 owns w[j], thread 288 the bias
-__global__ __launch_bounds__(320) void k_head_wgrad(const float *ddelta, const uint16_t *d1, int N, int H, int W,
+// head weight gradient of one pixel chunk: thread (slot, c) = (t / 32, t % 32)
+// sums the 9 taps of channel c over every 8th pixel of the chunk; the 8 slots
+// are reduced in LDS; partial[chunk][tap * 32 + c], partial[chunk][288] = bias
+__global__ __launch_bounds__(256) void k_head_wgrad(const float *ddelta, const uint16_t *d1, int N, int H, int W,
                                                     float *partial, int chunk_pix)
 {
+    __shared__ float red[8][289];
     const long P = (long)N * H * W;
     const long c0 = (long)blockIdx.x * chunk_pix;
     const long c1 = c0 + chunk_pix < P ? c0 + chunk_pix : P;
-    const int j = (int)threadIdx.x;
-    if (j > 288) return;
-    const int tap = j / 32, c = j % 32;
-    const int ky = tap / 3, kx = tap % 3;
-    float s = 0.0f;
-    for (long p = c0; p < c1; ++p) {
+    const int c = (int)threadIdx.x & 31, slot = (int)threadIdx.x >> 5;
+    float acc[9], bsum = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = 0.0f;
+    for (long p = c0 + slot; p < c1; p += 8) {
         const float dd = ddelta[p];
         if (dd == 0.0f) continue;
-        if (j == 288) {
-            s += dd;
-            continue;
-        }
+        bsum += dd;
         const int n = (int)(p / ((long)H * W));
         const int rem = (int)(p - (long)n * H * W);
-        const int y = rem / W + ky - 1, x = rem % W + kx - 1;
-        if (y < 0 || y >= H || x < 0 || x >= W) continue;
-        s += dd * bf2f(d1[(((size_t)n * H + y) * W + x) * 32 + c]);
+        const int y = rem / W, x = rem - (rem / W) * W;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+            if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+            acc[tap] += dd * bf2f(d1[(((size_t)n * H + yy) * W + xx) * 32 + c]);
+        }
     }
-    partial[(size_t)blockIdx.x * 289 + j] = s;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) red[slot][k * 32 + c] = acc[k];
+    if (c == 0) red[slot][288] = bsum;
+    __syncthreads();
+    for (int j = (int)threadIdx.x; j < 289; j += 256) {
+        float s = 0.0f;
+        for (int q = 0; q < 8; ++q) s += red[q][j];
+        partial[(size_t)blockIdx.x * 289 + j] = s;
+    }
 }
 
 __global__ __launch_bounds__(320) void k_head_reduce(const float *partial, int chunks, float *dw, float *db)
@@ -615,7 +626,7 @@ hipError_t launch_head_wgrad(const float *ddelta, const uint16_t *d1, int N, int
     const long P = (long)N * H * W;
     const int per = (int)((P + chunks - 1) / chunks);
     const int nc = (int)((P + per - 1) / per);
-    hipLaunchKernelGGL(k_head_wgrad, dim3(nc), dim3(320), 0, s, ddelta, d1, N, H, W, partial, per);
+    hipLaunchKernelGGL(k_head_wgrad, dim3(nc), dim3(256), 0, s, ddelta, d1, N, H, W, partial, per);
     hipLaunchKernelGGL(k_head_reduce, dim3(1), dim3(320), 0, s, partial, nc, dw, db);
     return hipGetLastError();
 }
