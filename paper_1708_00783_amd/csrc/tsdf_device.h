@@ -23,6 +23,9 @@ constexpr int kWave = 64;
 #ifndef TSDF_RAY_BITMAP
 #define TSDF_RAY_BITMAP 1       // consult the bucket-occupancy bitmap before an entry
 #endif
+#ifndef TSDF_RAY_SKIP
+#define TSDF_RAY_SKIP 8         // march positions tested together against the bitmap
+#endif
 
 __device__ __forceinline__ uint32_t hash_index(int x, int y, int z, uint32_t mask)
 {

@@ -193,12 +193,12 @@ __global__ __launch_bounds__(256) void k_range_bin(Vol v, Cam c, int all)
 }
 
 // LDS of a raycast tile: the (block key -> device pointer) table of the bin's
-// blocks and the per-pixel search range as float bits (all values > 0)
+// blocks and the bin's pixel boxes and z ranges (the first 16 bytes of each
+// record) for the per-pixel range
 struct TileTable {
     unsigned long long key[kTileTable];   // 0 = empty slot
     int ptr[kTileTable];
-    uint32_t zlo[256], zhi[256];
-    uint32_t zlo_all, zhi_all;            // records covering the whole tile
+    uint4 box[kBinCap];                   // x0, y0, x1, y1 (int16), zlo, zhi (float)
     int complete;                         // the table holds the whole bin
 };
 
@@ -207,75 +207,70 @@ __device__ __forceinline__ uint32_t table_slot(int bx, int by, int bz)
     return hash_index(bx, by, bz, (uint32_t)kTileTable - 1u);
 }
 
-// The tile's search range and block table from its bin (all records if the
-// bin overflowed, then without a table).  Each record updates the pixels of
-// its box inside the tile with LDS atomic min/max (order-free, so the result
-// is that of a per-pixel loop); a record covering the whole tile updates one
-// tile-wide pair.  The tile spans [tx0, tx0 + 16) x [ty0, ty0 + 16); every
-// thread of the workgroup calls it; read a pixel with tile_pixel_range.
-__device__ __forceinline__ void tile_range(const Vol &v, int tile, int tx0, int ty0, TileTable *tt, bool table)
+// The tile's block table and the search range of pixel (px, py) from the
+// tile's bin (all records, in chunks of kBinCap and without a table, if the
+// bin overflowed).  The records are staged in LDS and every thread takes the
+// min / max over those whose box holds its pixel: the per-pixel loop itself,
+// with no atomics.  Every thread of the workgroup calls it; zmin = +inf and
+// zmax = -inf when no record covers the pixel.
+__device__ __forceinline__ void tile_range(const Vol &v, int tile, int px, int py, TileTable *tt, bool table,
+                                           float &zmin, float &zmax)
 {
     for (int k = threadIdx.x; k < kTileTable; k += 256) tt->key[k] = 0ull;
-    tt->zlo[threadIdx.x] = 0x7f800000u;   // +inf
-    tt->zhi[threadIdx.x] = 0u;            // below every positive float
     const int cnt = v.bin_count[tile];
     const bool fallback = cnt > kBinCap;
     const int n = fallback ? (int)v.ctrl->n_rec : cnt;
-    if (threadIdx.x == 0) {
-        tt->zlo_all = 0x7f800000u;
-        tt->zhi_all = 0u;
-        tt->complete = table && !fallback;
-    }
-    __syncthreads();
-    for (int j = (int)threadIdx.x; j < n; j += 256) {
-        const Rec r = fallback ? v.recs[j] : v.bins[(size_t)tile * kBinCap + j];
-        if (table && !fallback) {
-            // keys in one bin are distinct; the table is at most half full
-            const unsigned long long key = pack_key(r.bx, r.by, r.bz);
-            uint32_t sl = table_slot(r.bx, r.by, r.bz);
-            for (int k = 0; k < kTileTable; ++k) {
-                if (atomicCAS(&tt->key[sl], 0ull, key) == 0ull) {
-                    tt->ptr[sl] = r.ptr;
-                    break;
+    if (threadIdx.x == 0) tt->complete = table && !fallback;
+    float lo = __builtin_inff(), hi = -__builtin_inff();
+    for (int base = 0; base < n; base += kBinCap) {
+        const int m = n - base < kBinCap ? n - base : kBinCap;
+        __syncthreads();   // the cleared table, or the previous chunk consumed
+        for (int j = (int)threadIdx.x; j < m; j += 256) {
+            const Rec r = fallback ? v.recs[base + j] : v.bins[(size_t)tile * kBinCap + j];
+            if (table && !fallback) {
+                // keys in one bin are distinct; the table is at most half full
+                const unsigned long long key = pack_key(r.bx, r.by, r.bz);
+                uint32_t sl = table_slot(r.bx, r.by, r.bz);
+                for (int k = 0; k < kTileTable; ++k) {
+                    if (atomicCAS(&tt->key[sl], 0ull, key) == 0ull) {
+                        tt->ptr[sl] = r.ptr;
+                        break;
+                    }
+                    sl = (sl + 1u) & (uint32_t)(kTileTable - 1);
                 }
-                sl = (sl + 1u) & (uint32_t)(kTileTable - 1);
+            }
+            tt->box[j] = make_uint4((uint32_t)(uint16_t)r.x0 | ((uint32_t)(uint16_t)r.y0 << 16),
+                                    (uint32_t)(uint16_t)r.x1 | ((uint32_t)(uint16_t)r.y1 << 16),
+                                    __float_as_uint(r.zlo), __float_as_uint(r.zhi));
+        }
+        __syncthreads();
+        for (int j = 0; j < m; ++j) {
+            const uint4 b = tt->box[j];
+            const int x0 = (int16_t)(b.x & 0xffffu), y0 = (int16_t)(b.x >> 16);
+            const int x1 = (int16_t)(b.y & 0xffffu), y1 = (int16_t)(b.y >> 16);
+            if (px >= x0 && px <= x1 && py >= y0 && py <= y1) {
+                const float zl = __uint_as_float(b.z), zh = __uint_as_float(b.w);
+                lo = zl < lo ? zl : lo;
+                hi = zh > hi ? zh : hi;
             }
         }
-        const int x0 = r.x0 > tx0 ? r.x0 : tx0, x1 = r.x1 < tx0 + kTile - 1 ? r.x1 : tx0 + kTile - 1;
-        const int y0 = r.y0 > ty0 ? r.y0 : ty0, y1 = r.y1 < ty0 + kTile - 1 ? r.y1 : ty0 + kTile - 1;
-        if (x0 > x1 || y0 > y1) continue;
-        const uint32_t lo = __float_as_uint(r.zlo), hi = __float_as_uint(r.zhi);
-        if (x0 == tx0 && x1 == tx0 + kTile - 1 && y0 == ty0 && y1 == ty0 + kTile - 1) {
-            atomicMin(&tt->zlo_all, lo);
-            atomicMax(&tt->zhi_all, hi);
-            continue;
-        }
-        for (int y = y0; y <= y1; ++y)
-            for (int x = x0; x <= x1; ++x) {
-                const int pi = (y - ty0) * kTile + (x - tx0);
-                atomicMin(&tt->zlo[pi], lo);
-                atomicMax(&tt->zhi[pi], hi);
-            }
     }
-    __syncthreads();
+    __syncthreads();   // the table is complete before any lookup
+    zmin = lo;
+    zmax = hi;
 }
 
-// search range of pixel pi of the tile after tile_range (+inf / -inf: none)
-__device__ __forceinline__ void tile_pixel_range(const TileTable *tt, int pi, float &zmin, float &zmax)
-{
-    const uint32_t lo = tt->zlo[pi] < tt->zlo_all ? tt->zlo[pi] : tt->zlo_all;
-    const uint32_t hi = tt->zhi[pi] > tt->zhi_all ? tt->zhi[pi] : tt->zhi_all;
-    zmin = __uint_as_float(lo);
-    zmax = hi ? __uint_as_float(hi) : -__builtin_inff();
-}
-
-// last workgroup of a raycast-kind launch clears the record counter
+// End of a raycast-kind workgroup (every thread calls it, after its last
+// read of the tile's bin): clear the tile's bin counter; the last workgroup
+// of the launch clears the record counter.  Taken at the end of the kernel,
+// the tickets of the workgroups arrive spread out in time.  No fence: every
+// workgroup has read the counter before its ticket, and the next launch sees
+// the stores.
 __device__ __forceinline__ void finish_tile(const Vol &v, int tile, bool count_raycast)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
         if (tile >= 0) v.bin_count[tile] = 0;
-        __threadfence();
         const uint32_t t = atomicAdd(&v.ctrl->ray_ticket, 1u);
         if (t == gridDim.x - 1u) {
             if (count_raycast) v.ctrl->tot_rec += v.ctrl->n_rec;
@@ -430,9 +425,8 @@ __global__ __launch_bounds__(256) void k_range_write(Vol v, Cam c, float *zmin_o
     const int tx0 = (tile % ntx) * kTile, ty0 = (tile / ntx) * kTile;
     const int px = tx0 + (int)(threadIdx.x % kTile);
     const int py = ty0 + (int)(threadIdx.x / kTile);
-    tile_range(v, tile, tx0, ty0, &tbl, false);
     float zmin, zmax;
-    tile_pixel_range(&tbl, (int)threadIdx.x, zmin, zmax);
+    tile_range(v, tile, px, py, &tbl, false, zmin, zmax);
     finish_tile(v, tile, false);
     if (px >= c.W || py >= c.H) return;
     zmin_out[(size_t)py * c.W + px] = zmin;
@@ -463,11 +457,7 @@ __global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, f
     const int tx0 = real ? (tile % ntx) * kTile : 0, ty0 = real ? (tile / ntx) * kTile : 0;
     const int px = tx0 + lx, py = ty0 + ly;
     float zmin = __builtin_inff(), zmax = -__builtin_inff();
-    if (real) {
-        tile_range(v, tile, tx0, ty0, &tbl, true);
-        tile_pixel_range(&tbl, ly * kTile + lx, zmin, zmax);
-    }
-    finish_tile(v, real ? tile : -1, true);
+    if (real) tile_range(v, tile, px, py, &tbl, true, zmin, zmax);
     const bool inside = real && px < c.W && py < c.H;
     float4 out_p = make_float4(0.f, 0.f, 0.f, 0.f), out_n = make_float4(0.f, 0.f, 0.f, 0.f);
     if (inside && zmin <= zmax) {
@@ -503,7 +493,7 @@ __global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, f
                 // kSkip positions together; a clear bit proves the block absent,
                 // so those iterations are exactly the ones the loop would run.
                 const float stp = state == SEARCH_BLOCK_COARSE ? 8.0f : mu_v;
-                constexpr int kSkip = 8;
+                constexpr int kSkip = TSDF_RAY_SKIP;
                 float tk[kSkip];
                 uint32_t hk[kSkip], wk[kSkip];
                 float tt = t;
@@ -591,6 +581,7 @@ __global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, f
     }
     __syncthreads();
     if (threadIdx.x == 0 && wg_hits) v.acc_hits[tile] += wg_hits;
+    finish_tile(v, real ? tile : -1, true);
 }
 
 // ============================================================================
