@@ -81,14 +81,12 @@ __device__ __forceinline__ uint32_t rank_in(unsigned long long m)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Retrieval (Sec. 3.3): bucket, then the chain of `offset` links.  Matches an
-// entry whose position equals the key and whose ptr >= min_ptr.  Returns the
-// entry index (and its ptr) or -1.
-__device__ __forceinline__ int find_entry_in(const DEntry *entries, uint32_t n_buckets, uint32_t n_excess, int bx,
-                                             int by, int bz, int min_ptr, int *ptr_out)
+// Retrieval (Sec. 3.3) from bucket i = hash_index(bx, by, bz): the bucket,
+// then the chain of `offset` links.  Matches an entry whose position equals
+// the key and whose ptr >= min_ptr.  Returns the entry index (and its ptr) or -1.
+__device__ __forceinline__ int find_entry_from(const DEntry *entries, uint32_t n_buckets, uint32_t n_excess, uint32_t i,
+                                               int bx, int by, int bz, int min_ptr, int *ptr_out)
 {
-    if (!in_short_range(bx) || !in_short_range(by) || !in_short_range(bz)) return -1;
-    uint32_t i = hash_index(bx, by, bz, n_buckets - 1u);
     const uint32_t kxy = (uint32_t)(uint16_t)bx | ((uint32_t)(uint16_t)by << 16);
     for (uint32_t it = 0; it <= n_excess; ++it) {
         int4 w = load_entry(entries, i);
@@ -100,6 +98,15 @@ __device__ __forceinline__ int find_entry_in(const DEntry *entries, uint32_t n_b
         i = n_buckets + (uint32_t)(w.z - 1);
     }
     return -1;
+}
+
+// the same from the block position alone
+__device__ __forceinline__ int find_entry_in(const DEntry *entries, uint32_t n_buckets, uint32_t n_excess, int bx,
+                                             int by, int bz, int min_ptr, int *ptr_out)
+{
+    if (!in_short_range(bx) || !in_short_range(by) || !in_short_range(bz)) return -1;
+    return find_entry_from(entries, n_buckets, n_excess, hash_index(bx, by, bz, n_buckets - 1u), bx, by, bz, min_ptr,
+                           ptr_out);
 }
 
 __device__ __forceinline__ int find_entry(const Vol &v, int bx, int by, int bz, int min_ptr, int *ptr_out)
@@ -637,6 +644,22 @@ struct Cell {
     int p[8], j[8];
     float tx, ty, tz;
 };
+
+// in-block indices of the cell's corners: base voxel (ix, iy, iz), corner c
+// at + (c & 1, c >> 1 & 1, c >> 2); a step across a block face (local index
+// 7, flagged by sx, sy, sz) wraps to index 0 of the neighbouring block
+__device__ __forceinline__ void cell_index(int ix, int iy, int iz, bool sx, bool sy, bool sz, int (&j)[8])
+{
+    j[0] = (iz & 7) + 8 * (iy & 7) + 64 * (ix & 7);
+    const int dx = sx ? -448 : 64, dy = sy ? -56 : 8, dz = sz ? -7 : 1;
+    j[1] = j[0] + dx;
+    j[2] = j[0] + dy;
+    j[3] = j[1] + dy;
+    j[4] = j[0] + dz;
+    j[5] = j[1] + dz;
+    j[6] = j[2] + dz;
+    j[7] = j[3] + dz;
+}
 
 // absent voxels read 1.0; lerp a + (b - a) t along x, then y, then z
 __device__ __forceinline__ float cell_interp(const Cell &C, const int16_t (&s)[8])

@@ -202,9 +202,14 @@ struct TileTable {
     int complete;                         // the table holds the whole bin
 };
 
+// slot hash of the tile's private table: products of the 16-bit coordinates
+// (callers have range-checked them) with 23-bit constants, which compile to
+// full-rate 24-bit multiplies, folded to the table size
 __device__ __forceinline__ uint32_t table_slot(int bx, int by, int bz)
 {
-    return hash_index(bx, by, bz, (uint32_t)kTileTable - 1u);
+    const int x = (int16_t)bx, y = (int16_t)by, z = (int16_t)bz;
+    const uint32_t h = (uint32_t)(x * 0x1f1f1f) ^ (uint32_t)(y * 0x3c6ef3) ^ (uint32_t)(z * 0x5a8279);
+    return (h ^ (h >> 10)) & (uint32_t)(kTileTable - 1);
 }
 
 // The tile's block table and the search range of pixel (px, py) from the
@@ -312,12 +317,11 @@ __device__ __forceinline__ int lookup_block(const Vol &v, const TileTable *tt, i
     }
     if (local) return -1;
     int ptr = -1, e = -1;
-#if TSDF_RAY_BITMAP
     const uint32_t h = hash_index(bx, by, bz, v.n_buckets - 1u);
-    if ((gload(v.occ + (h >> 5)) >> (h & 31u)) & 1u) e = find_entry(v, bx, by, bz, 0, &ptr);
-#else
-    e = find_entry(v, bx, by, bz, 0, &ptr);
+#if TSDF_RAY_BITMAP
+    if ((gload(v.occ + (h >> 5)) >> (h & 31u)) & 1u)
 #endif
+        e = find_entry_from(v.entries, v.n_buckets, v.n_excess, h, bx, by, bz, 0, &ptr);
     return e >= 0 ? ptr : -1;
 }
 
@@ -366,33 +370,40 @@ __device__ __forceinline__ void cell_setup(const Vol &v, const TileTable *tt, fl
     C.p[5] = p101;
     C.p[6] = p011;
     C.p[7] = p111;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int cx = ix + (c & 1), cy = iy + ((c >> 1) & 1), cz = iz + (c >> 2);
-        C.j[c] = (cz & 7) + 8 * (cy & 7) + 64 * (cx & 7);
-    }
+    cell_index(ix, iy, iz, sx, sy, sz, C.j);
 }
 
+// the corners' SDF values (an absent corner reads block 0; its value is not
+// used).  kOff32: the voxel array spans at most 4 GiB, so a corner's address
+// is the array base plus a 32-bit byte offset of full-rate 24-bit products.
+template <bool kOff32>
 __device__ __forceinline__ void cell_load(const Vol &v, const Cell &C, int16_t (&s)[8])
 {
 #pragma unroll
-    for (int c = 0; c < 8; ++c)
-        s[c] = gload(reinterpret_cast<const int16_t *>(v.voxels + (size_t)(C.p[c] >= 0 ? C.p[c] : 0) * kBlockBytes) +
-                     (C.p[c] >= 0 ? C.j[c] : 0));
+    for (int c = 0; c < 8; ++c) {
+        const uint32_t pc = C.p[c] >= 0 ? (uint32_t)C.p[c] : 0u;
+        if (kOff32)
+            s[c] = gload(reinterpret_cast<const int16_t *>(v.voxels + (__umul24(pc, (uint32_t)kBlockBytes) +
+                                                                      2u * (uint32_t)C.j[c])));
+        else
+            s[c] = gload(reinterpret_cast<const int16_t *>(v.voxels + (size_t)pc * kBlockBytes) + C.j[c]);
+    }
 }
 
 // trilinear interpolation of F at voxel-unit P (Sec. 4.4)
+template <bool kOff32>
 __device__ __forceinline__ float trilinear(const Vol &v, const TileTable *tt, float X, float Y, float Z,
                                            BlockCache &cc)
 {
     Cell C;
     int16_t s[8];
     cell_setup(v, tt, X, Y, Z, cc, C);
-    cell_load(v, C, s);
+    cell_load<kOff32>(v, C, s);
     return cell_interp(C, s);
 }
 
 // F(A) - F(B) with the sixteen voxel loads of both cells issued together
+template <bool kOff32>
 __device__ __forceinline__ float trilinear_diff(const Vol &v, const TileTable *tt, float AX, float AY, float AZ,
                                                 float BX, float BY, float BZ, BlockCache &cc)
 {
@@ -400,8 +411,8 @@ __device__ __forceinline__ float trilinear_diff(const Vol &v, const TileTable *t
     int16_t sa[8], sb[8];
     cell_setup(v, tt, AX, AY, AZ, cc, A);
     cell_setup(v, tt, BX, BY, BZ, cc, B);
-    cell_load(v, A, sa);
-    cell_load(v, B, sb);
+    cell_load<kOff32>(v, A, sa);
+    cell_load<kOff32>(v, B, sb);
     return cell_interp(A, sa) - cell_interp(B, sb);
 }
 
@@ -438,7 +449,9 @@ __global__ __launch_bounds__(256) void k_range_write(Vol v, Cam c, float *zmin_o
 // from its bin (LDS), the state machine per pixel, then the two refinement
 // steps and the normal for the hits of the wave together
 // ============================================================================
-__global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, float4 *pts, float4 *nrm)
+// five waves per SIMD keep every tile of a 640x480 view resident at once
+template <bool kOff32>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_raycast(Vol v, Cam c, int all_blocks, float4 *pts, float4 *nrm)
 {
     __shared__ TileTable tbl;
     const int ntx = (c.W + kTile - 1) / kTile, nty = (c.H + kTile - 1) / kTile;
@@ -534,7 +547,7 @@ __global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, f
                 state = SEARCH_BLOCK_FINE;
                 t += mu_v;
             } else {
-                F = trilinear(v, &tbl, P0, P1, P2, cc);
+                F = trilinear<kOff32>(v, &tbl, P0, P1, P2, cc);
                 if (state == SEARCH_BLOCK_FINE) {
                     state = (F < 0.0f) ? WRONG_SIDE : SEARCH_SURFACE;
                 } else if (state == SEARCH_SURFACE) {
@@ -557,15 +570,15 @@ __global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, f
         if (state == BEHIND_SURFACE) {
             t += F * mu_v;
             float P0 = ox + t * dx, P1 = oy + t * dy, P2 = oz + t * dz;
-            F = trilinear(v, &tbl, P0, P1, P2, cc);
+            F = trilinear<kOff32>(v, &tbl, P0, P1, P2, cc);
             t += F * mu_v;
             P0 = ox + t * dx;
             P1 = oy + t * dy;
             P2 = oz + t * dz;
             out_p = make_float4(P0 * vs, P1 * vs, P2 * vs, 1.0f);
-            const float gx = trilinear_diff(v, &tbl, P0 + 1.0f, P1, P2, P0 - 1.0f, P1, P2, cc) * 0.5f;
-            const float gy = trilinear_diff(v, &tbl, P0, P1 + 1.0f, P2, P0, P1 - 1.0f, P2, cc) * 0.5f;
-            const float gz = trilinear_diff(v, &tbl, P0, P1, P2 + 1.0f, P0, P1, P2 - 1.0f, cc) * 0.5f;
+            const float gx = trilinear_diff<kOff32>(v, &tbl, P0 + 1.0f, P1, P2, P0 - 1.0f, P1, P2, cc) * 0.5f;
+            const float gy = trilinear_diff<kOff32>(v, &tbl, P0, P1 + 1.0f, P2, P0, P1 - 1.0f, P2, cc) * 0.5f;
+            const float gz = trilinear_diff<kOff32>(v, &tbl, P0, P1, P2 + 1.0f, P0, P1, P2 - 1.0f, cc) * 0.5f;
             const float gn = sqrtf((gx * gx + gy * gy) + gz * gz);
             if (gn > 0.0f) out_n = make_float4(gx / gn, gy / gn, gz / gn, 1.0f);
         }
@@ -860,7 +873,10 @@ hipError_t launch_raycast(const Vol &v, const Cam &c, bool all_blocks, float4 *p
 #else
     const int grid = ntiles;
 #endif
-    hipLaunchKernelGGL(k_raycast, dim3(grid), dim3(256), 0, s, v, c, all_blocks ? 1 : 0, pts, nrm);
+    if ((size_t)v.n_blocks * kBlockBytes <= 0xffffffffu)
+        hipLaunchKernelGGL(k_raycast<true>, dim3(grid), dim3(256), 0, s, v, c, all_blocks ? 1 : 0, pts, nrm);
+    else
+        hipLaunchKernelGGL(k_raycast<false>, dim3(grid), dim3(256), 0, s, v, c, all_blocks ? 1 : 0, pts, nrm);
     return hipGetLastError();
 }
 

@@ -397,17 +397,13 @@ __device__ __forceinline__ float m_field(const MTileLds<NT> &L, int ns, float P0
         const uint8_t *vox = L.vox[k];
         int16_t s[8];
         uint8_t w8[8];
+        cell_index(ix, iy, iz, sx, sy, sz, C.j);
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            const int cx = ix + (c & 1), cy = iy + ((c >> 1) & 1), cz = iz + (c >> 2);
-            C.j[c] = (cz & 7) + 8 * (cy & 7) + 64 * (cx & 7);
-        }
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
+            // an absent corner reads block 0 (its values are not used)
             const uint8_t *blk = vox + (size_t)(C.p[c] >= 0 ? C.p[c] : 0) * kBlockBytes;
-            const int j = C.p[c] >= 0 ? C.j[c] : 0;
-            s[c] = gload(reinterpret_cast<const int16_t *>(blk) + j);
-            w8[c] = gload(blk + 1024 + j);
+            s[c] = gload(reinterpret_cast<const int16_t *>(blk) + C.j[c]);
+            w8[c] = gload(blk + 1024 + C.j[c]);
         }
         // trilinear weight (absent voxels weigh 0), same order as the SDF
         float wf[8];
