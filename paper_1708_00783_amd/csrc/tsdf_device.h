@@ -415,11 +415,14 @@ __device__ __forceinline__ void visible_body(const Vol &v)
         for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i <= v.reqset_mask; i += gridDim.x * 256u)
             v.reqset[i] = 0ull;
     }
-    const uint32_t gwave = (blockIdx.x * 256u + threadIdx.x) / kWave;
-    const uint32_t nwaves = gridDim.x * (256u / kWave);
+    // a workgroup takes 256 chunks of 16 flags at a time: a scan within each
+    // wave, the four wave totals combined in LDS, one counter atomic per
+    // workgroup step (same-address device atomics serialise)
+    __shared__ uint32_t wtot[4], wbase;
+    const uint32_t wv = threadIdx.x / kWave;
     const uint32_t nchunks = (v.n_entries + 15u) / 16u;
-    for (uint32_t cb = gwave * kWave; cb < nchunks; cb += nwaves * kWave) {
-        const uint32_t ch = cb + lane;
+    for (uint32_t cb = blockIdx.x * 256u; cb < nchunks; cb += gridDim.x * 256u) {
+        const uint32_t ch = cb + threadIdx.x;
         uint4 f = make_uint4(0u, 0u, 0u, 0u);
         if (ch < nchunks) f = reinterpret_cast<const uint4 *>(v.vis)[ch];
         const uint32_t words[4] = {f.x, f.y, f.z, f.w};
@@ -432,18 +435,22 @@ __device__ __forceinline__ void visible_body(const Vol &v)
             uint32_t t = __shfl_up(incl, d);
             if ((int)lane >= d) incl += t;
         }
-        const uint32_t total = __shfl(incl, kWave - 1);
-        if (total == 0) continue;
-        uint32_t base = 0;
-        if (lane == kWave - 1) base = atomicAdd(&v.ctrl->n_vis, total);
-        base = __shfl(base, kWave - 1);
-        uint32_t pos = base + incl - cnt;
+        if (lane == kWave - 1) wtot[wv] = incl;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t total = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+            wbase = total ? atomicAdd(&v.ctrl->n_vis, total) : 0u;
+        }
+        __syncthreads();
+        uint32_t pos = wbase + incl - cnt;
+        for (uint32_t k = 0; k < wv; ++k) pos += wtot[k];
         if (cnt) {
 #pragma unroll
             for (int j = 0; j < 16; ++j)
                 if ((words[j >> 2] >> (8 * (j & 3))) & 0xffu) v.vlist[pos++] = (int32_t)(ch * 16u + (uint32_t)j);
             reinterpret_cast<uint4 *>(v.vis)[ch] = make_uint4(0u, 0u, 0u, 0u);
         }
+        __syncthreads();   // wtot and wbase are rewritten by the next step
     }
 }
 
