@@ -269,6 +269,9 @@ def render_rooms(seeds, n, workers, tag):
     return [a[i * n:(i + 1) * n] for i in range(len(seeds))]
 
 
+C5_COVERAGE = 0.95
+
+
 def run_c5(args):
     """Train the prefilter on pairs the method makes itself (fused-model
     raycasts as targets), then fuse held-out rooms with raw and with denoised
@@ -333,8 +336,14 @@ def run_c5(args):
     den = np.array([np.mean([r[n][0] for r in res["denoised"]]) for n in ns])
     traw = np.array([np.mean([r[n][1] for r in res["raw"]]) for n in ns])
     tden = np.array([np.mean([r[n][1] for r in res["denoised"]]) for n in ns])
+    hraw = np.array([np.mean([r[n][2] for r in res["raw"]]) for n in ns])
+    hden = np.array([np.mean([r[n][2] for r in res["denoised"]]) for n in ns])
     e_star = float(raw[-1])
-    reach = [j for j, v in enumerate(den) if v <= e_star]
+    # equal error at equal coverage: the RMS is over evaluation hits only, so a
+    # model fused from few frames must also cover the room (>= 95% of the raw
+    # path's hits with every frame) before its error counts
+    h_star = float(hraw[-1])
+    reach = [j for j, v in enumerate(den) if v <= e_star and hden[j] >= C5_COVERAGE * h_star]
     nd = ns[reach[0]] if reach else None
     t_plain = float(traw[-1])
     t_den = float(tden[reach[0]]) if reach else None
@@ -356,8 +365,11 @@ def run_c5(args):
         "frames_per_s_denoised": round(float(ns[-1] / tden[-1]), 2),
         "rms_mm": {"frames_fused": cps, "raw": [round(v * 1e3, 4) for v in raw],
                    "denoised": [round(v * 1e3, 4) for v in den]},
+        "eval_hits": {"raw": [int(v) for v in hraw], "denoised": [int(v) for v in hden],
+                      "coverage_required": C5_COVERAGE},
         "protocol": "each N fuses every (300/N)-th frame of the whole trajectory into a fresh volume (equal "
-                    "coverage); RMS of the analytic SDF at the hits of every 10th pose, every 4th pixel",
+                    "coverage); RMS of the analytic SDF at the hits of every 10th pose, every 4th pixel; N_d "
+                    "also needs >= 95% of the raw path's evaluation hits at N = 300",
         "train": {"loss_curve": [(a, round(b, 6)) for a, b, _ in losses], "seconds": round(t_train, 2),
                   "pairs_seconds": round(t_pairs, 2), "render_seconds": round(t_render, 2)},
     }

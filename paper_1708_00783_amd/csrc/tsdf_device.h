@@ -668,19 +668,28 @@ __device__ __forceinline__ void cell_index(int ix, int iy, int iz, bool sx, bool
     j[7] = j[3] + dz;
 }
 
-// absent voxels read 1.0; lerp a + (b - a) t along x, then y, then z
-__device__ __forceinline__ float cell_interp(const Cell &C, const int16_t (&s)[8])
+// absent voxels read 1.0 (bit c of `present` clear: corner c has no block);
+// lerp a + (b - a) t along x, then y, then z
+__device__ __forceinline__ float cell_lerp(uint32_t present, const int16_t (&s)[8], float tx, float ty, float tz)
 {
     float f[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) f[c] = C.p[c] >= 0 ? (float)s[c] * (1.0f / 32767.0f) : 1.0f;
-    const float c00 = f[0] + (f[1] - f[0]) * C.tx;
-    const float c10 = f[2] + (f[3] - f[2]) * C.tx;
-    const float c01 = f[4] + (f[5] - f[4]) * C.tx;
-    const float c11 = f[6] + (f[7] - f[6]) * C.tx;
-    const float c0 = c00 + (c10 - c00) * C.ty;
-    const float c1 = c01 + (c11 - c01) * C.ty;
-    return c0 + (c1 - c0) * C.tz;
+    for (int c = 0; c < 8; ++c) f[c] = ((present >> c) & 1u) ? (float)s[c] * (1.0f / 32767.0f) : 1.0f;
+    const float c00 = f[0] + (f[1] - f[0]) * tx;
+    const float c10 = f[2] + (f[3] - f[2]) * tx;
+    const float c01 = f[4] + (f[5] - f[4]) * tx;
+    const float c11 = f[6] + (f[7] - f[6]) * tx;
+    const float c0 = c00 + (c10 - c00) * ty;
+    const float c1 = c01 + (c11 - c01) * ty;
+    return c0 + (c1 - c0) * tz;
+}
+
+__device__ __forceinline__ float cell_interp(const Cell &C, const int16_t (&s)[8])
+{
+    uint32_t present = 0u;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) present |= (C.p[c] >= 0 ? 1u : 0u) << c;
+    return cell_lerp(present, s, C.tx, C.ty, C.tz);
 }
 
 }  // namespace

@@ -15,6 +15,8 @@
 // Compiled with -ffp-contract=off and correctly rounded fp32 division and
 // square root: every float expression below is evaluated as written, one IEEE
 // operation at a time.
+#include <type_traits>
+
 #include "tsdf_device.h"
 
 namespace tsdf {
@@ -336,11 +338,23 @@ __device__ __forceinline__ int cached_block(const Vol &v, const TileTable *tt, i
     return cc.ptr;
 }
 
+// A trilinear cell ready to load: the corners' SDF addresses as byte offsets
+// into the voxel array (32-bit when the array spans at most 4 GiB), which
+// corners have a block, and the interpolation fractions.  An absent corner
+// addresses block 0; its value is not used.
+template <bool kOff32>
+struct RayCell {
+    typename std::conditional<kOff32, uint32_t, size_t>::type o[8];
+    uint32_t present;
+    float tx, ty, tz;
+};
+
 // corner blocks: the cell's own block through the ray's cache; where the
 // cell crosses a block face (local index 7), the neighbouring blocks by
 // direct lookups
+template <bool kOff32>
 __device__ __forceinline__ void cell_setup(const Vol &v, const TileTable *tt, float X, float Y, float Z,
-                                           BlockCache &cc, Cell &C)
+                                           BlockCache &cc, RayCell<kOff32> &C)
 {
     const float bx = floorf(X), by = floorf(Y), bz = floorf(Z);
     C.tx = X - bx;
@@ -349,45 +363,40 @@ __device__ __forceinline__ void cell_setup(const Vol &v, const TileTable *tt, fl
     const int ix = (int)bx, iy = (int)by, iz = (int)bz;
     const int Bx = ix >> 3, By = iy >> 3, Bz = iz >> 3;
     const bool sx = (ix & 7) == 7, sy = (iy & 7) == 7, sz = (iz & 7) == 7;
-    const int p000 = cached_block(v, tt, Bx, By, Bz, cc);
-    int p100 = p000, p010 = p000, p001 = p000, p110 = p000, p101 = p000, p011 = p000, p111 = p000;
+    int p[8];
+    p[0] = cached_block(v, tt, Bx, By, Bz, cc);
+#pragma unroll
+    for (int c = 1; c < 8; ++c) p[c] = p[0];
     if (sx | sy | sz) {
         const bool lc = cc.local;
-        if (sx) p100 = lookup_block(v, tt, Bx + 1, By, Bz, lc);
-        if (sy) p010 = lookup_block(v, tt, Bx, By + 1, Bz, lc);
-        if (sz) p001 = lookup_block(v, tt, Bx, By, Bz + 1, lc);
-        p110 = (sx & sy) ? lookup_block(v, tt, Bx + 1, By + 1, Bz, lc) : (sx ? p100 : p010);
-        p101 = (sx & sz) ? lookup_block(v, tt, Bx + 1, By, Bz + 1, lc) : (sx ? p100 : p001);
-        p011 = (sy & sz) ? lookup_block(v, tt, Bx, By + 1, Bz + 1, lc) : (sy ? p010 : p001);
-        p111 = (sx & sy & sz) ? lookup_block(v, tt, Bx + 1, By + 1, Bz + 1, lc)
-                              : (sx & sy) ? p110 : (sx & sz) ? p101 : (sy & sz) ? p011 : sx ? p100 : sy ? p010 : p001;
+        if (sx) p[1] = lookup_block(v, tt, Bx + 1, By, Bz, lc);
+        if (sy) p[2] = lookup_block(v, tt, Bx, By + 1, Bz, lc);
+        if (sz) p[4] = lookup_block(v, tt, Bx, By, Bz + 1, lc);
+        p[3] = (sx & sy) ? lookup_block(v, tt, Bx + 1, By + 1, Bz, lc) : (sx ? p[1] : p[2]);
+        p[5] = (sx & sz) ? lookup_block(v, tt, Bx + 1, By, Bz + 1, lc) : (sx ? p[1] : p[4]);
+        p[6] = (sy & sz) ? lookup_block(v, tt, Bx, By + 1, Bz + 1, lc) : (sy ? p[2] : p[4]);
+        p[7] = (sx & sy & sz) ? lookup_block(v, tt, Bx + 1, By + 1, Bz + 1, lc)
+                              : (sx & sy) ? p[3] : (sx & sz) ? p[5] : (sy & sz) ? p[6] : sx ? p[1] : sy ? p[2] : p[4];
     }
-    C.p[0] = p000;
-    C.p[1] = p100;
-    C.p[2] = p010;
-    C.p[3] = p110;
-    C.p[4] = p001;
-    C.p[5] = p101;
-    C.p[6] = p011;
-    C.p[7] = p111;
-    cell_index(ix, iy, iz, sx, sy, sz, C.j);
-}
-
-// the corners' SDF values (an absent corner reads block 0; its value is not
-// used).  kOff32: the voxel array spans at most 4 GiB, so a corner's address
-// is the array base plus a 32-bit byte offset of full-rate 24-bit products.
-template <bool kOff32>
-__device__ __forceinline__ void cell_load(const Vol &v, const Cell &C, int16_t (&s)[8])
-{
+    int j[8];
+    cell_index(ix, iy, iz, sx, sy, sz, j);
+    C.present = 0u;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        const uint32_t pc = C.p[c] >= 0 ? (uint32_t)C.p[c] : 0u;
+        C.present |= (p[c] >= 0 ? 1u : 0u) << c;
+        const uint32_t pc = p[c] >= 0 ? (uint32_t)p[c] : 0u;
         if (kOff32)
-            s[c] = gload(reinterpret_cast<const int16_t *>(v.voxels + (__umul24(pc, (uint32_t)kBlockBytes) +
-                                                                      2u * (uint32_t)C.j[c])));
+            C.o[c] = __umul24(pc, (uint32_t)kBlockBytes) + 2u * (uint32_t)j[c];
         else
-            s[c] = gload(reinterpret_cast<const int16_t *>(v.voxels + (size_t)pc * kBlockBytes) + C.j[c]);
+            C.o[c] = (size_t)pc * kBlockBytes + 2u * (uint32_t)j[c];
     }
+}
+
+template <bool kOff32>
+__device__ __forceinline__ void cell_load(const Vol &v, const RayCell<kOff32> &C, int16_t (&s)[8])
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c) s[c] = gload(reinterpret_cast<const int16_t *>(v.voxels + C.o[c]));
 }
 
 // trilinear interpolation of F at voxel-unit P (Sec. 4.4)
@@ -395,11 +404,11 @@ template <bool kOff32>
 __device__ __forceinline__ float trilinear(const Vol &v, const TileTable *tt, float X, float Y, float Z,
                                            BlockCache &cc)
 {
-    Cell C;
+    RayCell<kOff32> C;
     int16_t s[8];
     cell_setup(v, tt, X, Y, Z, cc, C);
-    cell_load<kOff32>(v, C, s);
-    return cell_interp(C, s);
+    cell_load(v, C, s);
+    return cell_lerp(C.present, s, C.tx, C.ty, C.tz);
 }
 
 // F(A) - F(B) with the sixteen voxel loads of both cells issued together
@@ -407,13 +416,13 @@ template <bool kOff32>
 __device__ __forceinline__ float trilinear_diff(const Vol &v, const TileTable *tt, float AX, float AY, float AZ,
                                                 float BX, float BY, float BZ, BlockCache &cc)
 {
-    Cell A, B;
+    RayCell<kOff32> A, B;
     int16_t sa[8], sb[8];
     cell_setup(v, tt, AX, AY, AZ, cc, A);
     cell_setup(v, tt, BX, BY, BZ, cc, B);
-    cell_load<kOff32>(v, A, sa);
-    cell_load<kOff32>(v, B, sb);
-    return cell_interp(A, sa) - cell_interp(B, sb);
+    cell_load(v, A, sa);
+    cell_load(v, B, sb);
+    return cell_lerp(A.present, sa, A.tx, A.ty, A.tz) - cell_lerp(B.present, sb, B.tx, B.ty, B.tz);
 }
 
 // "allocated" test of the march: the block of floor(P) has a device block
@@ -449,9 +458,8 @@ __global__ __launch_bounds__(256) void k_range_write(Vol v, Cam c, float *zmin_o
 // from its bin (LDS), the state machine per pixel, then the two refinement
 // steps and the normal for the hits of the wave together
 // ============================================================================
-// five waves per SIMD keep every tile of a 640x480 view resident at once
 template <bool kOff32>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_raycast(Vol v, Cam c, int all_blocks, float4 *pts, float4 *nrm)
+__global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, float4 *pts, float4 *nrm)
 {
     __shared__ TileTable tbl;
     const int ntx = (c.W + kTile - 1) / kTile, nty = (c.H + kTile - 1) / kTile;
