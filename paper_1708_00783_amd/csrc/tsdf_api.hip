@@ -257,6 +257,7 @@ int tf_create(const tf_params *p, void *d_workspace, size_t bytes, void *h_store
     ctx->h_store = h_store;
     ctx->h_transfer = h_transfer;
     ctx->have_alloc = false;
+    ctx->bins_pending = false;
     ctx->host_flags = 0;
     if (p->swap_transfer_blocks) ctx->host_has.assign((size_t)p->n_buckets + p->n_excess, 0);
     Vol &v = ctx->v;
@@ -369,6 +370,7 @@ int tf_reset(tf_ctx *ctx, tf_stream stream)
     if (e == hipSuccess) e = launch_clear_bins(ctx->v.bin_count, ctx->L.max_tiles, s);
     if (e == hipSuccess) e = launch_clear_bins((int32_t *)ctx->v.acc_hits, 2 * ctx->L.max_tiles, s);
     ctx->have_alloc = false;
+    ctx->bins_pending = false;
     ctx->host_flags = 0;
     std::fill(ctx->host_has.begin(), ctx->host_has.end(), (uint8_t)0);
     return hip_status(e);
@@ -382,7 +384,13 @@ int tf_alloc_and_visible(tf_ctx *ctx, const void *d_depth, int depth_format, con
     Cam c;
     make_cam(pose_w2c, intr, c);
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e;
+    hipError_t e = hipSuccess;
+    if (ctx->bins_pending) {
+        // records of the previous visible list that no raycast consumed
+        e = launch_clear_bins(ctx->v.bin_count, ctx->L.max_tiles, s, ctx->v.ctrl);
+        if (e != hipSuccess) return TF_E_HIP;
+        ctx->bins_pending = false;
+    }
     {
         Timed t(ctx, TF_K_ALLOC_RAYS, s);
         e = launch_alloc_rays(ctx->v, c, d_depth, depth_format, s);
@@ -423,7 +431,13 @@ int tf_integrate(tf_ctx *ctx, const void *d_depth, int depth_format, const float
         ctx->alloc_depth = d_depth;
         ctx->alloc_fmt = depth_format;
     }
-    return hip_status(launch_integrate(ctx->v, c, s));
+    // the allocation's own pose: the raycast that follows will use the visible
+    // list's search range, so integration bins it on the way
+    const bool bin = !ctx->bins_pending && memcmp(pose_w2c, ctx->alloc_pose, sizeof(ctx->alloc_pose)) == 0;
+    const hipError_t e = launch_integrate(ctx->v, c, bin, s);
+    if (e != hipSuccess) return TF_E_HIP;
+    if (bin) ctx->bins_pending = true;
+    return TF_OK;
 }
 
 static bool same_view(const tf_ctx *ctx, const float *pose, const tf_intrinsics *K)
@@ -435,6 +449,22 @@ static bool same_view(const tf_ctx *ctx, const float *pose, const tf_intrinsics 
            a.height == K->height;
 }
 
+// The search-range bins of one raycast-kind call (consumed and cleared by it):
+// those tf_integrate made for the allocation view when the call has that view,
+// else k_range_bin's (after clearing unused integration bins)
+static hipError_t bin_range(tf_ctx *ctx, const Cam &c, bool all, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    if (ctx->bins_pending) {
+        ctx->bins_pending = false;
+        if (!all) return hipSuccess;
+        e = launch_clear_bins(ctx->v.bin_count, ctx->L.max_tiles, s, ctx->v.ctrl);
+        if (e != hipSuccess) return e;
+    }
+    Timed t(ctx, TF_K_RANGE_BIN, s);
+    return launch_range_bin(ctx->v, c, all, s);
+}
+
 int tf_raycast(tf_ctx *ctx, const float pose_w2c[16], const tf_intrinsics *intr, float *d_points,
                float *d_normals, tf_stream stream)
 {
@@ -443,12 +473,8 @@ int tf_raycast(tf_ctx *ctx, const float pose_w2c[16], const tf_intrinsics *intr,
     hipStream_t s = (hipStream_t)stream;
     Cam c;
     make_cam(pose_w2c, intr, c);
-    hipError_t e;
     const bool all = !same_view(ctx, pose_w2c, intr);
-    {
-        Timed t(ctx, TF_K_RANGE_BIN, s);
-        e = launch_range_bin(ctx->v, c, all, s);
-    }
+    const hipError_t e = bin_range(ctx, c, all, s);
     if (e != hipSuccess) return TF_E_HIP;
     Timed t(ctx, TF_K_RAYCAST, s);
     return hip_status(launch_raycast(ctx->v, c, all, (float4 *)d_points, (float4 *)d_normals, s));
@@ -461,7 +487,7 @@ int tf_range_image(tf_ctx *ctx, const float pose_w2c[16], const tf_intrinsics *i
     hipStream_t s = (hipStream_t)stream;
     Cam c;
     make_cam(pose_w2c, intr, c);
-    hipError_t e = launch_range_bin(ctx->v, c, !same_view(ctx, pose_w2c, intr), s);
+    const hipError_t e = bin_range(ctx, c, !same_view(ctx, pose_w2c, intr), s);
     if (e != hipSuccess) return TF_E_HIP;
     return hip_status(launch_range_write(ctx->v, c, d_zmin, d_zmax, s));
 }

@@ -31,6 +31,7 @@ struct tf_ctx {
     void *h_store;
     void *h_transfer;
     bool have_alloc;
+    bool bins_pending;                // tf_integrate binned the allocation view's search-range records
     tf_intrinsics alloc_intr;
     float alloc_pose[16];
     const void *alloc_depth;

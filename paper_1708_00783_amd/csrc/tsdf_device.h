@@ -462,9 +462,17 @@ __device__ __forceinline__ void visible_body(const Vol &v)
 // contiguous bytes of SDF and 8 of weight, so a wave moves a block in one
 // dwordx4 and one dwordx2 access per lane.
 // NT threads per workgroup; rcp_w (260 floats) and wg_cols are the caller's
-// LDS; dry: compute every update but store nothing (timing probes)
+// LDS; dry: compute every update but store nothing (timing probes).
+// bin: the camera is also the next raycast's (the allocation view): each
+// block's search-range record goes to slot i of the record list (an empty
+// record for a block off the image) and, by the wave's lanes, to the bin of
+// every 16x16 tile its box covers -- the work of k_range_bin over the visible
+// list, done while the block's voxels load.
+__device__ __forceinline__ bool block_record(const Vol &v, const Cam &c, int bx, int by, int bz, Rec &r);
+
 template <int NT>
-__device__ __forceinline__ void integrate_body(const Vol &v, const Cam &c, float *rcp_w, uint32_t *wg_cols, bool dry)
+__device__ __forceinline__ void integrate_body(const Vol &v, const Cam &c, float *rcp_w, uint32_t *wg_cols, bool dry,
+                                               bool bin = false)
 {
     for (int k = threadIdx.x; k < 260; k += NT) rcp_w[k] = k ? 1.0f / (float)k : 0.0f;
     __syncthreads();
@@ -484,18 +492,55 @@ __device__ __forceinline__ void integrate_body(const Vol &v, const Cam &c, float
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         v.ctrl->tot_vis += nvis;
         v.ctrl->n_integrate += 1ull;
+        if (bin) v.ctrl->n_rec = nvis;
     }
     uint32_t cols = 0;
+    const int ntx = (c.W + kTile - 1) / kTile;
 
     for (uint32_t i = gwave; i < nvis; i += nwaves) {
         const int e = v.vlist[i];
         const int4 w = load_entry(v.entries, (uint32_t)e);
         const int ptr = w.w;
-        if (ptr < 0) continue;
         const int bx = (int16_t)(w.x & 0xffff), by = (int16_t)((uint32_t)w.x >> 16), bz = (int16_t)(w.y & 0xffff);
+        if (ptr < 0) {
+            if (bin && lane == 0) {
+                Rec r = {};
+                r.x0 = 1;   // empty box
+                v.recs[i] = r;
+            }
+            continue;
+        }
         uint8_t *blk = v.voxels + (size_t)ptr * kBlockBytes;
         uint4 s8 = reinterpret_cast<const uint4 *>(blk)[lane];
         uint2 w8 = reinterpret_cast<const uint2 *>(blk + 1024)[lane];
+        if (bin) {
+            Rec r;
+            const bool emit = block_record(v, c, bx, by, bz, r);
+            if (!emit) {
+                r.x0 = 1;
+                r.x1 = 0;
+                r.y0 = 1;
+                r.y1 = 0;
+                r.zlo = __builtin_inff();
+                r.zhi = -__builtin_inff();
+            }
+            r.bx = (int16_t)bx;
+            r.by = (int16_t)by;
+            r.bz = (int16_t)bz;
+            r.pad = 0;
+            r.ptr = ptr;
+            r.pad2 = 0;
+            if (lane == 0) v.recs[i] = r;
+            if (emit) {
+                const int tx0 = r.x0 / kTile, tx1 = r.x1 / kTile, ty0 = r.y0 / kTile, ty1 = r.y1 / kTile;
+                const int nx = tx1 - tx0 + 1, cnt = nx * (ty1 - ty0 + 1);
+                for (int k = (int)lane; k < cnt; k += kWave) {
+                    const int t = (ty0 + k / nx) * ntx + tx0 + k % nx;
+                    const int sl = atomicAdd(&v.bin_count[t], 1);
+                    if (sl < kBinCap) v.bins[(size_t)t * kBinCap + sl] = r;
+                }
+            }
+        }
         uint32_t sw[4] = {s8.x, s8.y, s8.z, s8.w};
         uint32_t ww[2] = {w8.x, w8.y};
         const float X = (float)(8 * bx + lx) * vs;

@@ -126,12 +126,12 @@ struct Layout {
 
 // ---- kernel launchers (tsdf_kernels.hip) -----------------------------------
 hipError_t launch_init(const Vol &v, hipStream_t s);
-hipError_t launch_clear_bins(int32_t *bin_count, uint32_t n, hipStream_t s);
+hipError_t launch_clear_bins(int32_t *bin_count, uint32_t n, hipStream_t s, Ctrl *ctrl = nullptr);
 hipError_t launch_alloc_rays(const Vol &v, const Cam &c, const void *depth, int fmt, hipStream_t s);
 hipError_t launch_insert(const Vol &v, const Cam &c, hipStream_t s);
 hipError_t launch_visible(const Vol &v, hipStream_t s);
 hipError_t launch_depth_convert(const Vol &v, const void *depth, int fmt, int n, hipStream_t s);
-hipError_t launch_integrate(const Vol &v, const Cam &c, hipStream_t s);
+hipError_t launch_integrate(const Vol &v, const Cam &c, bool bin, hipStream_t s);
 hipError_t launch_range_bin(const Vol &v, const Cam &c, bool all_blocks, hipStream_t s);
 // all_blocks: the bins hold every allocated block (not only the visible list)
 hipError_t launch_raycast(const Vol &v, const Cam &c, bool all_blocks, float4 *pts, float4 *nrm, hipStream_t s);

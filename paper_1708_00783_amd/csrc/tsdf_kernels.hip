@@ -53,10 +53,12 @@ __global__ __launch_bounds__(256) void k_init(Vol v)
     }
 }
 
-__global__ __launch_bounds__(256) void k_clear_bins(int32_t *bin_count, uint32_t n)
+// zero n counters; with ctrl, also the record count (bins abandoned unread)
+__global__ __launch_bounds__(256) void k_clear_bins(int32_t *bin_count, uint32_t n, Ctrl *ctrl)
 {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         bin_count[i] = 0;
+    if (ctrl && blockIdx.x == 0 && threadIdx.x == 0) ctrl->n_rec = 0u;
 }
 
 // ============================================================================
@@ -72,11 +74,11 @@ __global__ __launch_bounds__(256) void k_insert(Vol v, Cam c) { insert_body(v, c
 
 __global__ __launch_bounds__(256) void k_visible(Vol v) { visible_body(v); }
 
-__global__ __launch_bounds__(256) void k_integrate(Vol v, Cam c)
+__global__ __launch_bounds__(256) void k_integrate(Vol v, Cam c, int bin)
 {
     __shared__ float rcp_w[260];
     __shared__ uint32_t wg_cols;
-    integrate_body<256>(v, c, rcp_w, &wg_cols, false);
+    integrate_body<256>(v, c, rcp_w, &wg_cols, false, bin != 0);
 }
 
 // ============================================================================
@@ -821,9 +823,9 @@ hipError_t launch_init(const Vol &v, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_clear_bins(int32_t *bin_count, uint32_t n, hipStream_t s)
+hipError_t launch_clear_bins(int32_t *bin_count, uint32_t n, hipStream_t s, Ctrl *ctrl)
 {
-    hipLaunchKernelGGL(k_clear_bins, dim3(cu_grid(n, 256, 1024)), dim3(256), 0, s, bin_count, n);
+    hipLaunchKernelGGL(k_clear_bins, dim3(cu_grid(n, 256, 1024)), dim3(256), 0, s, bin_count, n, ctrl);
     return hipGetLastError();
 }
 
@@ -861,9 +863,9 @@ hipError_t launch_depth_convert(const Vol &v, const void *depth, int fmt, int n,
     return hipGetLastError();
 }
 
-hipError_t launch_integrate(const Vol &v, const Cam &c, hipStream_t s)
+hipError_t launch_integrate(const Vol &v, const Cam &c, bool bin, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_integrate, dim3(kIntegrateGrid), dim3(256), 0, s, v, c);
+    hipLaunchKernelGGL(k_integrate, dim3(kIntegrateGrid), dim3(256), 0, s, v, c, bin ? 1 : 0);
     return hipGetLastError();
 }
 
