@@ -203,13 +203,26 @@ __device__ __forceinline__ bool block_in_frustum(const Vol &v, const Cam &c, int
     return false;
 }
 
+// Previous visible list entry i (Sec. 4.2, part 3): a block with a device
+// block that is not marked yet stays visible while it is in view.  Rays of
+// the same frame may mark it concurrently; both write kVisTouched.
+__device__ __forceinline__ void keep_in_view(const Vol &v, const Cam &c, uint32_t i)
+{
+    const int e = v.vlist[i];
+    const int4 w = load_entry(v.entries, (uint32_t)e);
+    if (w.w < 0 || v.vis[e] != 0) return;
+    const int bx = (int16_t)(w.x & 0xffff), by = (int16_t)((uint32_t)w.x >> 16), bz = (int16_t)(w.y & 0xffff);
+    if (block_in_frustum(v, c, bx, by, bz)) v.vis[e] = kVisTouched;
+}
+
 
 // ============================================================================
 // kernel bodies (each launch wraps one; blockIdx.x / gridDim.x index the work
 // of one volume, so a batched launch may use blockIdx.y for the volume)
 // ============================================================================
 // ============================================================================
-// allocation, part 1: segments, probes, marks, requests
+// allocation, part 1: segments, probes, marks, requests; the previous
+// visible list's frustum re-test (part 3) in the workgroups past the image
 // ============================================================================
 // write_depth: keep the converted depth map (integration reads it)
 template <int FMT>
@@ -218,14 +231,22 @@ __device__ __forceinline__ void alloc_rays_body(const Vol &v, const Cam &c, cons
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p == 0) {
         Ctrl *C = v.ctrl;
-        C->n_vis_prev = C->n_vis;
         C->sweep_req = 0u;
-        C->n_vis = 0u;
         C->n_new = 0u;
         C->n_swapped_in = 0u;
         C->n_swap_cand = 0u;
     }
     const int W = c.W, H = c.H;
+    const int pix_groups = (W * H + 255) / 256;
+    if ((int)blockIdx.x >= pix_groups) {
+        // the workgroups past the image re-test the previous visible list
+        // (its length is still in n_vis, cleared by the insertion kernel)
+        const uint32_t np = v.ctrl->n_vis;
+        const uint32_t stride = (gridDim.x - (uint32_t)pix_groups) * 256u;
+        for (uint32_t i = (blockIdx.x - (uint32_t)pix_groups) * 256u + threadIdx.x; i < np; i += stride)
+            keep_in_view(v, c, i);
+        return;
+    }
     if (p >= W * H) return;
     float d;
     if (FMT == TF_DEPTH_U16_MM)
@@ -288,7 +309,7 @@ __device__ __forceinline__ void alloc_rays_body(const Vol &v, const Cam &c, cons
 }
 
 // ============================================================================
-// allocation, parts 2 and 3a: insertion and the previous list's frustum test
+// allocation, part 2: insertion
 // ============================================================================
 __device__ __forceinline__ void insert_body(const Vol &v, const Cam &c)
 {
@@ -300,6 +321,7 @@ __device__ __forceinline__ void insert_body(const Vol &v, const Cam &c)
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         v.ctrl->sweep_req = v.ctrl->req_overflow;
         v.ctrl->req_overflow = 0u;
+        v.ctrl->n_vis = 0u;   // the compaction's counter (the previous list is re-tested)
     }
 
     for (uint32_t base = gwave * kWave; base < n; base += nwaves * kWave) {
@@ -381,14 +403,6 @@ __device__ __forceinline__ void insert_body(const Vol &v, const Cam &c)
         }
     }
 
-    const uint32_t np = v.ctrl->n_vis_prev;
-    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < np; i += gridDim.x * 256u) {
-        const int e = v.vlist[i];
-        const int4 w = load_entry(v.entries, (uint32_t)e);
-        if (w.w < 0 || v.vis[e] != 0) continue;
-        const int bx = (int16_t)(w.x & 0xffff), by = (int16_t)((uint32_t)w.x >> 16), bz = (int16_t)(w.y & 0xffff);
-        if (block_in_frustum(v, c, bx, by, bz)) v.vis[e] = kVisTouched;
-    }
 }
 
 // ============================================================================
@@ -468,7 +482,7 @@ __device__ __forceinline__ void visible_body(const Vol &v)
 // record for a block off the image) and, by the wave's lanes, to the bin of
 // every 16x16 tile its box covers -- the work of k_range_bin over the visible
 // list, done while the block's voxels load.
-__device__ __forceinline__ bool block_record(const Vol &v, const Cam &c, int bx, int by, int bz, Rec &r);
+__device__ __forceinline__ bool block_record_wave(const Vol &v, const Cam &c, int bx, int by, int bz, Rec &r);
 
 template <int NT>
 __device__ __forceinline__ void integrate_body(const Vol &v, const Cam &c, float *rcp_w, uint32_t *wg_cols, bool dry,
@@ -515,7 +529,7 @@ __device__ __forceinline__ void integrate_body(const Vol &v, const Cam &c, float
         uint2 w8 = reinterpret_cast<const uint2 *>(blk + 1024)[lane];
         if (bin) {
             Rec r;
-            const bool emit = block_record(v, c, bx, by, bz, r);
+            const bool emit = block_record_wave(v, c, bx, by, bz, r);
             if (!emit) {
                 r.x0 = 1;
                 r.x1 = 0;
@@ -683,6 +697,59 @@ __device__ __forceinline__ bool cube_record(const float *M, const Cam &c, float 
 __device__ __forceinline__ bool block_record(const Vol &v, const Cam &c, int bx, int by, int bz, Rec &r)
 {
     return cube_record(c.M, c, v.voxel, 8 * bx, 8 * by, 8 * bz, 8, r);
+}
+
+// block_record by a whole wave (every lane active, the same block): lane l
+// takes corner l & 7, and min / max go round each 8-lane group by shuffles
+// (order-free, so the record is the serial one); a block reaching in front of
+// the near plane takes the serial form for its edge crossings.  Every lane
+// returns the same record.
+__device__ __forceinline__ bool block_record_wave(const Vol &v, const Cam &c, int bx, int by, int bz, Rec &r)
+{
+    const int k = (int)(lane_id() & 7u);
+    const int px = 8 * (bx + (k & 1)), py = 8 * (by + ((k >> 1) & 1)), pz = 8 * (bz + (k >> 2));
+    const float *M = c.M;
+    const float X = (float)px * v.voxel, Y = (float)py * v.voxel, Z = (float)pz * v.voxel;
+    const float xs = ((M[0] * X + M[1] * Y) + M[2] * Z) + M[3];
+    const float ys = ((M[4] * X + M[5] * Y) + M[6] * Z) + M[7];
+    const float zs = ((M[8] * X + M[9] * Y) + M[10] * Z) + M[11];
+    const bool front = !(zs < kZNear);
+    const float rz = 1.0f / (front ? zs : 1.0f);
+    const float u = (c.fx * xs) * rz + c.cx;
+    const float vv = (c.fy * ys) * rz + c.cy;
+    float zlo = zs, zhi = zs;
+    float umin = front ? u : __builtin_inff(), umax = front ? u : -__builtin_inff();
+    float vmin = front ? vv : __builtin_inff(), vmax = front ? vv : -__builtin_inff();
+#pragma unroll
+    for (int d = 1; d < 8; d <<= 1) {
+        float o = __shfl_xor(zlo, d);
+        zlo = o < zlo ? o : zlo;
+        o = __shfl_xor(zhi, d);
+        zhi = o > zhi ? o : zhi;
+        o = __shfl_xor(umin, d);
+        umin = o < umin ? o : umin;
+        o = __shfl_xor(umax, d);
+        umax = o > umax ? o : umax;
+        o = __shfl_xor(vmin, d);
+        vmin = o < vmin ? o : vmin;
+        o = __shfl_xor(vmax, d);
+        vmax = o > vmax ? o : vmax;
+    }
+    if (zhi < kZNear) return false;
+    if (zlo < kZNear) return block_record(v, c, bx, by, bz, r);
+    float fx0 = floorf(umin), fx1 = ceilf(umax), fy0 = floorf(vmin), fy1 = ceilf(vmax);
+    if (fx0 < 0.0f) fx0 = 0.0f;
+    if (fy0 < 0.0f) fy0 = 0.0f;
+    if (fx1 > (float)(c.W - 1)) fx1 = (float)(c.W - 1);
+    if (fy1 > (float)(c.H - 1)) fy1 = (float)(c.H - 1);
+    if (fx0 > fx1 || fy0 > fy1) return false;
+    r.x0 = (int16_t)(int)fx0;
+    r.x1 = (int16_t)(int)fx1;
+    r.y0 = (int16_t)(int)fy0;
+    r.y1 = (int16_t)(int)fy1;
+    r.zlo = zlo;
+    r.zhi = zhi;
+    return true;
 }
 
 // ============================================================================

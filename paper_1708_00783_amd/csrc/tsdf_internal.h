@@ -20,6 +20,7 @@ constexpr float kZNear = 0.05f;         // near plane of the search-range projec
 constexpr int kMaxRaySteps = 65536;     // hard bound on raycast iterations
 constexpr int kMaxSegmentSamples = 64;  // samples kept per pixel segment
 constexpr int kIntegrateGrid = 2048;    // workgroups of the integration launch
+constexpr int kKeepGroups = 64;         // allocation workgroups past the image: the previous list's frustum test
 
 // vis[] byte per hash entry, reset by the visible-list compaction
 constexpr uint8_t kVisTouched = 1;      // touched by a ray segment or kept in view
@@ -55,7 +56,6 @@ struct alignas(256) Ctrl {
     int32_t free_excess;     // height of the free excess-slot stack
     uint32_t n_req;          // unique insertion requests of the current frame
     uint32_t n_vis;          // visible-list length
-    uint32_t n_vis_prev;     // previous visible-list length (read by k_insert)
     uint32_t n_ret;          // blocks to return to the free stack
     uint32_t flags;          // sticky TF_FLAG_*
     uint32_t n_rec;          // search-range records of the current raycast

@@ -2,13 +2,16 @@
 //
 // Frame pipeline (one launch each, counts stay on the device):
 //   k_alloc_rays   one lane per pixel: depth ingest, segment samples, hash probes,
-//                  visible marks, de-duplicated insertion requests      (Sec. 4.2, part 1)
+//                  visible marks, de-duplicated insertion requests; workgroups
+//                  past the image re-test the previous visible list   (Sec. 4.2, parts 1, 3)
 //   k_insert       one lane per request: free-stack pops, bucket claim or excess
-//                  chain link, block init; frustum re-test of the previous visible
-//                  list                                                  (Sec. 4.2, parts 2-3)
-//   k_visible      16 entries per lane: wave-scan compaction of the marks (Sec. 4.2, part 3)
-//   k_integrate    one wave per visible block, 8 voxels per lane         (Sec. 4.3)
-//   k_range_bin    one lane per block: projected box -> 16x16-pixel tile bins (Sec. 4.4)
+//                  chain link, block init                              (Sec. 4.2, part 2)
+//   k_visible      16 entries per lane: scan compaction of the marks   (Sec. 4.2, part 3)
+//   k_integrate    one wave per visible block, 8 voxels per lane; for the
+//                  allocation view also the block's search-range record and
+//                  its 16x16-pixel tile bins                           (Sec. 4.3, 4.4)
+//   k_range_bin    one lane per block: projected box -> tile bins, for any
+//                  other view                                          (Sec. 4.4)
 //   k_raycast      one workgroup per 16x16 tile: per-pixel search range from the
 //                  tile's bin, then the ray state machine                (Sec. 4.4)
 //
@@ -832,7 +835,7 @@ hipError_t launch_clear_bins(int32_t *bin_count, uint32_t n, hipStream_t s, Ctrl
 hipError_t launch_alloc_rays(const Vol &v, const Cam &c, const void *depth, int fmt, hipStream_t s)
 {
     const int npix = c.W * c.H;
-    const dim3 g((npix + 255) / 256), b(256);
+    const dim3 g((npix + 255) / 256 + kKeepGroups), b(256);
     if (fmt == TF_DEPTH_U16_MM)
         hipLaunchKernelGGL(k_alloc_rays<TF_DEPTH_U16_MM>, g, b, 0, s, v, c, depth);
     else

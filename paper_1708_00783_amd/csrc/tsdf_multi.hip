@@ -572,7 +572,7 @@ __global__ __launch_bounds__(TW *TH) void k_m_range_write(const MSub *subs, cons
 hipError_t launch_m_alloc(const Vol *vols, const MFrame *f, int w, int h, hipStream_t s)
 {
     const int npix = w * h;
-    hipLaunchKernelGGL(k_m_alloc, dim3((npix + 255) / 256, kMaxSel), dim3(256), 0, s, vols, f);
+    hipLaunchKernelGGL(k_m_alloc, dim3((npix + 255) / 256 + kKeepGroups, kMaxSel), dim3(256), 0, s, vols, f);
     if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     hipLaunchKernelGGL(k_m_insert, dim3(128, kMaxSel), dim3(256), 0, s, vols, f);
     if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
