@@ -35,8 +35,10 @@ N_TRAJ = 300
 PROFILE_EVERY = 8
 
 
+# the sources the single-volume kernels are built from (the traffic figures of
+# profiles/ are keyed by their hash)
 KERNEL_SOURCES = ("paper_1708_00783_amd/csrc/tsdf_device.h", "paper_1708_00783_amd/csrc/tsdf_kernels.hip",
-                  "paper_1708_00783_amd/csrc/tsdf_internal.h", "paper_1708_00783_amd/csrc/tsdf_multi.hip")
+                  "paper_1708_00783_amd/csrc/tsdf_internal.h", "include/tsdf.h")
 
 
 def measured_traffic(kernel):

@@ -589,9 +589,19 @@ __global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, f
             P1 = oy + t * dy;
             P2 = oz + t * dz;
             out_p = make_float4(P0 * vs, P1 * vs, P2 * vs, 1.0f);
-            const float gx = trilinear_diff<kOff32>(v, &tbl, P0 + 1.0f, P1, P2, P0 - 1.0f, P1, P2, cc) * 0.5f;
-            const float gy = trilinear_diff<kOff32>(v, &tbl, P0, P1 + 1.0f, P2, P0, P1 - 1.0f, P2, cc) * 0.5f;
-            const float gz = trilinear_diff<kOff32>(v, &tbl, P0, P1, P2 + 1.0f, P0, P1, P2 - 1.0f, cc) * 0.5f;
+            // one axis per iteration: unrolled, the compiler keeps all six
+            // cells in flight, and the registers cost half the waves per SIMD
+            float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+#pragma unroll 1
+            for (int ax = 0; ax < 3; ++ax) {
+                const float d = trilinear_diff<kOff32>(v, &tbl, ax == 0 ? P0 + 1.0f : P0, ax == 1 ? P1 + 1.0f : P1,
+                                                       ax == 2 ? P2 + 1.0f : P2, ax == 0 ? P0 - 1.0f : P0,
+                                                       ax == 1 ? P1 - 1.0f : P1, ax == 2 ? P2 - 1.0f : P2, cc) *
+                                0.5f;
+                gx = ax == 0 ? d : gx;
+                gy = ax == 1 ? d : gy;
+                gz = ax == 2 ? d : gz;
+            }
             const float gn = sqrtf((gx * gx + gy * gy) + gz * gz);
             if (gn > 0.0f) out_n = make_float4(gx / gn, gy / gn, gz / gn, 1.0f);
         }
