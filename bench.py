@@ -56,7 +56,8 @@ def measured_traffic(kernel):
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(f):
             m = re.match(r"traffic (\S+) ([0-9a-f]{16}) (\d+)", line.strip())
-            if m and m.group(1) == kernel and m.group(2) == sha:
+            # the trace names a template instance (k_raycast<true>); match the kernel
+            if m and m.group(1).split("<")[0] == kernel and m.group(2) == sha:
                 return int(m.group(3))
     return None
 
@@ -194,10 +195,20 @@ def run_c4(args):
         mm.frame(d_frames[k], K, poses[k % configs.C4_N_FRAMES], sels[k], views_of(k), use_graph=graph, stream=stream)
 
     step(0, graph=False)
-    best, best_ms = mm.autotune(d_frames[1], K, poses[1], sels[1], views_of(1), reps=3, stream=stream)
-    print(f"[bench] c4 autotune: {best} ({best_ms:.3f} ms)", file=sys.stderr, flush=True)
     for k in range(1, args.warmup):
         step(k)
+    if args.c4_tile:
+        tw, th = (int(x) for x in args.c4_tile.split("x"))
+        mm.set_config(tile_w=tw, tile_h=th)
+        best = mm.get_config().as_dict()
+        print(f"[bench] c4 fixed shape: {best}", file=sys.stderr, flush=True)
+    else:
+        # tuned on the first timed frame: the submaps grow over the run, so an
+        # early frame would pick for a lighter workload
+        w = args.warmup
+        best, best_ms = mm.autotune(d_frames[w], K, poses[w % configs.C4_N_FRAMES], sels[w], views_of(w), reps=3,
+                                    stream=stream)
+        print(f"[bench] c4 autotune: {best} ({best_ms:.3f} ms)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     s0 = mm.stats()
     t0 = time.perf_counter()
@@ -453,6 +464,7 @@ def main():
     ap.add_argument("--workers", type=int, default=min(16, cpu_cores()))
     ap.add_argument("--frames-cache", default=None,
                     help="npy file holding the generated depth frames (written if absent)")
+    ap.add_argument("--c4-tile", default="", help="c4: fixed raycast tile shape WxH instead of autotuning")
     ap.add_argument("--workload", choices=("c2", "c4", "c5", "prefilter"), default="c2",
                     help="c2: one volume, the headline metric; c4: 64 batched submaps, 8 views; "
                          "c5: train the depth prefilter, then denoised vs plain at equal surface error")

@@ -194,7 +194,8 @@ struct MTileLds {
     int smid[kMaxSubmaps];
     unsigned long long mask;
     uint32_t n_tab, hits, unfit;                // unfit: a record whose key or pointer does not pack
-    uint4 box[NT];                              // a chunk of the bin: x0, y0, x1, y1 (int16), zlo, zhi
+    uint32_t zlo[NT], zhi[NT];                  // per-pixel range as float bits (all values > 0)
+    uint32_t zlo_all, zhi_all;                  // from records covering the whole tile
 };
 
 template <int NT>
@@ -216,66 +217,64 @@ __device__ __forceinline__ unsigned long long mkey(int sm, int bx, int by, int b
            ((unsigned long long)(by & 0x7ff) << 35) | ((unsigned long long)(bx & 0x7ff) << 24);
 }
 
-// Search range of pixel (px, py) and the tile's LDS state from its bin.  The
-// bin goes through LDS in chunks of NT records (one per thread, which also
-// enters it in the block table); every thread then takes the min / max over
-// the chunk's records whose box holds its pixel (the per-pixel loop itself,
-// no atomics).  Every thread of the workgroup calls it; zmin = +inf and
-// zmax = -inf when no record covers the pixel.
+// Search range of the pixel and the tile's LDS state from its bin.  The range
+// is a min/max over the records covering the pixel: each record updates the
+// pixels of its box inside the tile with LDS atomics (positive floats order
+// like their bit patterns); a record covering the whole tile updates one
+// tile-wide pair instead.  Every thread of the workgroup calls it; pixel
+// (px, py) is the calling thread's, the tile spans [tx0, tx0 + TW) x [ty0, ty0 + TH).
 template <int NT, int TW, int TH>
-__device__ __forceinline__ void m_tile_setup(const MSub *subs, const MTiles &t, uint32_t g, int px, int py,
-                                             MTileLds<NT> &L, float &zmin, float &zmax)
+__device__ __forceinline__ void m_tile_setup(const MSub *subs, const MTiles &t, uint32_t g, int tx0, int ty0,
+                                             MTileLds<NT> &L)
 {
     constexpr int TT = MTileLds<NT>::TT;
     for (int k = threadIdx.x; k < TT; k += NT) L.slot[k] = 0ull;
+    L.zlo[threadIdx.x] = 0x7f800000u;   // +inf
+    L.zhi[threadIdx.x] = 0u;            // below every positive float
     if (threadIdx.x == 0) {
         L.mask = 0ull;
         L.n_tab = 0u;
         L.hits = 0u;
         L.unfit = 0u;
+        L.zlo_all = 0x7f800000u;
+        L.zhi_all = 0u;
     }
     const uint32_t o0 = t.off[g];
     uint32_t o1 = t.off[g + 1];
     if (o1 > t.cap) o1 = t.cap;
     const int n = o1 > o0 ? (int)(o1 - o0) : 0;
-    float lo = __builtin_inff(), hi = -__builtin_inff();
-    for (int base = 0; base < n; base += NT) {
-        __syncthreads();   // the cleared state, or the previous chunk consumed
-        const int j = base + (int)threadIdx.x;
-        if (j < n) {
-            const Rec r = t.bins[o0 + (uint32_t)j];
-            atomicOr(&L.mask, 1ull << (uint32_t)r.pad);
-            // keys in one bin are distinct; keep the table at most half full
-            if (!mfits(r.bx, r.by, r.bz) || r.ptr >= (1 << 24)) {
-                L.unfit = 1u;
-            } else if (atomicAdd(&L.n_tab, 1u) < (uint32_t)(TT / 2)) {
-                const unsigned long long val = mkey(r.pad, r.bx, r.by, r.bz) | (unsigned long long)r.ptr;
-                uint32_t sl = mslot<NT>(r.pad, r.bx, r.by, r.bz);
-                for (int k = 0; k < TT; ++k) {
-                    if (atomicCAS(&L.slot[sl], 0ull, val) == 0ull) break;
-                    sl = (sl + 1u) & (uint32_t)(TT - 1);
-                }
-            }
-            L.box[threadIdx.x] = make_uint4((uint32_t)(uint16_t)r.x0 | ((uint32_t)(uint16_t)r.y0 << 16),
-                                            (uint32_t)(uint16_t)r.x1 | ((uint32_t)(uint16_t)r.y1 << 16),
-                                            __float_as_uint(r.zlo), __float_as_uint(r.zhi));
-        }
-        __syncthreads();
-        const int m = n - base < NT ? n - base : NT;
-        for (int q = 0; q < m; ++q) {
-            const uint4 b = L.box[q];
-            const int x0 = (int16_t)(b.x & 0xffffu), y0 = (int16_t)(b.x >> 16);
-            const int x1 = (int16_t)(b.y & 0xffffu), y1 = (int16_t)(b.y >> 16);
-            if (px >= x0 && px <= x1 && py >= y0 && py <= y1) {
-                const float zl = __uint_as_float(b.z), zh = __uint_as_float(b.w);
-                lo = zl < lo ? zl : lo;
-                hi = zh > hi ? zh : hi;
+    __syncthreads();
+    for (int j = (int)threadIdx.x; j < n; j += NT) {
+        const Rec r = t.bins[o0 + (uint32_t)j];
+        atomicOr(&L.mask, 1ull << (uint32_t)r.pad);
+        // keys in one bin are distinct; keep the table at most half full
+        if (!mfits(r.bx, r.by, r.bz) || r.ptr >= (1 << 24)) {
+            L.unfit = 1u;
+        } else if (atomicAdd(&L.n_tab, 1u) < (uint32_t)(TT / 2)) {
+            const unsigned long long val = mkey(r.pad, r.bx, r.by, r.bz) | (unsigned long long)r.ptr;
+            uint32_t sl = mslot<NT>(r.pad, r.bx, r.by, r.bz);
+            for (int k = 0; k < TT; ++k) {
+                if (atomicCAS(&L.slot[sl], 0ull, val) == 0ull) break;
+                sl = (sl + 1u) & (uint32_t)(TT - 1);
             }
         }
+        const int x0 = r.x0 > tx0 ? r.x0 : tx0, x1 = r.x1 < tx0 + TW - 1 ? r.x1 : tx0 + TW - 1;
+        const int y0 = r.y0 > ty0 ? r.y0 : ty0, y1 = r.y1 < ty0 + TH - 1 ? r.y1 : ty0 + TH - 1;
+        if (x0 > x1 || y0 > y1) continue;
+        const uint32_t lo = __float_as_uint(r.zlo), hi = __float_as_uint(r.zhi);
+        if (x0 == tx0 && x1 == tx0 + TW - 1 && y0 == ty0 && y1 == ty0 + TH - 1) {
+            atomicMin(&L.zlo_all, lo);
+            atomicMax(&L.zhi_all, hi);
+            continue;
+        }
+        for (int y = y0; y <= y1; ++y)
+            for (int x = x0; x <= x1; ++x) {
+                const int pi = (y - ty0) * TW + (x - tx0);
+                atomicMin(&L.zlo[pi], lo);
+                atomicMax(&L.zhi[pi], hi);
+            }
     }
     __syncthreads();
-    zmin = lo;
-    zmax = hi;
     // the tile's submaps, ascending
     if (threadIdx.x < (unsigned)kMaxSubmaps) {
         const unsigned long long m = L.mask;
@@ -294,6 +293,16 @@ __device__ __forceinline__ void m_tile_setup(const MSub *subs, const MTiles &t, 
         }
     }
     __syncthreads();
+}
+
+// the calling thread's pixel range after m_tile_setup (pixel index pi in the tile)
+template <int NT>
+__device__ __forceinline__ void m_pixel_range(const MTileLds<NT> &L, int pi, float &zmin, float &zmax)
+{
+    const uint32_t lo = L.zlo[pi] < L.zlo_all ? L.zlo[pi] : L.zlo_all;
+    const uint32_t hi = L.zhi[pi] > L.zhi_all ? L.zhi[pi] : L.zhi_all;
+    zmin = __uint_as_float(lo);                               // +inf when nothing covers the pixel
+    zmax = hi ? __uint_as_float(hi) : -__builtin_inff();
 }
 
 // device pointer of block (bx, by, bz) of the k-th submap of the tile (-1 =
@@ -385,8 +394,6 @@ __device__ __forceinline__ float m_field(const MTileLds<NT> &L, int ns, float P0
         C.p[5] = p101;
         C.p[6] = p011;
         C.p[7] = p111;
-        // no corner block: trilinear weight 0, the submap does not contribute
-        if ((p000 & p100 & p010 & p110 & p001 & p101 & p011 & p111) < 0) continue;
         const uint8_t *vox = L.vox[k];
         int16_t s[8];
         uint8_t w8[8];
@@ -450,7 +457,8 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
     const int lx = (q % (TW / 8)) * 8 + (i & 7), ly = (q / (TW / 8)) * 8 + (i >> 3);
     const int px = tx0 + lx, py = ty0 + ly;
     float zmin, zmax;
-    m_tile_setup<NT, TW, TH>(subs, t, (uint32_t)g, px, py, L, zmin, zmax);
+    m_tile_setup<NT, TW, TH>(subs, t, (uint32_t)g, tx0, ty0, L);
+    m_pixel_range<NT>(L, ly * TW + lx, zmin, zmax);
     const int ns = __popcll(L.mask);
     const bool full = L.n_tab <= (uint32_t)(MTileLds<NT>::TT / 2) && !L.unfit;   // the table holds the whole bin
     const bool inside = px < W && py < H;
@@ -551,7 +559,8 @@ __global__ __launch_bounds__(TW *TH) void k_m_range_write(const MSub *subs, cons
     const int lx = (q % (TW / 8)) * 8 + (i & 7), ly = (q / (TW / 8)) * 8 + (i >> 3);
     const int px = tx0 + lx, py = ty0 + ly;
     float zmin, zmax;
-    m_tile_setup<NT, TW, TH>(subs, t, (uint32_t)g, px, py, L, zmin, zmax);
+    m_tile_setup<NT, TW, TH>(subs, t, (uint32_t)g, tx0, ty0, L);
+    m_pixel_range<NT>(L, ly * TW + lx, zmin, zmax);
     if (px >= V.cam.W || py >= V.cam.H) return;
     zmin_out[(size_t)py * V.cam.W + px] = zmin;
     zmax_out[(size_t)py * V.cam.W + px] = zmax;
