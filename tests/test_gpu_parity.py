@@ -83,6 +83,33 @@ def test_ragged_image_and_foreign_view():
     compare_raycast(gp, gn, op, on, "ragged foreign intrinsics")
 
 
+def test_search_range_reuse_and_rebuild():
+    """The allocation view's search range is binned by the integration launch
+    and consumed by the next raycast of that view; a repeated raycast, a
+    raycast of another view in between, a range image, and an integration at
+    a pose other than the allocation's (no binning) all match the oracle."""
+    d, p, K, _ = configs.c1_frames(5)
+    pair = Pair(configs.C1_VOLUME, K.width, K.height)
+    for k in range(4):
+        pair.frame(d[k], K, p[k])
+    for tag, pose in (("allocation view", p[3]), ("allocation view again", p[3]), ("other view", p[0]),
+                      ("allocation view after another", p[3])):
+        gp, gn, op, on = pair.raycast(K, pose)
+        nhit, flips = compare_raycast(gp, gn, op, on, tag)
+        _log(f"{tag}: hits {nhit} flips {flips}")
+    # bins pending from the integration, then a range image of the allocation view
+    pair.frame(d[4], K, p[4])
+    gz0, gz1 = pair.g.range_image(p[4], K)
+    oz0, oz1 = pair.o.range_image(K.width, K.height, K.as_array(), p[4])
+    assert np.array_equal(gz0.cpu().numpy(), oz0) and np.array_equal(gz1.cpu().numpy(), oz1)
+    # allocation at one pose, integration at another: the raycast bins for itself
+    pair.alloc(d[3], K, p[3])
+    pair.integrate(d[3], K, p[2])
+    gp, gn, op, on = pair.raycast(K, p[3])
+    compare_raycast(gp, gn, op, on, "integration at another pose")
+    compare_tables(pair.g, pair.o, "integration at another pose")
+
+
 def test_empty_and_invalid_depth():
     K = configs.C1_INTR
     pair = Pair(configs.C1_VOLUME, K.width, K.height)
