@@ -88,6 +88,7 @@ Layout make_layout(const tf_params *p)
     L.acc_cols = take((size_t)kIntegrateGrid * 8);
     L.acc_hits = take((size_t)L.max_tiles * 8);
     L.occ = take((size_t)p->n_buckets / 8);
+    L.brick = take((size_t)kBrickWords * 4);
     if (p->swap_transfer_blocks) {
         L.host_has = take(n_vis);
         L.xfer_idx = take((size_t)p->swap_transfer_blocks * 4);
@@ -279,6 +280,7 @@ int tf_create(const tf_params *p, void *d_workspace, size_t bytes, void *h_store
     v.acc_cols = (unsigned long long *)(b + L.acc_cols);
     v.acc_hits = (unsigned long long *)(b + L.acc_hits);
     v.occ = (uint32_t *)(b + L.occ);
+    v.brick = (uint32_t *)(b + L.brick);
     v.host_has = p->swap_transfer_blocks ? b + L.host_has : nullptr;
     v.xfer_idx = p->swap_transfer_blocks ? (int32_t *)(b + L.xfer_idx) : nullptr;
     v.xfer_vox = p->swap_transfer_blocks ? b + L.xfer_vox : nullptr;

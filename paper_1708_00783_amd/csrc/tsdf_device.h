@@ -24,7 +24,7 @@ constexpr int kWave = 64;
 #define TSDF_RAY_BITMAP 1       // consult the bucket-occupancy bitmap before an entry
 #endif
 #ifndef TSDF_RAY_SKIP
-#define TSDF_RAY_SKIP 8         // march positions tested together against the bitmap
+#define TSDF_RAY_SKIP 4         // march positions tested together against the occupancy bricks
 #endif
 
 __device__ __forceinline__ uint32_t hash_index(int x, int y, int z, uint32_t mask)
@@ -34,6 +34,21 @@ __device__ __forceinline__ uint32_t hash_index(int x, int y, int z, uint32_t mas
 }
 
 __device__ __forceinline__ bool in_short_range(int a) { return a >= -32768 && a <= 32767; }
+
+// Block-occupancy bricks: one bit per block position modulo a window of
+// 256 blocks per axis, each 32-bit word a 4 x 4 x 2 brick of blocks, so that
+// the positions of a ray share words.  Set when an entry is inserted, never
+// cleared (a swapped-out entry keeps its bit): a clear bit proves the block
+// absent; blocks a window apart share a bit (a false "maybe").
+__device__ __forceinline__ uint32_t brick_word(int bx, int by, int bz)
+{
+    return (((uint32_t)(bx >> 2) & 63u) << 13) | (((uint32_t)(by >> 2) & 63u) << 7) | ((uint32_t)(bz >> 1) & 127u);
+}
+
+__device__ __forceinline__ uint32_t brick_bit(int bx, int by, int bz)
+{
+    return 1u << (((uint32_t)bx & 3u) | (((uint32_t)by & 3u) << 2) | (((uint32_t)bz & 1u) << 4));
+}
 
 __device__ __forceinline__ unsigned long long pack_key(int x, int y, int z)
 {
@@ -382,7 +397,10 @@ __device__ __forceinline__ void insert_body(const Vol &v, const Cam &c)
         }
         if (entry >= 0) {
             v.vis[entry] = kVisNew;
-            if (revive < 0) atomicOr(&v.occ[h >> 5], 1u << (h & 31u));
+            if (revive < 0) {
+                atomicOr(&v.occ[h >> 5], 1u << (h & 31u));
+                atomicOr(&v.brick[brick_word(bx, by, bz)], brick_bit(bx, by, bz));
+            }
             if (revive < 0 && v.alist) {
                 // submap volumes keep a list of their allocated blocks (no swapping there)
                 const uint32_t ai = atomicAdd(&v.ctrl->n_alloc, 1u);

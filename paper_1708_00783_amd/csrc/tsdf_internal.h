@@ -20,6 +20,7 @@ constexpr float kZNear = 0.05f;         // near plane of the search-range projec
 constexpr int kMaxRaySteps = 65536;     // hard bound on raycast iterations
 constexpr int kMaxSegmentSamples = 64;  // samples kept per pixel segment
 constexpr int kIntegrateGrid = 2048;    // workgroups of the integration launch
+constexpr uint32_t kBrickWords = 1u << 19;   // block-occupancy bricks: 2 MiB per volume
 constexpr int kKeepGroups = 64;         // allocation workgroups past the image: the previous list's frustum test
 
 // vis[] byte per hash entry, reset by the visible-list compaction
@@ -96,6 +97,7 @@ struct Vol {
     unsigned long long *acc_cols;   // per integration workgroup: 8-voxel columns written back
     unsigned long long *acc_hits;   // per raycast tile: pixels with a hit
     uint32_t *occ;                  // bucket-occupancy bitmap: bit h set once any entry hashes to h
+    uint32_t *brick;                // block-occupancy bricks (kBrickWords words), see brick_word
     uint8_t *host_has;              // swapping: 1 if the host store holds data for the entry
     int32_t *xfer_idx;              // swapping: transfer-buffer entry indices
     uint8_t *xfer_vox;              // swapping: transfer-buffer blocks
@@ -120,7 +122,7 @@ struct Cam {
 // workspace carving
 struct Layout {
     size_t entries, vis, free_blocks, free_excess, voxels, vlist, reqset, reqs, ret, depth,
-        recs, bins, bin_count, ctrl, acc_cols, acc_hits, occ, host_has, xfer_idx, xfer_vox, swap_chunks, total;
+        recs, bins, bin_count, ctrl, acc_cols, acc_hits, occ, brick, host_has, xfer_idx, xfer_vox, swap_chunks, total;
     uint32_t reqset_size, max_req, max_tiles;
 };
 

@@ -48,6 +48,7 @@ __global__ __launch_bounds__(256) void k_init(Vol v)
         for (size_t i = gid; i < nvis; i += stride) v.host_has[i] = 0;
     for (size_t i = gid; i < (size_t)kIntegrateGrid; i += stride) v.acc_cols[i] = 0ull;
     for (size_t i = gid; i < (size_t)(v.n_buckets / 32u); i += stride) v.occ[i] = 0u;
+    for (size_t i = gid; i < (size_t)kBrickWords; i += stride) v.brick[i] = 0u;
     if (gid == 0) {
         Ctrl c = {};
         c.free_blocks = (int32_t)v.n_blocks;
@@ -307,7 +308,7 @@ struct BlockCache {
 };
 
 // device pointer of a block (-1 = absent or not on the device): the tile's
-// LDS table first; unless `local`, then the bucket bitmap and the hash table.
+// LDS table first; unless `local`, then the occupancy bricks and the hash table.
 // `local` holds for a ray whose points all lie at or beyond the near plane in
 // a tile whose table holds its whole bin: every block within kExpandV voxels
 // of such a point is in the bin, so a miss proves absence.
@@ -323,12 +324,12 @@ __device__ __forceinline__ int lookup_block(const Vol &v, const TileTable *tt, i
         sl = (sl + 1u) & (uint32_t)(kTileTable - 1);
     }
     if (local) return -1;
-    int ptr = -1, e = -1;
-    const uint32_t h = hash_index(bx, by, bz, v.n_buckets - 1u);
 #if TSDF_RAY_BITMAP
-    if ((gload(v.occ + (h >> 5)) >> (h & 31u)) & 1u)
+    if (!(gload(v.brick + brick_word(bx, by, bz)) & brick_bit(bx, by, bz))) return -1;
 #endif
-        e = find_entry_from(v.entries, v.n_buckets, v.n_excess, h, bx, by, bz, 0, &ptr);
+    int ptr = -1;
+    const int e = find_entry_from(v.entries, v.n_buckets, v.n_excess, hash_index(bx, by, bz, v.n_buckets - 1u), bx,
+                                  by, bz, 0, &ptr);
     return e >= 0 ? ptr : -1;
 }
 
@@ -515,7 +516,7 @@ __global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, f
 #if TSDF_RAY_BITMAP
             if (state == SEARCH_BLOCK_COARSE || state == SEARCH_BLOCK_FINE) {
                 // Empty-space skip: the march stays in this state with a fixed
-                // step while it finds no block.  Test the bucket bits of the next
+                // step while it finds no block.  Test the occupancy bricks of the next
                 // kSkip positions together; a clear bit proves the block absent,
                 // so those iterations are exactly the ones the loop would run.
                 const float stp = state == SEARCH_BLOCK_COARSE ? 8.0f : mu_v;
@@ -527,8 +528,8 @@ __global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, f
                 for (int k = 0; k < kSkip; ++k) {
                     tk[k] = tt;
                     const int b0 = block_of(ox + tt * dx), b1 = block_of(oy + tt * dy), b2 = block_of(oz + tt * dz);
-                    hk[k] = hash_index(b0, b1, b2, v.n_buckets - 1u);
-                    wk[k] = gload(v.occ + (hk[k] >> 5));
+                    hk[k] = brick_bit(b0, b1, b2);
+                    wk[k] = gload(v.brick + brick_word(b0, b1, b2));
                     tt += stp;
                 }
                 bool stop = false;
@@ -536,7 +537,7 @@ __global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, f
                 for (int k = 0; k < kSkip; ++k) {
                     if (stop) continue;
                     t = tk[k];
-                    if (!(t < t_end && steps < kMaxRaySteps) || ((wk[k] >> (hk[k] & 31u)) & 1u)) {
+                    if (!(t < t_end && steps < kMaxRaySteps) || (wk[k] & hk[k])) {
                         stop = true;
                         continue;
                     }
