@@ -435,6 +435,7 @@ __device__ __forceinline__ void visible_body(const Vol &v)
         C->tot_new += C->n_new;
         C->n_req = 0u;
         C->frames += 1u;
+        if (v.alist) C->n_marked = C->n_alloc;   // the marking kernel has run on the new blocks
         const uint32_t nr = C->n_ret;
         if (nr) {
             const int32_t h = C->free_blocks;

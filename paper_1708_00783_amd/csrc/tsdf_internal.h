@@ -69,6 +69,7 @@ struct alignas(256) Ctrl {
     uint32_t n_swap_cand;    // swap-out candidates gathered by the last swap selection
     uint32_t sweep_req;      // copy of req_overflow taken by k_insert for k_visible
     uint32_t n_alloc;        // submap volumes: length of the allocated-block list
+    uint32_t n_marked;       // submap volumes: list entries already marked in the world occupancy
     // totals since creation (each written by a single thread of one kernel)
     unsigned long long tot_vis;        // blocks visited by integration
     unsigned long long tot_rec;        // projected blocks behind raycast search ranges
@@ -200,11 +201,13 @@ struct MTiles {
     Rec *bins;            // entries, pad = submap index
     MCtrl *mc;
     unsigned long long *acc_hits;   // per tile: pixels with a hit
+    uint32_t *wocc;       // world occupancy bricks (kBrickWords): 8-voxel world cells any submap block may reach
     uint32_t cap;         // capacity of bins
     uint32_t n_tiles;     // tiles over all views
 };
 
-hipError_t launch_m_alloc(const Vol *vols, const MFrame *f, int max_w, int max_h, hipStream_t s);
+hipError_t launch_m_alloc(const Vol *vols, const MSub *subs, const MFrame *f, uint32_t *wocc, int max_w, int max_h,
+                          hipStream_t s);
 hipError_t launch_m_integrate(const Vol *vols, const MFrame *f, int nt, int grid, bool dry, hipStream_t s);
 hipError_t launch_m_bin(const MSub *subs, const MFrame *f, const MTiles &t, int n_views, int grid, float voxel,
                         hipStream_t s);

@@ -172,7 +172,50 @@ __global__ __launch_bounds__(256) void k_m_clear(MTiles t)
         t.off[i] = 0u;
         t.acc_hits[i] = 0ull;
     }
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < kBrickWords; i += gridDim.x * 256u) t.wocc[i] = 0u;
     if (blockIdx.x == 0 && threadIdx.x == 0) t.off[t.n_tiles] = 0u;
+}
+
+// World occupancy: every block a selected submap gained this frame (its
+// allocated list past n_marked) marks the 8-voxel world cells of its cube's
+// world-space box, grown by one voxel (far above the rounding of the pose
+// transforms).  A clear cell then proves that no submap has a block at any
+// point of it.  Blocks are never removed, so marks are never cleared.
+__global__ __launch_bounds__(256) void k_m_mark(const Vol *vols, const MSub *subs, const MFrame *f, uint32_t *wocc)
+{
+    const int y = (int)blockIdx.y;
+    if (y >= f->n_sel) return;
+    const int si = f->sel[y];
+    const Vol v = vols[si];
+    const MSub &S = subs[si];
+    const uint32_t n0 = v.ctrl->n_marked;
+    uint32_t n1 = v.ctrl->n_alloc;
+    if (n1 > v.n_blocks) n1 = v.n_blocks;
+    for (uint32_t i = n0 + blockIdx.x * 256u + threadIdx.x; i < n1; i += gridDim.x * 256u) {
+        const int4 a = v.alist[i];
+        const int bx = (int16_t)(a.x & 0xffff), by = (int16_t)((uint32_t)a.x >> 16), bz = a.y;
+        float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+        float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+        for (int k = 0; k < 8; ++k) {
+            // corner of the block in submap voxel units, to world: P = R^T (Q - s)
+            const float q0 = (float)(8 * (bx + (k & 1))) - S.s[0];
+            const float q1 = (float)(8 * (by + ((k >> 1) & 1))) - S.s[1];
+            const float q2 = (float)(8 * (bz + (k >> 2))) - S.s[2];
+            for (int r = 0; r < 3; ++r) {
+                const float w = (S.R[r] * q0 + S.R[3 + r] * q1) + S.R[6 + r] * q2;
+                lo[r] = w < lo[r] ? w : lo[r];
+                hi[r] = w > hi[r] ? w : hi[r];
+            }
+        }
+        int c0[3], c1[3];
+        for (int r = 0; r < 3; ++r) {
+            c0[r] = ((int)floorf(lo[r] - 1.0f)) >> 3;
+            c1[r] = ((int)floorf(hi[r] + 1.0f)) >> 3;
+        }
+        for (int cx = c0[0]; cx <= c1[0]; ++cx)
+            for (int cy = c0[1]; cy <= c1[1]; ++cy)
+                for (int cz = c0[2]; cz <= c1[2]; ++cz) atomicOr(&wocc[brick_word(cx, cy, cz)], brick_bit(cx, cy, cz));
+    }
 }
 
 // ============================================================================
@@ -485,7 +528,10 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
             ++steps;
             const float P0 = ox + tt * dx, P1 = oy + tt * dy, P2 = oz + tt * dz;
             const bool local = full && tt * zscale >= kZNear;
-            const bool alloc = m_allocated(L, ns, P0, P1, P2, local);
+            // a world cell no submap block reaches: nothing is allocated there
+            const int c0 = block_of(P0), c1 = block_of(P1), c2 = block_of(P2);
+            const bool alloc = (gload(t.wocc + brick_word(c0, c1, c2)) & brick_bit(c0, c1, c2)) &&
+                               m_allocated(L, ns, P0, P1, P2, local);
             if (state == M_COARSE) {
                 if (!alloc) {
                     tt += 8.0f;
@@ -569,12 +615,15 @@ __global__ __launch_bounds__(TW *TH) void k_m_range_write(const MSub *subs, cons
 // ============================================================================
 // launchers
 // ============================================================================
-hipError_t launch_m_alloc(const Vol *vols, const MFrame *f, int w, int h, hipStream_t s)
+hipError_t launch_m_alloc(const Vol *vols, const MSub *subs, const MFrame *f, uint32_t *wocc, int w, int h,
+                          hipStream_t s)
 {
     const int npix = w * h;
     hipLaunchKernelGGL(k_m_alloc, dim3((npix + 255) / 256 + kKeepGroups, kMaxSel), dim3(256), 0, s, vols, f);
     if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     hipLaunchKernelGGL(k_m_insert, dim3(128, kMaxSel), dim3(256), 0, s, vols, f);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    hipLaunchKernelGGL(k_m_mark, dim3(64, kMaxSel), dim3(256), 0, s, vols, subs, f, wocc);
     if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     hipLaunchKernelGGL(k_m_visible, dim3(256, kMaxSel), dim3(256), 0, s, vols, f);
     return hipGetLastError();
