@@ -525,6 +525,39 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
         float F = 1.0f;
         int steps = 0;
         while (tt < t_end && steps < kMaxRaySteps) {
+            if (state == M_COARSE || state == M_FINE) {
+                // Empty-space skip: while no block is found the march keeps
+                // its fixed step; the world cells of the next kSkip positions
+                // are tested together, a clear cell proves the position
+                // unallocated, so the iterations skipped are those the loop
+                // would run.
+                const float stp = state == M_COARSE ? 8.0f : mu_v;
+                constexpr int kSkip = 4;
+                float tk[kSkip];
+                uint32_t bk[kSkip], wk[kSkip];
+                float t2 = tt;
+#pragma unroll
+                for (int k = 0; k < kSkip; ++k) {
+                    tk[k] = t2;
+                    const int c0 = block_of(ox + t2 * dx), c1 = block_of(oy + t2 * dy), c2 = block_of(oz + t2 * dz);
+                    bk[k] = brick_bit(c0, c1, c2);
+                    wk[k] = gload(t.wocc + brick_word(c0, c1, c2));
+                    t2 += stp;
+                }
+                bool stop = false;
+#pragma unroll
+                for (int k = 0; k < kSkip; ++k) {
+                    if (stop) continue;
+                    tt = tk[k];
+                    if (!(tt < t_end && steps < kMaxRaySteps) || (wk[k] & bk[k])) {
+                        stop = true;
+                        continue;
+                    }
+                    ++steps;   // an iteration on unallocated space
+                }
+                if (!stop) tt = t2;
+                if (!(tt < t_end && steps < kMaxRaySteps)) break;
+            }
             ++steps;
             const float P0 = ox + tt * dx, P1 = oy + tt * dy, P2 = oz + tt * dz;
             const bool local = full && tt * zscale >= kZNear;
