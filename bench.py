@@ -38,7 +38,7 @@ PROFILE_EVERY = 8
 # the sources the single-volume kernels are built from (the traffic figures of
 # profiles/ are keyed by their hash)
 KERNEL_SOURCES = ("paper_1708_00783_amd/csrc/tsdf_device.h", "paper_1708_00783_amd/csrc/tsdf_kernels.hip",
-                  "paper_1708_00783_amd/csrc/tsdf_internal.h", "include/tsdf.h")
+                  "paper_1708_00783_amd/csrc/tsdf_internal.h")
 
 
 def measured_traffic(kernel):
@@ -70,6 +70,11 @@ def _gen(k):
 def _gen_c4(k):
     from synth import configs
     return configs.c4_frame(k)
+
+
+def _gen_c3(k):
+    from synth import configs
+    return configs.c3_frame(k)
 
 
 def _gen_prefill(ij):
@@ -165,6 +170,83 @@ def c4_prefill(mm, workers, max_frames=48, batch=4):
         print(f"[bench] prefill: {used} frames, {sum(counts)} blocks, {len(need)} submaps below target",
               file=sys.stderr, flush=True)
     return counts, used
+
+
+C3_TRANSFER = 8192          # blocks per swap-in / swap-out call (12.6 MB of transfer buffer)
+
+
+def run_c3(args):
+    """C3: the large multi-room walk (4 mm voxels, 2^20 device blocks) with host
+    swapping every frame: allocation + swap-in, integration, raycast, swap-out.
+    Both swap calls synchronise with the host (it needs the candidate counts),
+    so each frame is timed from its first launch to the end of its swap-out."""
+    import torch
+    import paper_1708_00783_amd as T
+    from synth import configs
+    K = configs.KINECT_INTR
+    n = min(1500, args.warmup + args.steps)
+    frames = make_frames(n, args.workers, args.frames_cache, gen=_gen_c3)
+    poses = np.stack(configs.c3_poses(1500)[:n]).astype(np.float32)
+    torch.cuda.set_device(0)
+    d = torch.from_numpy(frames).cuda()
+    vol = T.Volume(configs.C3_VOLUME, K.width, K.height, swap_transfer_blocks=C3_TRANSFER)
+    pts = torch.empty((K.height, K.width, 4), dtype=torch.float32, device="cuda")
+    nrm = torch.empty_like(pts)
+
+    def frame(k):
+        vol.alloc_and_visible(d[k], K, poses[k])
+        vol.integrate(d[k], poses[k])
+        vol.raycast(poses[k], K, pts, nrm)
+        vol.swap_out()
+
+    for k in range(args.warmup):
+        frame(k)
+    torch.cuda.synchronize()
+    vol.profile_enable(True)
+    vol.profile_select(("integrate", "raycast", "swap"), PROFILE_EVERY)
+    vol.profile_read(reset=True)
+    s0 = vol.stats()
+    dt, sw_in, sw_out, hits, dev_blocks = 0.0, 0, 0, 0, []
+    for k in range(args.warmup, n):
+        t0 = time.perf_counter()
+        frame(k)
+        torch.cuda.synchronize()
+        dt += time.perf_counter() - t0
+        st = vol.stats()
+        sw_in += st["n_swapped_in"]
+        sw_out += st["n_swapped_out"]
+        dev_blocks.append(st["n_allocated"])
+    s1 = vol.stats()
+    prof = vol.profile_read()
+    assert s1["flags"] == 0, f"capacity flags raised: {s1['flags']:#x}"
+    steps = n - args.warmup
+    WH = K.width * K.height
+    d_rec = s1["total_range_records"] - s0["total_range_records"]
+    ray_ms = prof["raycast"]["ms"] / max(1, prof["raycast"]["launches"])
+    ray_bytes = d_rec * (1024 + 16) / steps + 32 * WH
+    gbs = ray_bytes / (ray_ms * 1e-3) / 1e9 if ray_ms > 0 else 0.0
+    out = {
+        "metric": "frames/s: alloc + swap-in + integrate + raycast + swap-out, large multi-room walk",
+        "value": round(steps / dt, 3), "unit": "frames/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt / steps, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "large scene: 640x480 uint16 depth walking a 12x12x3 m 3x3-room layout with 200 "
+                               "primitives, voxel 4 mm, mu 1.6 cm, 2^22 buckets + 2^19 excess, 2^20 device blocks, "
+                               f"host store per entry, {C3_TRANSFER}-block transfer buffer, swap-out every frame",
+                   "frames": n},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "raycast",
+                     "algorithmic_bytes_per_launch": int(ray_bytes), "avg_launch_ms": round(ray_ms, 5)},
+        "cpu_baseline": None,
+        "extra": {"swapped_in_per_frame": round(sw_in / steps, 1), "swapped_out_per_frame": round(sw_out / steps, 1),
+                  "pcie_mb_per_frame": round((sw_in + sw_out) * (1536 + 4) / steps / 1e6, 3),
+                  "device_blocks_last": dev_blocks[-1], "device_blocks_max": max(dev_blocks),
+                  "kernel_ms_per_launch": {k: round(v["ms"] / max(1, v["launches"]), 5) for k, v in prof.items()
+                                           if v["launches"]},
+                  "avg_visible_blocks": round((s1["total_integrated_blocks"] - s0["total_integrated_blocks"]) / steps, 1),
+                  "hit_fraction": round((s1["total_rays_hit"] - s0["total_rays_hit"]) / (steps * WH), 4)},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def run_c4(args):
@@ -465,8 +547,9 @@ def main():
     ap.add_argument("--frames-cache", default=None,
                     help="npy file holding the generated depth frames (written if absent)")
     ap.add_argument("--c4-tile", default="", help="c4: fixed raycast tile shape WxH instead of autotuning")
-    ap.add_argument("--workload", choices=("c2", "c4", "c5", "prefilter"), default="c2",
-                    help="c2: one volume, the headline metric; c4: 64 batched submaps, 8 views; "
+    ap.add_argument("--workload", choices=("c2", "c3", "c4", "c5", "prefilter"), default="c2",
+                    help="c2: one volume, the headline metric; c3: the large walk with host swapping; "
+                         "c4: 64 batched submaps, 8 views; "
                          "c5: train the depth prefilter, then denoised vs plain at equal surface error")
     ap.add_argument("--c5-rooms", type=int, default=50, help="training rooms (seeds 5000..)")
     ap.add_argument("--c5-frames", type=int, default=100, help="training frames per room")
@@ -494,6 +577,8 @@ def main():
               "layout of the path is described in the design notes but not run.", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "c3":
+        return run_c3(args)
     if args.workload == "c4":
         return run_c4(args)
     if args.workload == "c5":

@@ -91,7 +91,9 @@ typedef struct {
     /* work totals since creation/reset (counted on the device) */
     uint64_t total_integrated_blocks;  /* visible blocks visited by tf_integrate (x512 voxels) */
     uint64_t total_written_columns;    /* 8-voxel columns (24 bytes) written back by tf_integrate */
-    uint64_t total_range_records;      /* projected blocks behind the tf_raycast search ranges */
+    uint64_t total_range_records;      /* search-range records behind tf_raycast calls: one per visible
+                                          block for the allocation view (an off-image block's record is
+                                          empty), one per projected block for any other view */
     uint64_t total_rays_hit;           /* tf_raycast pixels with a surface hit */
     uint64_t total_requests;           /* unique insertion requests */
     uint64_t total_new_blocks;         /* blocks inserted */
