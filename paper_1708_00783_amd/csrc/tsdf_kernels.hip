@@ -692,9 +692,12 @@ __global__ __launch_bounds__(256) void k_mark_visible(Vol v, uint8_t val)
 
 // swap-out candidates: a device block and not visible.  Ordered selection of
 // the lowest entry indices: per-chunk counts, a scan, then in-order writes.
+// A bucket whose occupancy bit is clear never held an entry: no read.
 __device__ __forceinline__ bool swap_out_candidate(const Vol &v, uint32_t e)
 {
-    return e < v.n_entries && v.vis[e] == 0 && load_entry(v.entries, e).w >= 0;
+    if (e >= v.n_entries || v.vis[e] != 0) return false;
+    if (e < v.n_buckets && !((v.occ[e >> 5] >> (e & 31u)) & 1u)) return false;
+    return load_entry(v.entries, e).w >= 0;
 }
 
 __device__ __forceinline__ uint32_t wg_exclusive_scan(uint32_t x, uint32_t *lds, uint32_t &total)
@@ -715,12 +718,14 @@ __device__ __forceinline__ uint32_t wg_exclusive_scan(uint32_t x, uint32_t *lds,
     return base + incl - x;
 }
 
+// a chunk is 16 slices of 256 consecutive entries, one entry per thread in a
+// slice (coalesced reads)
 __global__ __launch_bounds__(256) void k_swap_count(Vol v)
 {
     __shared__ uint32_t lds[4];
-    const uint32_t e0 = blockIdx.x * (uint32_t)kSwapChunk + threadIdx.x * 16u;
+    const uint32_t e0 = blockIdx.x * (uint32_t)kSwapChunk + threadIdx.x;
     uint32_t cnt = 0;
-    for (int k = 0; k < 16; ++k) cnt += swap_out_candidate(v, e0 + k) ? 1u : 0u;
+    for (int k = 0; k < 16; ++k) cnt += swap_out_candidate(v, e0 + 256u * (uint32_t)k) ? 1u : 0u;
     uint32_t total;
     wg_exclusive_scan(cnt, lds, total);
     if (threadIdx.x == 0) v.swap_chunks[blockIdx.x] = total;
@@ -741,19 +746,21 @@ __global__ __launch_bounds__(256) void k_swap_scan(Vol v, uint32_t nchunks)
     if (threadIdx.x == 0) v.ctrl->n_swap_cand = carry;
 }
 
+// in entry order: slice by slice, a workgroup scan of the candidate flags
 __global__ __launch_bounds__(256) void k_swap_pick(Vol v)
 {
     __shared__ uint32_t lds[4];
-    const uint32_t e0 = blockIdx.x * (uint32_t)kSwapChunk + threadIdx.x * 16u;
-    uint32_t cnt = 0;
-    for (int k = 0; k < 16; ++k) cnt += swap_out_candidate(v, e0 + k) ? 1u : 0u;
-    uint32_t total;
-    uint32_t pos = v.swap_chunks[blockIdx.x] + wg_exclusive_scan(cnt, lds, total);
-    for (int k = 0; k < 16; ++k)
-        if (swap_out_candidate(v, e0 + k)) {
-            if (pos < v.transfer_blocks) v.xfer_idx[pos] = (int32_t)(e0 + k);
-            ++pos;
-        }
+    uint32_t base = v.swap_chunks[blockIdx.x];
+    if (base >= v.transfer_blocks) return;   // uniform: every pick of this chunk is past the capacity
+    const uint32_t e0 = blockIdx.x * (uint32_t)kSwapChunk + threadIdx.x;
+    for (int k = 0; k < 16; ++k) {
+        const uint32_t e = e0 + 256u * (uint32_t)k;
+        const bool c = swap_out_candidate(v, e);
+        uint32_t total;
+        const uint32_t pos = base + wg_exclusive_scan(c ? 1u : 0u, lds, total);
+        if (c && pos < v.transfer_blocks) v.xfer_idx[pos] = (int32_t)e;
+        base += total;
+    }
 }
 
 // device blocks of the selected entries into the transfer buffer; one wave per block
