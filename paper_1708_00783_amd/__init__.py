@@ -274,6 +274,9 @@ class Volume:
             n_store = int(lib().tf_host_store_bytes(ctypes.byref(self.params)))
             n_xfer = int(lib().tf_host_transfer_bytes(ctypes.byref(self.params)))
             self.h_store = np.empty(n_store, np.uint8)
+            # touch every page now: a swap-out writes blocks at entry-indexed,
+            # scattered places, and first-touch page faults would land there
+            self.h_store[::4096] = 0
             self.h_transfer = torch.empty(n_xfer, dtype=torch.uint8, pin_memory=True)
             hs = ctypes.c_void_p(self.h_store.ctypes.data)
             ht = ctypes.c_void_p(self.h_transfer.data_ptr())
