@@ -112,9 +112,10 @@ __global__ __launch_bounds__(256) void k_pack(const float *w, int cin, int cinp,
 }
 
 // ============================================================================
-// forward 3x3 convolution: each wave computes 32 output pixels x COUT
+// forward 3x3 convolution: each wave computes 16 T output pixels x COUT (T
+// row tiles share every weight fragment it loads)
 // ============================================================================
-template <int CINP, int COUT, int STRIDE, bool UP, bool SKIP>
+template <int CINP, int COUT, int STRIDE, bool UP, bool SKIP, int T>
 __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, int Ws, const uint16_t *g,
                                                   const float *bias, const uint16_t *skip, uint16_t *out, int N,
                                                   int Ho, int Wo)
@@ -123,14 +124,14 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, in
     constexpr int NT = COUT / 16;
     const int lane = (int)threadIdx.x & 63;
     const long P = (long)N * Ho * Wo;
-    const long p0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
+    const long p0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * (16 * T);
     if (p0 >= P) return;
     const int r = lane & 15, gq = lane >> 4;
     const int Hc = UP ? 2 * Hs : Hs, Wc = UP ? 2 * Ws : Ws;   // conv input size
-    int pn[2], py[2], px[2];
-    bool pv[2];
+    int pn[T], py[T], px[T];
+    bool pv[T];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < T; ++t) {
         long p = p0 + t * 16 + r;
         pv[t] = p < P;
         if (!pv[t]) p = 0;
@@ -139,18 +140,18 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, in
         py[t] = rem / Wo;
         px[t] = rem - py[t] * Wo;
     }
-    f32x4 acc[2][NT];
+    f32x4 acc[T][NT];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < T; ++t)
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < KP; k0 += 32) {
         const int k = k0 + gq * 8;
         const int tap = k / CINP, ci = k - (k / CINP) * CINP;
         const int ky = tap / 3, kx = tap - (tap / 3) * 3;
-        bf16x8 a[2];
+        bf16x8 a[T];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < T; ++t) {
             const int iy = STRIDE * py[t] + ky - 1, ix = STRIDE * px[t] + kx - 1;
             u32x4 v = {0u, 0u, 0u, 0u};
             if (tap < 9 && pv[t] && iy >= 0 && iy < Hc && ix >= 0 && ix < Wc) {
@@ -162,12 +163,12 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, in
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
             const bf16x8 b = as_bf(ld16(g + (size_t)(j * 16 + r) * KP + k));
-            acc[0][j] = mfma(a[0], b, acc[0][j]);
-            acc[1][j] = mfma(a[1], b, acc[1][j]);
+#pragma unroll
+            for (int t = 0; t < T; ++t) acc[t][j] = mfma(a[t], b, acc[t][j]);
         }
     }
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < T; ++t)
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
             const int co = j * 16 + r;
@@ -580,15 +581,17 @@ hipError_t launch_pack(const Net &net, const float *params, uint16_t *g, uint16_
 hipError_t launch_conv_fwd(int layer, const uint16_t *in, int Hs, int Ws, const uint16_t *g, const float *bias,
                            const uint16_t *skip, uint16_t *out, int N, int Ho, int Wo, hipStream_t s)
 {
-    const dim3 gr = grid1((long)N * Ho * Wo, 128), b(256);
+    // 64 output pixels per wave for 32 output channels, else 32
+    const long P = (long)N * Ho * Wo;
+    const dim3 g4 = grid1(P, 256), g2 = grid1(P, 128), b(256);
     switch (layer) {
-    case 0: hipLaunchKernelGGL((k_conv_fwd<8, 32, 1, false, false>), gr, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 1: hipLaunchKernelGGL((k_conv_fwd<32, 64, 2, false, false>), gr, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 2: hipLaunchKernelGGL((k_conv_fwd<64, 64, 2, false, false>), gr, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 3: hipLaunchKernelGGL((k_conv_fwd<64, 128, 2, false, false>), gr, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 4: hipLaunchKernelGGL((k_conv_fwd<128, 64, 1, true, true>), gr, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 5: hipLaunchKernelGGL((k_conv_fwd<64, 64, 1, true, true>), gr, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 6: hipLaunchKernelGGL((k_conv_fwd<64, 32, 1, true, true>), gr, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 0: hipLaunchKernelGGL((k_conv_fwd<8, 32, 1, false, false, 4>), g4, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 1: hipLaunchKernelGGL((k_conv_fwd<32, 64, 2, false, false, 2>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 2: hipLaunchKernelGGL((k_conv_fwd<64, 64, 2, false, false, 2>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 3: hipLaunchKernelGGL((k_conv_fwd<64, 128, 2, false, false, 2>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 4: hipLaunchKernelGGL((k_conv_fwd<128, 64, 1, true, true, 2>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 5: hipLaunchKernelGGL((k_conv_fwd<64, 64, 1, true, true, 2>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 6: hipLaunchKernelGGL((k_conv_fwd<64, 32, 1, true, true, 4>), g4, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
