@@ -433,12 +433,17 @@ def run_c5(args):
     tden = np.array([np.mean([r[n][1] for r in res["denoised"]]) for n in ns])
     hraw = np.array([np.mean([r[n][2] for r in res["raw"]]) for n in ns])
     hden = np.array([np.mean([r[n][2] for r in res["denoised"]]) for n in ns])
+    # the same with the median over rooms (one room with a large error on both
+    # paths should not decide the comparison)
+    raw_md = np.array([np.median([r[n][0] for r in res["raw"]]) for n in ns])
+    den_md = np.array([np.median([r[n][0] for r in res["denoised"]]) for n in ns])
     e_star = float(raw[-1])
     # equal error at equal coverage: the RMS is over evaluation hits only, so a
     # model fused from few frames must also cover the room (>= 95% of the raw
     # path's hits with every frame) before its error counts
     h_star = float(hraw[-1])
     reach = [j for j, v in enumerate(den) if v <= e_star and hden[j] >= C5_COVERAGE * h_star]
+    reach_md = [j for j, v in enumerate(den_md) if v <= raw_md[-1] and hden[j] >= C5_COVERAGE * h_star]
     nd = ns[reach[0]] if reach else None
     t_plain = float(traw[-1])
     t_den = float(tden[reach[0]]) if reach else None
@@ -460,6 +465,13 @@ def run_c5(args):
         "frames_per_s_denoised": round(float(ns[-1] / tden[-1]), 2),
         "rms_mm": {"frames_fused": cps, "raw": [round(v * 1e3, 4) for v in raw],
                    "denoised": [round(v * 1e3, 4) for v in den]},
+        "median_over_rooms": {"e_star_mm": round(float(raw_md[-1]) * 1e3, 4),
+                              "n_d": ns[reach_md[0]] if reach_md else None,
+                              "ratio": round(t_plain / float(tden[reach_md[0]]), 4) if reach_md else None,
+                              "raw_mm": [round(v * 1e3, 4) for v in raw_md],
+                              "denoised_mm": [round(v * 1e3, 4) for v in den_md]},
+        "per_room_mm_at_300": {"raw": [round(r[ns[-1]][0] * 1e3, 4) for r in res["raw"]],
+                               "denoised": [round(r[ns[-1]][0] * 1e3, 4) for r in res["denoised"]]},
         "eval_hits": {"raw": [int(v) for v in hraw], "denoised": [int(v) for v in hden],
                       "coverage_required": C5_COVERAGE},
         "protocol": "each N fuses every (300/N)-th frame of the whole trajectory into a fresh volume (equal "
