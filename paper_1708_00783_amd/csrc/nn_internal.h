@@ -22,7 +22,7 @@ namespace nn {
 constexpr int kLayers = 8;              // e1 e2 e3 e4 d3 d2 d1 head
 constexpr float kDepthScale = 4.0f;     // metres: input normalisation (d / 4 m)
 constexpr float kCorrScale = 0.05f;     // metres: unit of the head's depth correction
-constexpr int kHeadChunks = 512;        // pixel chunks of the head's weight-gradient reduction
+constexpr int kHeadChunks = 1024;       // pixel chunks of the head's weight-gradient reduction
 
 struct LayerDesc {
     int cin, cinp, cout, stride, up;    // up: the conv reads up2(source)

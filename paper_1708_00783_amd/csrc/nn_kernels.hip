@@ -484,55 +484,90 @@ __global__ __launch_bounds__(256) void k_head_bwd(const float *ddelta, const flo
     }
 }
 
-// head weight gradient of one pixel chunk: thread (slot, c) = (t / 32, t % 32)
-// sums the 9 taps of channel c over every 8th pixel of the chunk; the 8 slots
-// are reduced in LDS; partial[chunk][tap * 32 + c], partial[chunk][288] = bias
+// head weight gradient of one pixel chunk, gathered from the input side:
+// dw[tap][c] = sum_p ddelta[p] d1[p + off(tap)][c] = sum_q d1[q][c] ddelta[q - off(tap)],
+// so every d1 pixel is read once.  Thread t takes pixel t / 4 of each
+// 64-pixel pass and channels 8 (t % 4) .. +7; the 16 lanes of a wave with the
+// same channel octet are summed by a fixed butterfly, the 4 waves in LDS.
+// partial[j * nchunk + chunk]: j = tap * 32 + c, j = 288 the bias (the sum of
+// ddelta, from the octet-0 lanes)
 __global__ __launch_bounds__(256) void k_head_wgrad(const float *ddelta, const uint16_t *d1, int N, int H, int W,
                                                     float *partial, int chunk_pix)
 {
-    __shared__ float red[8][289];
+    __shared__ float red[4][4][73];
     const long P = (long)N * H * W;
     const long c0 = (long)blockIdx.x * chunk_pix;
     const long c1 = c0 + chunk_pix < P ? c0 + chunk_pix : P;
-    const int c = (int)threadIdx.x & 31, slot = (int)threadIdx.x >> 5;
-    float acc[9], bsum = 0.0f;
+    const int oct = (int)threadIdx.x & 3, lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+    float acc[9][8], bsum = 0.0f;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) acc[k] = 0.0f;
-    for (long p = c0 + slot; p < c1; p += 8) {
-        const float dd = ddelta[p];
-        if (dd == 0.0f) continue;
-        bsum += dd;
-        const int n = (int)(p / ((long)H * W));
-        const int rem = (int)(p - (long)n * H * W);
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[k][e] = 0.0f;
+    for (long q = c0 + ((int)threadIdx.x >> 2); q < c1; q += 64) {
+        const int n = (int)(q / ((long)H * W));
+        const int rem = (int)(q - (long)n * H * W);
         const int y = rem / W, x = rem - (rem / W) * W;
+        const u32x4 v = ld16(d1 + (size_t)q * 32 + 8 * oct);
+        float a[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a[e] = bf2f((uint16_t)(v[e >> 1] >> (16 * (e & 1))));
+        const float *drow = ddelta + (size_t)n * H * W;
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
-            const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-            if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-            acc[tap] += dd * bf2f(d1[(((size_t)n * H + yy) * W + xx) * 32 + c]);
+            const int py = y - tap / 3 + 1, px = x - tap % 3 + 1;
+            if (py < 0 || py >= H || px < 0 || px >= W) continue;
+            const float dd = drow[(size_t)py * W + px];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc[tap][e] += dd * a[e];
+            if (tap == 4 && oct == 0) bsum += dd;
         }
     }
 #pragma unroll
-    for (int k = 0; k < 9; ++k) red[slot][k * 32 + c] = acc[k];
-    if (c == 0) red[slot][288] = bsum;
+    for (int m = 4; m < 64; m <<= 1) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc[k][e] += __shfl_xor(acc[k][e], m);
+        bsum += __shfl_xor(bsum, m);
+    }
+    if (lane < 4) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) red[wv][oct][k * 8 + e] = acc[k][e];
+        red[wv][oct][72] = bsum;
+    }
     __syncthreads();
+    const int nchunk = (int)gridDim.x;
     for (int j = (int)threadIdx.x; j < 289; j += 256) {
-        float s = 0.0f;
-        for (int q = 0; q < 8; ++q) s += red[q][j];
-        partial[(size_t)blockIdx.x * 289 + j] = s;
+        // j = tap * 32 + c (c = 8 oct + e); the bias sits at octet 0, slot 72
+        const int tap = j >> 5, c = j & 31;
+        const int o = j < 288 ? c >> 3 : 0, k = j < 288 ? tap * 8 + (c & 7) : 72;
+        const float s = (red[0][o][k] + red[1][o][k]) + (red[2][o][k] + red[3][o][k]);
+        partial[(size_t)j * nchunk + blockIdx.x] = s;
     }
 }
 
-__global__ __launch_bounds__(320) void k_head_reduce(const float *partial, int chunks, float *dw, float *db)
+// fixed-order sum of the head partials: workgroup j sums row j of partial
+__global__ __launch_bounds__(256) void k_head_reduce(const float *partial, int chunks, float *dw, float *db)
 {
-    const int j = (int)threadIdx.x;
-    if (j > 288) return;
+    __shared__ float red[256];
+    const int j = (int)blockIdx.x;
     float s = 0.0f;
-    for (int c = 0; c < chunks; ++c) s += partial[(size_t)c * 289 + j];
-    if (j < 288)
-        dw[j] = s;
-    else
-        db[0] = s;
+    for (int c = (int)threadIdx.x; c < chunks; c += 256) s += partial[(size_t)j * chunks + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int m = 128; m > 0; m >>= 1) {
+        if ((int)threadIdx.x < m) red[threadIdx.x] += red[threadIdx.x + m];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (j < 288)
+            dw[j] = red[0];
+        else
+            db[0] = red[0];
+    }
 }
 
 // Adam (Kingma & Ba, Algorithm 1); c1 = 1 - beta1^t, c2 = 1 - beta2^t
@@ -630,7 +665,7 @@ hipError_t launch_head_wgrad(const float *ddelta, const uint16_t *d1, int N, int
     const int per = (int)((P + chunks - 1) / chunks);
     const int nc = (int)((P + per - 1) / per);
     hipLaunchKernelGGL(k_head_wgrad, dim3(nc), dim3(256), 0, s, ddelta, d1, N, H, W, partial, per);
-    hipLaunchKernelGGL(k_head_reduce, dim3(1), dim3(320), 0, s, partial, nc, dw, db);
+    hipLaunchKernelGGL(k_head_reduce, dim3(289), dim3(256), 0, s, partial, nc, dw, db);
     return hipGetLastError();
 }
 
