@@ -60,8 +60,6 @@ Net make_net()
 
 namespace {
 
-constexpr int kChunks = 64;   // pixel chunks of the weight-gradient reductions
-
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct NLayout {
@@ -96,10 +94,11 @@ bool nlayout(const Net &net, uint32_t B, uint32_t H, uint32_t W, int training, N
         L.v = take(4 * (size_t)net.n_params);
         size_t mx = 0;
         for (int l = 0; l < kLayers - 1; ++l) {
-            const size_t e = (size_t)net.L[l].cout * 9 * net.L[l].cinp + net.L[l].cout;
+            const size_t P = (size_t)B * (H / net.L[l].scale) * (W / net.L[l].scale);
+            const size_t e = (size_t)wgrad_chunks((long)P) * ((size_t)net.L[l].cout * 9 * net.L[l].cinp + net.L[l].cout);
             if (e > mx) mx = e;
         }
-        L.partial = take(4 * (size_t)kChunks * mx);
+        L.partial = take(4 * mx);
         L.hpartial = take(4 * (size_t)kHeadChunks * 289);
         L.scratch = take(16);
         L.loss = take(16);
@@ -273,7 +272,7 @@ int tf_nn_backward(tf_nn *nn, const float *d_target, float *d_loss, tf_stream st
         const int ss = act_scale(L.src);
         const int Hs = H / ss, Ws = W / ss, Ho = H / L.scale, Wo = W / L.scale;
         uint16_t *gpre = nn->grad[l + 1];
-        e = launch_conv_wgrad(l, gpre, nn->act[L.src], Hs, Ws, N, Ho, Wo, nn->partial, kChunks,
+        e = launch_conv_wgrad(l, gpre, nn->act[L.src], Hs, Ws, N, Ho, Wo, nn->partial, wgrad_chunks((long)N * Ho * Wo),
                               nn->grads + L.w_off, nn->grads + L.b_off, s);
         if (e == hipSuccess && l > 0)
             e = launch_conv_bwd_data(l, gpre, Ho, Wo, nn->t + L.t_off,

@@ -267,21 +267,28 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t *gpre, int
 }
 
 // ============================================================================
-// weight gradient of one tap (blockIdx.x) over one pixel chunk (blockIdx.y):
+// weight gradient of one tap over one pixel chunk:
 // partial[chunk][co][tap][ci] = sum_p gpre[p][co] * in_tap(p)[ci]; the bias
 // gradient partial[chunk][co] comes from the tap-0 workgroups
 // ============================================================================
 template <int CINP, int COUT, int STRIDE, bool UP>
 __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *gpre, const uint16_t *in, int Hs, int Ws, int N,
-                                                    int Ho, int Wo, float *partial, float *partial_b, int chunk_pix)
+                                                    int Ho, int Wo, float *partial, float *partial_b, int chunk_pix,
+                                                    int nchunk)
 {
     constexpr int CT = CINP < 16 ? 16 : CINP;
     constexpr int MT = COUT / 16, NTT = CT / 16, TILES = MT * NTT, TPW = (TILES + 3) / 4;
-    constexpr int LD = 40;   // LDS row pitch in bf16 elements (80 bytes: 16-byte aligned rows)
+    constexpr int KS = kWgradStep;   // pixels staged per round (4 MFMA k-steps)
+    constexpr int LD = KS + 8;       // LDS row pitch in bf16 elements (16-byte aligned rows)
+    constexpr int GV = KS * (COUT / 8), IV = KS * (CT / 8);   // 16-byte vectors staged per round
     __shared__ uint16_t gT[COUT][LD];
     __shared__ uint16_t iT[CT][LD];
-    __shared__ float bsum[COUT];
-    const int tap = (int)blockIdx.x, chunk = (int)blockIdx.y;
+    // workgroups are dealt to the 8 XCDs round-robin by their linear index:
+    // the 9 taps of a chunk get indices of one residue mod 8, so they run on
+    // one XCD and read the chunk's gradient and input through the same L2
+    const int id = (int)blockIdx.x, slot = id >> 3;
+    const int chunk = (id & 7) + 8 * (slot / 9), tap = slot - (slot / 9) * 9;
+    if (chunk >= nchunk) return;
     const int ky = tap / 3, kx = tap - (tap / 3) * 3;
     const long P = (long)N * Ho * Wo;
     const long c0 = (long)chunk * chunk_pix;
@@ -292,45 +299,64 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *gpre, const 
 #pragma unroll
     for (int j = 0; j < TPW; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
     float bpart = 0.0f;   // bias gradient: thread threadIdx.x < COUT owns channel threadIdx.x
-    for (long pb = c0; pb < c1; pb += 32) {
-        for (int v = threadIdx.x; v < 32 * (COUT / 8); v += 256) {
+    for (long pb = c0; pb < c1; pb += KS) {
+        u32x4 gv[(GV + 255) / 256], iv[(IV + 255) / 256];
+#pragma unroll
+        for (int q = 0; q < (GV + 255) / 256; ++q) {
+            const int v = (int)threadIdx.x + 256 * q;
             const int pi = v / (COUT / 8), cv = (v - pi * (COUT / 8)) * 8;
             const long p = pb + pi;
-            u32x4 val = {0u, 0u, 0u, 0u};
-            if (p < c1) val = ld16(gpre + (size_t)p * COUT + cv);
-#pragma unroll
-            for (int e = 0; e < 8; ++e) gT[cv + e][pi] = (uint16_t)(val[e >> 1] >> (16 * (e & 1)));
+            gv[q] = u32x4{0u, 0u, 0u, 0u};
+            if (v < GV && p < c1) gv[q] = ld16(gpre + (size_t)p * COUT + cv);
         }
-        for (int v = threadIdx.x; v < 32 * (CT / 8); v += 256) {
+#pragma unroll
+        for (int q = 0; q < (IV + 255) / 256; ++q) {
+            const int v = (int)threadIdx.x + 256 * q;
             const int pi = v / (CT / 8), cv = (v - pi * (CT / 8)) * 8;
             const long p = pb + pi;
-            u32x4 val = {0u, 0u, 0u, 0u};
-            if (p < c1 && cv < CINP) {
+            iv[q] = u32x4{0u, 0u, 0u, 0u};
+            if (v < IV && p < c1 && cv < CINP) {
                 const int n = (int)(p / ((long)Ho * Wo));
                 const int rem = (int)(p - (long)n * Ho * Wo);
                 const int oy = rem / Wo, ox = rem - (rem / Wo) * Wo;
                 const int iy = STRIDE * oy + ky - 1, ix = STRIDE * ox + kx - 1;
                 if (iy >= 0 && iy < Hc && ix >= 0 && ix < Wc) {
                     const int sy = UP ? (iy >> 1) : iy, sx = UP ? (ix >> 1) : ix;
-                    val = ld16(in + (((size_t)n * Hs + sy) * Ws + sx) * CINP + cv);
+                    iv[q] = ld16(in + (((size_t)n * Hs + sy) * Ws + sx) * CINP + cv);
                 }
             }
+        }
 #pragma unroll
-            for (int e = 0; e < 8; ++e) iT[cv + e][pi] = (uint16_t)(val[e >> 1] >> (16 * (e & 1)));
+        for (int q = 0; q < (GV + 255) / 256; ++q) {
+            const int v = (int)threadIdx.x + 256 * q;
+            const int pi = v / (COUT / 8), cv = (v - pi * (COUT / 8)) * 8;
+            if (v < GV)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) gT[cv + e][pi] = (uint16_t)(gv[q][e >> 1] >> (16 * (e & 1)));
+        }
+#pragma unroll
+        for (int q = 0; q < (IV + 255) / 256; ++q) {
+            const int v = (int)threadIdx.x + 256 * q;
+            const int pi = v / (CT / 8), cv = (v - pi * (CT / 8)) * 8;
+            if (v < IV)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) iT[cv + e][pi] = (uint16_t)(iv[q][e >> 1] >> (16 * (e & 1)));
         }
         __syncthreads();
         if (tap == 0 && (int)threadIdx.x < COUT)
-            for (int k = 0; k < 32; ++k) bpart += bf2f(gT[threadIdx.x][k]);
+            for (int k = 0; k < KS; ++k) bpart += bf2f(gT[threadIdx.x][k]);
 #pragma unroll
-        for (int j = 0; j < TPW; ++j) {
-            const int tile = w * TPW + j;
-            if (tile < TILES) {
-                const int mt = tile / NTT, nt = tile - (tile / NTT) * NTT;
-                const bf16x8 a = as_bf(*reinterpret_cast<const u32x4 *>(&gT[mt * 16 + r][gq * 8]));
-                const bf16x8 b = as_bf(*reinterpret_cast<const u32x4 *>(&iT[nt * 16 + r][gq * 8]));
-                acc[j] = mfma(a, b, acc[j]);
+        for (int kk = 0; kk < KS; kk += 32)
+#pragma unroll
+            for (int j = 0; j < TPW; ++j) {
+                const int tile = w * TPW + j;
+                if (tile < TILES) {
+                    const int mt = tile / NTT, nt = tile - (tile / NTT) * NTT;
+                    const bf16x8 a = as_bf(*reinterpret_cast<const u32x4 *>(&gT[mt * 16 + r][kk + gq * 8]));
+                    const bf16x8 b = as_bf(*reinterpret_cast<const u32x4 *>(&iT[nt * 16 + r][kk + gq * 8]));
+                    acc[j] = mfma(a, b, acc[j]);
+                }
             }
-        }
         __syncthreads();
     }
 #pragma unroll
@@ -346,28 +372,44 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *gpre, const 
             partial[(((size_t)chunk * COUT + co) * 9 + tap) * CINP + ci] = acc[j][i];
         }
     }
-    if (tap == 0 && (int)threadIdx.x < COUT) {
-        bsum[threadIdx.x] = bpart;
-        partial_b[(size_t)chunk * COUT + threadIdx.x] = bpart;
-    }
+    if (tap == 0 && (int)threadIdx.x < COUT) partial_b[(size_t)chunk * COUT + threadIdx.x] = bpart;
 }
 
-// fixed-order sum of the chunk partials into the fp32 gradient vector
+// fixed-order sum of the chunk partials into the fp32 gradient vector: a
+// workgroup takes 64 consecutive partial entries j (weights with the padded
+// input channels, then the biases); wave sl sums chunks sl, sl + 4, ... with
+// eight loads in flight per lane, and the four wave sums are added in LDS
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float *partial, const float *partial_b, int chunks,
                                                       int cout, int cin, int cinp, float *dw, float *db)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    const int nw = cout * 9 * cin;
-    if (i < nw) {
-        const int co = i / (9 * cin), rem = i - co * 9 * cin, tap = rem / cin, ci = rem - (rem / cin) * cin;
-        float s = 0.0f;
-        for (int c = 0; c < chunks; ++c) s += partial[(((size_t)c * cout + co) * 9 + tap) * cinp + ci];
-        dw[i] = s;
-    } else if (i < nw + cout) {
-        const int co = i - nw;
-        float s = 0.0f;
-        for (int c = 0; c < chunks; ++c) s += partial_b[(size_t)c * cout + co];
-        db[co] = s;
+    __shared__ float red[4][64];
+    const int nw = cout * 9 * cinp;
+    const int j = (int)blockIdx.x * 64 + ((int)threadIdx.x & 63), sl = (int)threadIdx.x >> 6;
+    const bool isw = j < nw, valid = j < nw + cout;
+    float s = 0.0f;
+    if (valid) {
+        const float *src = isw ? partial + j : partial_b + (j - nw);
+        const size_t stride = isw ? (size_t)nw : (size_t)cout;
+        float a[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a[k] = 0.0f;
+        int c = sl;
+        for (; c + 28 < chunks; c += 32)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a[k] += src[(size_t)(c + 4 * k) * stride];
+        for (; c < chunks; c += 4) a[0] += src[(size_t)c * stride];
+        s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    }
+    red[sl][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (sl != 0 || !valid) return;
+    const int l = (int)threadIdx.x;
+    const float t = (red[0][l] + red[1][l]) + (red[2][l] + red[3][l]);
+    if (isw) {
+        const int co = j / (9 * cinp), rem = j - co * 9 * cinp, tap = rem / cinp, ci = rem - (rem / cinp) * cinp;
+        if (ci < cin) dw[(co * 9 + tap) * cin + ci] = t;
+    } else {
+        db[j - nw] = t;
     }
 }
 
@@ -691,31 +733,31 @@ hipError_t launch_conv_wgrad(int layer, const uint16_t *gpre, const uint16_t *in
 {
     const long P = (long)N * Ho * Wo;
     int per = (int)((P + chunks - 1) / chunks);
-    per = ((per + 31) / 32) * 32;
+    per = ((per + kWgradStep - 1) / kWgradStep) * kWgradStep;
     const int nc = (int)((P + per - 1) / per);
     float *pb = partial;   // bias partials after the weight partials
-    const dim3 gr(9, nc), b(256);
+    const dim3 gr(9 * ((nc + 7) / 8) * 8), b(256);   // (tap, chunk) pairs, chunks padded to a multiple of 8
     int cout = 0, cin = 0, cinp = 0;
     switch (layer) {
     case 0: cout = 32; cin = 3; cinp = 8; pb += (size_t)nc * 32 * 9 * 8;
-        hipLaunchKernelGGL((k_conv_wgrad<8, 32, 1, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per); break;
+        hipLaunchKernelGGL((k_conv_wgrad<8, 32, 1, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
     case 1: cout = 64; cin = cinp = 32; pb += (size_t)nc * 64 * 9 * 32;
-        hipLaunchKernelGGL((k_conv_wgrad<32, 64, 2, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per); break;
+        hipLaunchKernelGGL((k_conv_wgrad<32, 64, 2, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
     case 2: cout = 64; cin = cinp = 64; pb += (size_t)nc * 64 * 9 * 64;
-        hipLaunchKernelGGL((k_conv_wgrad<64, 64, 2, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per); break;
+        hipLaunchKernelGGL((k_conv_wgrad<64, 64, 2, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
     case 3: cout = 128; cin = cinp = 64; pb += (size_t)nc * 128 * 9 * 64;
-        hipLaunchKernelGGL((k_conv_wgrad<64, 128, 2, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per); break;
+        hipLaunchKernelGGL((k_conv_wgrad<64, 128, 2, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
     case 4: cout = 64; cin = cinp = 128; pb += (size_t)nc * 64 * 9 * 128;
-        hipLaunchKernelGGL((k_conv_wgrad<128, 64, 1, true>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per); break;
+        hipLaunchKernelGGL((k_conv_wgrad<128, 64, 1, true>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
     case 5: cout = 64; cin = cinp = 64; pb += (size_t)nc * 64 * 9 * 64;
-        hipLaunchKernelGGL((k_conv_wgrad<64, 64, 1, true>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per); break;
+        hipLaunchKernelGGL((k_conv_wgrad<64, 64, 1, true>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
     case 6: cout = 32; cin = cinp = 64; pb += (size_t)nc * 32 * 9 * 64;
-        hipLaunchKernelGGL((k_conv_wgrad<64, 32, 1, true>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per); break;
+        hipLaunchKernelGGL((k_conv_wgrad<64, 32, 1, true>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
     default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_wgrad_reduce, grid1((long)cout * 9 * cin + cout, 256), dim3(256), 0, s, partial, pb, nc,
+    hipLaunchKernelGGL(k_wgrad_reduce, grid1((long)cout * 9 * cinp + cout, 64), dim3(256), 0, s, partial, pb, nc,
                        cout, cin, cinp, dw, db);
     return hipGetLastError();
 }
