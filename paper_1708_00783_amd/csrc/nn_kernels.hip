@@ -112,19 +112,23 @@ __global__ __launch_bounds__(256) void k_pack(const float *w, int cin, int cinp,
 }
 
 // ============================================================================
-// forward 3x3 convolution: each wave computes 16 T output pixels x COUT (T
-// row tiles share every weight fragment it loads)
+// forward 3x3 convolution: each wave computes 16 T output pixels x COUT / NS
+// output channels (T row tiles share every weight fragment it loads; the NS
+// waves of a pixel group sit in one workgroup and share its input loads in L1)
 // ============================================================================
-template <int CINP, int COUT, int STRIDE, bool UP, bool SKIP, int T>
+template <int CINP, int COUT, int STRIDE, bool UP, bool SKIP, int T, int NS>
 __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, int Ws, const uint16_t *g,
                                                   const float *bias, const uint16_t *skip, uint16_t *out, int N,
                                                   int Ho, int Wo)
 {
+    static_assert(NS == 1 || NS == 2 || NS == 4, "channel split must divide the 4 waves of a workgroup");
     constexpr int KP = ((9 * CINP + 31) / 32) * 32;
-    constexpr int NT = COUT / 16;
+    constexpr int NT = COUT / 16 / NS;
     const int lane = (int)threadIdx.x & 63;
     const long P = (long)N * Ho * Wo;
-    const long p0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * (16 * T);
+    const int wid = (int)blockIdx.x * 4 + ((int)threadIdx.x >> 6);
+    const int cbase = (wid % NS) * (COUT / NS);
+    const long p0 = (long)(wid / NS) * (16 * T);
     if (p0 >= P) return;
     const int r = lane & 15, gq = lane >> 4;
     const int Hc = UP ? 2 * Hs : Hs, Wc = UP ? 2 * Ws : Ws;   // conv input size
@@ -162,7 +166,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, in
         }
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            const bf16x8 b = as_bf(ld16(g + (size_t)(j * 16 + r) * KP + k));
+            const bf16x8 b = as_bf(ld16(g + (size_t)(cbase + j * 16 + r) * KP + k));
 #pragma unroll
             for (int t = 0; t < T; ++t) acc[t][j] = mfma(a[t], b, acc[t][j]);
         }
@@ -171,7 +175,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, in
     for (int t = 0; t < T; ++t)
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            const int co = j * 16 + r;
+            const int co = cbase + j * 16 + r;
             const float bb = bias[co];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -189,17 +193,23 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, in
 // backward data: gradient at the conv input (or, for an upsampled input, at
 // its source), then + skip gradient, then the source's relu mask
 // ============================================================================
-template <int CIN, int COUT, int STRIDE, bool UPSUM, bool SKIP>
+// A wave takes 32 pixels and CIN / NS of the input channels: NS waves of one
+// workgroup share a pixel group (its gradient operand loads hit L1), so layers
+// with few pixels still fill the chip.
+template <int CIN, int COUT, int STRIDE, bool UPSUM, bool SKIP, int NS>
 __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t *gpre, int Ho, int Wo, const uint16_t *tw,
                                                        const uint16_t *skipg, const uint16_t *act, uint16_t *gout,
                                                        int N, int Hq, int Wq)
 {
+    static_assert(NS == 1 || NS == 2 || NS == 4, "channel split must divide the 4 waves of a workgroup");
     constexpr int K9 = 9 * COUT;
     constexpr int KT = (UPSUM ? 4 : 1) * K9;
-    constexpr int NT = CIN / 16;
+    constexpr int NT = CIN / 16 / NS;
     const int lane = (int)threadIdx.x & 63;
     const long P = (long)N * Hq * Wq;
-    const long p0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
+    const int wid = (int)blockIdx.x * 4 + ((int)threadIdx.x >> 6);
+    const int cbase = (wid % NS) * (CIN / NS);
+    const long p0 = (long)(wid / NS) * 32;
     if (p0 >= P) return;
     const int r = lane & 15, gq = lane >> 4;
     int pn[2], py[2], px[2];
@@ -244,7 +254,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t *gpre, int
         }
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            const bf16x8 b = as_bf(ld16(tw + (size_t)(j * 16 + r) * K9 + rem));
+            const bf16x8 b = as_bf(ld16(tw + (size_t)(cbase + j * 16 + r) * K9 + rem));
             acc[0][j] = mfma(a[0], b, acc[0][j]);
             acc[1][j] = mfma(a[1], b, acc[1][j]);
         }
@@ -253,7 +263,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t *gpre, int
     for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            const int c = j * 16 + r;
+            const int c = cbase + j * 16 + r;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const long p = p0 + t * 16 + gq * 4 + i;
@@ -658,17 +668,18 @@ hipError_t launch_pack(const Net &net, const float *params, uint16_t *g, uint16_
 hipError_t launch_conv_fwd(int layer, const uint16_t *in, int Hs, int Ws, const uint16_t *g, const float *bias,
                            const uint16_t *skip, uint16_t *out, int N, int Ho, int Wo, hipStream_t s)
 {
-    // 64 output pixels per wave for 32 output channels, else 32
+    // 64 output pixels per wave for 32 output channels, else 32; the deepest
+    // layers (fewest pixels) split their output channels over 4 or 2 waves
     const long P = (long)N * Ho * Wo;
-    const dim3 g4 = grid1(P, 256), g2 = grid1(P, 128), b(256);
+    const dim3 g4 = grid1(P, 256), g2 = grid1(P, 128), g2s2 = grid1(P, 64), g2s4 = grid1(P, 32), b(256);
     switch (layer) {
-    case 0: hipLaunchKernelGGL((k_conv_fwd<8, 32, 1, false, false, 4>), g4, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 1: hipLaunchKernelGGL((k_conv_fwd<32, 64, 2, false, false, 2>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 2: hipLaunchKernelGGL((k_conv_fwd<64, 64, 2, false, false, 2>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 3: hipLaunchKernelGGL((k_conv_fwd<64, 128, 2, false, false, 2>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 4: hipLaunchKernelGGL((k_conv_fwd<128, 64, 1, true, true, 2>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 5: hipLaunchKernelGGL((k_conv_fwd<64, 64, 1, true, true, 2>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 6: hipLaunchKernelGGL((k_conv_fwd<64, 32, 1, true, true, 4>), g4, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 0: hipLaunchKernelGGL((k_conv_fwd<8, 32, 1, false, false, 4, 1>), g4, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 1: hipLaunchKernelGGL((k_conv_fwd<32, 64, 2, false, false, 2, 1>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 2: hipLaunchKernelGGL((k_conv_fwd<64, 64, 2, false, false, 2, 1>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 3: hipLaunchKernelGGL((k_conv_fwd<64, 128, 2, false, false, 2, 4>), g2s4, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 4: hipLaunchKernelGGL((k_conv_fwd<128, 64, 1, true, true, 2, 2>), g2s2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 5: hipLaunchKernelGGL((k_conv_fwd<64, 64, 1, true, true, 2, 1>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 6: hipLaunchKernelGGL((k_conv_fwd<64, 32, 1, true, true, 4, 1>), g4, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -715,14 +726,15 @@ hipError_t launch_conv_bwd_data(int layer, const uint16_t *gpre, int Ho, int Wo,
                                 const uint16_t *skipg, const uint16_t *act, uint16_t *gout, int N, int Hq, int Wq,
                                 hipStream_t s)
 {
-    const dim3 gr = grid1((long)N * Hq * Wq, 128), b(256);
+    const long P = (long)N * Hq * Wq;
+    const dim3 g1 = grid1(P, 128), g2 = grid1(P, 64), g4 = grid1(P, 32), b(256);
     switch (layer) {
-    case 1: hipLaunchKernelGGL((k_conv_bwd_data<32, 64, 2, false, true>), gr, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
-    case 2: hipLaunchKernelGGL((k_conv_bwd_data<64, 64, 2, false, true>), gr, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
-    case 3: hipLaunchKernelGGL((k_conv_bwd_data<64, 128, 2, false, true>), gr, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
-    case 4: hipLaunchKernelGGL((k_conv_bwd_data<128, 64, 1, true, false>), gr, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
-    case 5: hipLaunchKernelGGL((k_conv_bwd_data<64, 64, 1, true, false>), gr, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
-    case 6: hipLaunchKernelGGL((k_conv_bwd_data<64, 32, 1, true, false>), gr, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
+    case 1: hipLaunchKernelGGL((k_conv_bwd_data<32, 64, 2, false, true, 1>), g1, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
+    case 2: hipLaunchKernelGGL((k_conv_bwd_data<64, 64, 2, false, true, 1>), g1, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
+    case 3: hipLaunchKernelGGL((k_conv_bwd_data<64, 128, 2, false, true, 2>), g2, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
+    case 4: hipLaunchKernelGGL((k_conv_bwd_data<128, 64, 1, true, false, 4>), g4, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
+    case 5: hipLaunchKernelGGL((k_conv_bwd_data<64, 64, 1, true, false, 1>), g1, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
+    case 6: hipLaunchKernelGGL((k_conv_bwd_data<64, 32, 1, true, false, 1>), g1, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
