@@ -291,6 +291,12 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *gpre, const 
     constexpr int KS = kWgradStep;   // pixels staged per round (4 MFMA k-steps)
     constexpr int LD = KS + 8;       // LDS row pitch in bf16 elements (16-byte aligned rows)
     constexpr int GV = KS * (COUT / 8), IV = KS * (CT / 8);   // 16-byte vectors staged per round
+    static_assert(KS == 64, "the column swizzle below spans 64 pixels");
+    // the pixel column of LDS row `row` is XORed with 8 ((row / 8) % 8): the
+    // transposed 16-bit writes of one instruction (8 rows apart per lane
+    // group) then spread over the banks, and 8 consecutive pixels stay one
+    // aligned 16-byte operand read
+    auto swz = [](int row) { return ((row >> 3) & 7) << 3; };
     __shared__ uint16_t gT[COUT][LD];
     __shared__ uint16_t iT[CT][LD];
     // workgroups are dealt to the 8 XCDs round-robin by their linear index:
@@ -342,7 +348,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *gpre, const 
             const int pi = v / (COUT / 8), cv = (v - pi * (COUT / 8)) * 8;
             if (v < GV)
 #pragma unroll
-                for (int e = 0; e < 8; ++e) gT[cv + e][pi] = (uint16_t)(gv[q][e >> 1] >> (16 * (e & 1)));
+                for (int e = 0; e < 8; ++e) gT[cv + e][pi ^ swz(cv + e)] = (uint16_t)(gv[q][e >> 1] >> (16 * (e & 1)));
         }
 #pragma unroll
         for (int q = 0; q < (IV + 255) / 256; ++q) {
@@ -350,11 +356,11 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *gpre, const 
             const int pi = v / (CT / 8), cv = (v - pi * (CT / 8)) * 8;
             if (v < IV)
 #pragma unroll
-                for (int e = 0; e < 8; ++e) iT[cv + e][pi] = (uint16_t)(iv[q][e >> 1] >> (16 * (e & 1)));
+                for (int e = 0; e < 8; ++e) iT[cv + e][pi ^ swz(cv + e)] = (uint16_t)(iv[q][e >> 1] >> (16 * (e & 1)));
         }
         __syncthreads();
         if (tap == 0 && (int)threadIdx.x < COUT)
-            for (int k = 0; k < KS; ++k) bpart += bf2f(gT[threadIdx.x][k]);
+            for (int k = 0; k < KS; ++k) bpart += bf2f(gT[threadIdx.x][k ^ swz((int)threadIdx.x)]);
 #pragma unroll
         for (int kk = 0; kk < KS; kk += 32)
 #pragma unroll
@@ -362,8 +368,8 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *gpre, const 
                 const int tile = w * TPW + j;
                 if (tile < TILES) {
                     const int mt = tile / NTT, nt = tile - (tile / NTT) * NTT;
-                    const bf16x8 a = as_bf(*reinterpret_cast<const u32x4 *>(&gT[mt * 16 + r][kk + gq * 8]));
-                    const bf16x8 b = as_bf(*reinterpret_cast<const u32x4 *>(&iT[nt * 16 + r][kk + gq * 8]));
+                    const bf16x8 a = as_bf(*reinterpret_cast<const u32x4 *>(&gT[mt * 16 + r][(kk + gq * 8) ^ swz(mt * 16 + r)]));
+                    const bf16x8 b = as_bf(*reinterpret_cast<const u32x4 *>(&iT[nt * 16 + r][(kk + gq * 8) ^ swz(nt * 16 + r)]));
                     acc[j] = mfma(a, b, acc[j]);
                 }
             }
