@@ -22,8 +22,8 @@ namespace nn {
 constexpr int kLayers = 8;              // e1 e2 e3 e4 d3 d2 d1 head
 constexpr float kDepthScale = 4.0f;     // metres: input normalisation (d / 4 m)
 constexpr float kCorrScale = 0.05f;     // metres: unit of the head's depth correction
-constexpr int kWgradStep = 64;         // pixels per LDS staging round of the conv weight gradient
-constexpr int kWgradChunkPix = 512;   // target pixels per chunk of a conv weight-gradient reduction
+constexpr int kWgradStep = 64;          // pixels per LDS staging round of the conv weight gradient
+constexpr int kWgradChunkPix = 512;    // target pixels per chunk of a conv weight-gradient reduction
 
 // pixel chunks of a conv weight-gradient reduction over P output pixels
 inline int wgrad_chunks(long P)

@@ -291,7 +291,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *gpre, const 
     constexpr int KS = kWgradStep;   // pixels staged per round (4 MFMA k-steps)
     constexpr int LD = KS + 8;       // LDS row pitch in bf16 elements (16-byte aligned rows)
     constexpr int GV = KS * (COUT / 8), IV = KS * (CT / 8);   // 16-byte vectors staged per round
-    static_assert(KS == 64, "the column swizzle below spans 64 pixels");
+    static_assert(KS % 64 == 0, "the column swizzle below permutes within 64-pixel spans");
     // the pixel column of LDS row `row` is XORed with 8 ((row / 8) % 8): the
     // transposed 16-bit writes of one instruction (8 rows apart per lane
     // group) then spread over the banks, and 8 consecutive pixels stay one
