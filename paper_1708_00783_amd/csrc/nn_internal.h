@@ -23,7 +23,7 @@ constexpr int kLayers = 8;              // e1 e2 e3 e4 d3 d2 d1 head
 constexpr float kDepthScale = 4.0f;     // metres: input normalisation (d / 4 m)
 constexpr float kCorrScale = 0.05f;     // metres: unit of the head's depth correction
 constexpr int kWgradStep = 64;          // pixels per LDS staging round of the conv weight gradient
-constexpr int kWgradChunkPix = 512;    // target pixels per chunk of a conv weight-gradient reduction
+constexpr int kWgradChunkPix = 512;     // target pixels per chunk of a conv weight-gradient reduction
 
 // pixel chunks of a conv weight-gradient reduction over P output pixels
 inline int wgrad_chunks(long P)
@@ -31,6 +31,7 @@ inline int wgrad_chunks(long P)
     const long c = P / kWgradChunkPix;
     return (int)(c < 64 ? 64 : (c > 512 ? 512 : c));
 }
+
 constexpr int kHeadChunks = 1024;       // pixel chunks of the head's weight-gradient reduction
 
 struct LayerDesc {
