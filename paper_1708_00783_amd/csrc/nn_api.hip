@@ -42,7 +42,8 @@ Net make_net()
         L.kp = ((9 * L.cinp + 31) / 32) * 32;
         if (l < kLayers - 1) {
             L.g_off = go;
-            go += L.cout * L.kp;
+            // upsampled layers: the forward reads parity-folded 2x2 weights
+            go += L.up ? 4 * L.cout * 4 * L.cinp : L.cout * L.kp;
             L.t_off = l > 0 ? to : -1;
             if (l > 0) to += L.cinp * 9 * L.cout;
         } else {

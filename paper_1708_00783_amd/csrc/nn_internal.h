@@ -40,7 +40,8 @@ struct LayerDesc {
     int skip;                           // activation index added before the relu (-1 none)
     int w_off, b_off;                   // fp32 parameter offsets
     int kp;                             // forward GEMM K (padded)
-    int g_off, t_off;                   // bf16 packed-weight offsets (elements)
+    int g_off, t_off;                   // bf16 packed-weight offsets (elements); g of an up layer is
+                                        // parity-folded: [4 parities][cout][4 source taps x cinp]
     int scale;                          // output resolution divisor (1, 2, 4, 8)
 };
 

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_pack(const float *w, int cin, int cinp,
                                               uint16_t *t)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < cout * kp) {
+    if (g && i < cout * kp) {
         const int co = i / kp, k = i % kp, tap = k / cinp, ci = k % cinp;
         g[i] = (tap < 9 && ci < cin) ? f2bf(w[(co * 9 + tap) * cin + ci]) : (uint16_t)0;
     }
@@ -109,6 +109,107 @@ __global__ __launch_bounds__(256) void k_pack(const float *w, int cin, int cinp,
         const int ci = i / (9 * cout), k = i % (9 * cout), tap = k / cout, co = k % cout;
         t[i] = ci < cin ? f2bf(w[(co * 9 + tap) * cin + ci]) : (uint16_t)0;
     }
+}
+
+// Nearest 2x upsampling followed by a 3x3 convolution, folded by output
+// parity: output pixel (2m + py, 2n + px) reads only the 2x2 source pixels
+// (m + py - 1 + a, n + px - 1 + b), a, b in {0, 1}.  Tap ky lands on source
+// row offset a = ((py + ky - 1) >> 1) + 1 - py (likewise kx -> b), so
+// gu[py * 2 + px][co][(a * 2 + b) * cinp + ci] is the fp32 sum of the
+// bf16-rounded weights of the taps that land there (ascending ky, kx),
+// rounded to bf16.  Zero padding agrees: a source row is outside the image
+// exactly when every tap landing on it is.
+__global__ __launch_bounds__(256) void k_pack_up(const float *w, int cin, int cinp, int cout, uint16_t *gu)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int k4 = 4 * cinp;
+    if (i >= 4 * cout * k4) return;
+    const int par = i / (cout * k4), rem = i - par * cout * k4;
+    const int co = rem / k4, k = rem - co * k4, q = k / cinp, ci = k - (k / cinp) * cinp;
+    const int py = par >> 1, px = par & 1, a = q >> 1, b = q & 1;
+    float s = 0.0f;
+    if (ci < cin)
+        for (int ky = 0; ky < 3; ++ky) {
+            if (((py + ky - 1) >> 1) + 1 - py != a) continue;
+            for (int kx = 0; kx < 3; ++kx) {
+                if (((px + kx - 1) >> 1) + 1 - px != b) continue;
+                s += bf2f(f2bf(w[(co * 9 + ky * 3 + kx) * cin + ci]));
+            }
+        }
+    gu[i] = f2bf(s);
+}
+
+// forward of an upsampled layer on the parity-folded weights: a wave takes
+// 16 T source columns of one source row and one output parity (K = 4 cinp
+// instead of 9 cinp) and COUT / NS output channels; the 4 parities of a
+// column run are neighbouring waves and read the same source pixels
+template <int CINP, int COUT, bool SKIP, int T, int NS>
+__global__ __launch_bounds__(256) void k_conv_fwd_up(const uint16_t *in, int Hs, int Ws, const uint16_t *gu,
+                                                     const float *bias, const uint16_t *skip, uint16_t *out, int N)
+{
+    static_assert(NS == 1 || NS == 2 || NS == 4, "channel split must divide the 4 waves of a workgroup");
+    constexpr int K4 = 4 * CINP;
+    static_assert(K4 % 32 == 0, "K must be whole MFMA steps");
+    constexpr int NT = COUT / 16 / NS;
+    const int lane = (int)threadIdx.x & 63, r = lane & 15, gq = lane >> 4;
+    const int runs = (Ws + 16 * T - 1) / (16 * T);
+    const long wid = (long)blockIdx.x * 4 + ((int)threadIdx.x >> 6);
+    const long grp = wid / NS;
+    if (grp >= (long)N * Hs * runs * 4) return;
+    const int cbase = (int)(wid % NS) * (COUT / NS);
+    const int par = (int)(grp & 3);
+    const long rowrun = grp >> 2;
+    const int run = (int)(rowrun % runs);
+    const long nm = rowrun / runs;   // image * Hs + source row
+    const int nimg = (int)(nm / Hs), m = (int)(nm - (long)nimg * Hs);
+    const int py = par >> 1, px = par & 1;
+    const int Ho = 2 * Hs, Wo = 2 * Ws;
+    const int c0 = run * 16 * T;
+    f32x4 acc[T][NT];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t *gp = gu + (size_t)par * COUT * K4;
+    for (int k0 = 0; k0 < K4; k0 += 32) {
+        const int k = k0 + gq * 8;
+        const int q = k / CINP, ci = k - (k / CINP) * CINP;
+        const int sy = m + py - 1 + (q >> 1);
+        bf16x8 av[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const int nn = c0 + t * 16 + r;
+            const int sx = nn + px - 1 + (q & 1);
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (nn < Ws && sy >= 0 && sy < Hs && sx >= 0 && sx < Ws)
+                v = ld16(in + (((size_t)nimg * Hs + sy) * Ws + sx) * CINP + ci);
+            av[t] = as_bf(v);
+        }
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const bf16x8 b = as_bf(ld16(gp + (size_t)(cbase + j * 16 + r) * K4 + k));
+#pragma unroll
+            for (int t = 0; t < T; ++t) acc[t][j] = mfma(av[t], b, acc[t][j]);
+        }
+    }
+    const size_t orow = ((size_t)nimg * Ho + 2 * m + py) * Wo;
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int co = cbase + j * 16 + r;
+            const float bb = bias[co];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int nn = c0 + t * 16 + gq * 4 + i;
+                if (nn >= Ws) continue;
+                const size_t p = orow + 2 * nn + px;
+                float v = acc[t][j][i] + bb;
+                if (SKIP) v += bf2f(skip[p * COUT + co]);
+                v = v > 0.0f ? v : 0.0f;
+                out[p * COUT + co] = f2bf(v);
+            }
+        }
 }
 
 // ============================================================================
@@ -664,11 +765,24 @@ hipError_t launch_pack(const Net &net, const float *params, uint16_t *g, uint16_
         const LayerDesc &L = net.L[l];
         const int n = L.cout * L.kp > L.cinp * 9 * L.cout ? L.cout * L.kp : L.cinp * 9 * L.cout;
         hipLaunchKernelGGL(k_pack, grid1(n, 256), dim3(256), 0, s, params + L.w_off, L.cin, L.cinp, L.cout, L.kp,
-                           g + L.g_off, L.t_off >= 0 ? t + L.t_off : (uint16_t *)nullptr);
+                           L.up ? (uint16_t *)nullptr : g + L.g_off, L.t_off >= 0 ? t + L.t_off : (uint16_t *)nullptr);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+        if (L.up) {
+            hipLaunchKernelGGL(k_pack_up, grid1(16L * L.cout * L.cinp, 256), dim3(256), 0, s, params + L.w_off, L.cin,
+                               L.cinp, L.cout, g + L.g_off);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
+}
+
+// workgroups of k_conv_fwd_up: N Hs source rows x column runs of 16 T x 4 parities x NS waves
+static dim3 up_grid(int N, int Hs, int Ws, int T, int NS)
+{
+    const long waves = (long)N * Hs * ((Ws + 16 * T - 1) / (16 * T)) * 4 * NS;
+    return dim3((unsigned)((waves + 3) / 4));
 }
 
 hipError_t launch_conv_fwd(int layer, const uint16_t *in, int Hs, int Ws, const uint16_t *g, const float *bias,
@@ -677,15 +791,17 @@ hipError_t launch_conv_fwd(int layer, const uint16_t *in, int Hs, int Ws, const 
     // 64 output pixels per wave for 32 output channels, else 32; the deepest
     // layers (fewest pixels) split their output channels over 4 or 2 waves
     const long P = (long)N * Ho * Wo;
-    const dim3 g4 = grid1(P, 256), g2 = grid1(P, 128), g2s2 = grid1(P, 64), g2s4 = grid1(P, 32), b(256);
+    const dim3 g4 = grid1(P, 256), g2 = grid1(P, 128), g2s4 = grid1(P, 32), b(256);
+    if (layer >= 4 && (Ho != 2 * Hs || Wo != 2 * Ws)) return hipErrorInvalidValue;
     switch (layer) {
     case 0: hipLaunchKernelGGL((k_conv_fwd<8, 32, 1, false, false, 4, 1>), g4, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
     case 1: hipLaunchKernelGGL((k_conv_fwd<32, 64, 2, false, false, 2, 1>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
     case 2: hipLaunchKernelGGL((k_conv_fwd<64, 64, 2, false, false, 2, 1>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
     case 3: hipLaunchKernelGGL((k_conv_fwd<64, 128, 2, false, false, 2, 4>), g2s4, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 4: hipLaunchKernelGGL((k_conv_fwd<128, 64, 1, true, true, 2, 2>), g2s2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 5: hipLaunchKernelGGL((k_conv_fwd<64, 64, 1, true, true, 2, 1>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 6: hipLaunchKernelGGL((k_conv_fwd<64, 32, 1, true, true, 4, 1>), g4, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    // upsampled layers: parity-folded weights, one wave per (source row, parity, column run)
+    case 4: hipLaunchKernelGGL((k_conv_fwd_up<128, 64, true, 2, 2>), up_grid(N, Hs, Ws, 2, 2), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
+    case 5: hipLaunchKernelGGL((k_conv_fwd_up<64, 64, true, 2, 1>), up_grid(N, Hs, Ws, 2, 1), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
+    case 6: hipLaunchKernelGGL((k_conv_fwd_up<64, 32, true, 4, 1>), up_grid(N, Hs, Ws, 4, 1), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

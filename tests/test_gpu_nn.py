@@ -2,11 +2,15 @@
 fp32 accumulation) against the oracle.
 
 Per layer, the oracle recomputes the GPU's result from the GPU's own bf16
-operands (inputs, bf16-rounded weights, upstream gradients) in float64, so
+operands (inputs, bf16-rounded weights -- parity-folded for the forward of an
+upsampled layer --, upstream gradients) in float64, so
 the only differences are accumulation order and the final bf16 rounding:
 outputs within 1 bf16 ulp-scale (0.8% relative plus a small absolute floor),
 weight gradients within 1e-3 relative.  End to end against the float64
-oracle on bf16-rounded weights and input: per-layer gradient cosine >= 0.999.
+oracle on bf16-rounded weights and input: per-layer gradient cosine >= 0.998
+(the forward of the upsampled layers rounds its parity-folded weights to
+bf16 once more, which moves a few L1-loss signs and near-zero relu decisions;
+a wrong gradient anywhere gives cosines far below this).
 Adam matches the oracle's update; a zero head is the identity exactly.
 The end-to-end comparison runs the oracle with bf16 rounding of everything the
 kernels store in bf16, so both sides take their relu decisions on the same
@@ -15,6 +19,7 @@ import numpy as np
 import pytest
 
 from oracle import denoise as D
+from upfold import fold, folded_forward
 
 pytestmark = pytest.mark.gpu
 
@@ -83,8 +88,13 @@ def test_forward_layers_match_oracle():
         if name == "e1":
             a = a[..., :3]
         if up:
-            a = D.up2(a)
-        ref = D.conv(a, _rb(P[name + ".w"]), P[name + ".b"], stride)
+            # the kernel's operands: parity-folded weights, the fp32 sum of the
+            # bf16-rounded taps rounded to bf16 (the fold itself is checked
+            # against up2 + conv in test_upsample_fold)
+            f = D.to_bf16(fold(_rb(P[name + ".w"]), np.float32)).astype(np.float64)
+            ref = folded_forward(a, f, P[name + ".b"])
+        else:
+            ref = D.conv(a, _rb(P[name + ".w"]), P[name + ".b"], stride)
         if skip:
             ref = ref + _bf(net, skip)
         ref = np.maximum(ref, 0)
@@ -153,7 +163,7 @@ def test_end_to_end_gradient_cosine():
         a, b = grads[k].reshape(-1).astype(np.float64), G[k].reshape(-1)
         cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30))
         _log(f"{k}: cosine {cos:.6f}")
-        assert cos >= 0.999, (k, cos)
+        assert cos >= 0.998, (k, cos)
 
 
 def test_adam_matches_oracle():

@@ -1,0 +1,40 @@
+"""Test helper: a nearest 2x upsampling followed by a 3x3 convolution written
+as four 2x2 convolutions of the source, one per output parity (py, px).  Tap
+ky lands on source row offset a = floor((py + ky - 1) / 2) + 1 - py in {0, 1}
+(likewise kx -> b), so output (2m + py, 2n + px) reads source pixels
+(m + py - 1 + a, n + px - 1 + b)."""
+import numpy as np
+
+
+def fold(w, acc_dtype=np.float64):
+    """(cout, 3, 3, cin) or (cout, 9, cin) -> (2, 2, cout, 2, 2, cin):
+    [py][px][co][a][b][ci], summed in ascending (ky, kx) order in `acc_dtype`"""
+    w = w.reshape(w.shape[0], 9, w.shape[-1])
+    cout, _, cin = w.shape
+    f = np.zeros((2, 2, cout, 2, 2, cin), acc_dtype)
+    for py in range(2):
+        for px in range(2):
+            for ky in range(3):
+                a = ((py + ky - 1) >> 1) + 1 - py
+                for kx in range(3):
+                    b = ((px + kx - 1) >> 1) + 1 - px
+                    f[py, px, :, a, b, :] += w[:, ky * 3 + kx, :].astype(acc_dtype)
+    return f
+
+
+def folded_forward(x, f, bias):
+    """(N, Hs, Ws, cin) source, folded weights -> (N, 2 Hs, 2 Ws, cout), no relu"""
+    N, Hs, Ws, cin = x.shape
+    cout = f.shape[2]
+    xp = np.zeros((N, Hs + 2, Ws + 2, cin))
+    xp[:, 1:-1, 1:-1] = x
+    y = np.zeros((N, 2 * Hs, 2 * Ws, cout))
+    for py in range(2):
+        for px in range(2):
+            acc = np.zeros((N, Hs, Ws, cout)) + bias
+            for a in range(2):
+                for b in range(2):
+                    src = xp[:, py + a:py + a + Hs, px + b:px + b + Ws]
+                    acc += src @ f[py, px, :, a, b, :].astype(np.float64).T
+            y[:, py::2, px::2] = acc
+    return y
