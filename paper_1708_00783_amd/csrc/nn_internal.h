@@ -62,6 +62,17 @@ inline int act_channels(int a) { static const int c[kActs] = {8, 32, 64, 64, 128
 inline int act_scale(int a) { static const int s[kActs] = {1, 1, 2, 4, 8, 4, 2, 1}; return s[a]; }
 
 hipError_t launch_make_input(const void *depth, int fmt, int N, int H, int W, uint16_t *x, float *dm, hipStream_t s);
+// one layer's share of the weight packing (forward g, backward-data t)
+struct PackJob {
+    const float *w;
+    uint16_t *g, *t;
+    int cin, cinp, cout, kp, up, n_g, n_t;
+};
+struct PackJobs {
+    PackJob job[kLayers - 1];
+    int start[kLayers];   // first thread of each layer; start[kLayers - 1] = total
+};
+
 hipError_t launch_pack(const Net &net, const float *params, uint16_t *g, uint16_t *t, hipStream_t s);
 hipError_t launch_conv_fwd(int layer, const uint16_t *in, int Hs, int Ws, const uint16_t *g, const float *bias,
                            const uint16_t *skip, uint16_t *out, int N, int Ho, int Wo, hipStream_t s);

@@ -95,20 +95,18 @@ __global__ __launch_bounds__(256) void k_make_input(const void *depth, int N, in
 }
 
 // ============================================================================
-// fp32 master weights -> bf16 GEMM operands of one layer
+// fp32 master weights -> bf16 GEMM operands of every conv layer
 // ============================================================================
-__global__ __launch_bounds__(256) void k_pack(const float *w, int cin, int cinp, int cout, int kp, uint16_t *g,
-                                              uint16_t *t)
+__device__ __forceinline__ void pack_g(const float *w, int cin, int cinp, int kp, int i, uint16_t *g)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (g && i < cout * kp) {
-        const int co = i / kp, k = i % kp, tap = k / cinp, ci = k % cinp;
-        g[i] = (tap < 9 && ci < cin) ? f2bf(w[(co * 9 + tap) * cin + ci]) : (uint16_t)0;
-    }
-    if (t && i < cinp * 9 * cout) {
-        const int ci = i / (9 * cout), k = i % (9 * cout), tap = k / cout, co = k % cout;
-        t[i] = ci < cin ? f2bf(w[(co * 9 + tap) * cin + ci]) : (uint16_t)0;
-    }
+    const int co = i / kp, k = i % kp, tap = k / cinp, ci = k % cinp;
+    g[i] = (tap < 9 && ci < cin) ? f2bf(w[(co * 9 + tap) * cin + ci]) : (uint16_t)0;
+}
+
+__device__ __forceinline__ void pack_t(const float *w, int cin, int cout, int i, uint16_t *t)
+{
+    const int ci = i / (9 * cout), k = i % (9 * cout), tap = k / cout, co = k % cout;
+    t[i] = ci < cin ? f2bf(w[(co * 9 + tap) * cin + ci]) : (uint16_t)0;
 }
 
 // Nearest 2x upsampling followed by a 3x3 convolution, folded by output
@@ -119,11 +117,9 @@ __global__ __launch_bounds__(256) void k_pack(const float *w, int cin, int cinp,
 // bf16-rounded weights of the taps that land there (ascending ky, kx),
 // rounded to bf16.  Zero padding agrees: a source row is outside the image
 // exactly when every tap landing on it is.
-__global__ __launch_bounds__(256) void k_pack_up(const float *w, int cin, int cinp, int cout, uint16_t *gu)
+__device__ __forceinline__ void pack_up(const float *w, int cin, int cinp, int cout, int i, uint16_t *gu)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
     const int k4 = 4 * cinp;
-    if (i >= 4 * cout * k4) return;
     const int par = i / (cout * k4), rem = i - par * cout * k4;
     const int co = rem / k4, k = rem - co * k4, q = k / cinp, ci = k - (k / cinp) * cinp;
     const int py = par >> 1, px = par & 1, a = q >> 1, b = q & 1;
@@ -137,6 +133,25 @@ __global__ __launch_bounds__(256) void k_pack_up(const float *w, int cin, int ci
             }
         }
     gu[i] = f2bf(s);
+}
+
+// every conv layer's packed weights in one launch: thread i belongs to the
+// layer whose [start, next start) range holds it
+__global__ __launch_bounds__(256) void k_pack(PackJobs J)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    int l = 0;
+    while (l < kLayers - 1 && i >= J.start[l + 1]) ++l;
+    if (l >= kLayers - 1) return;
+    const PackJob &p = J.job[l];
+    const int li = i - J.start[l];
+    if (li < p.n_g) {
+        if (p.up)
+            pack_up(p.w, p.cin, p.cinp, p.cout, li, p.g);
+        else
+            pack_g(p.w, p.cin, p.cinp, p.kp, li, p.g);
+    }
+    if (p.t && li < p.n_t) pack_t(p.w, p.cin, p.cout, li, p.t);
 }
 
 // forward of an upsampled layer on the parity-folded weights: a wave takes
@@ -761,21 +776,27 @@ hipError_t launch_make_input(const void *depth, int fmt, int N, int H, int W, ui
 
 hipError_t launch_pack(const Net &net, const float *params, uint16_t *g, uint16_t *t, hipStream_t s)
 {
+    PackJobs J = {};
+    int at = 0;
     for (int l = 0; l < kLayers - 1; ++l) {
         const LayerDesc &L = net.L[l];
-        const int n = L.cout * L.kp > L.cinp * 9 * L.cout ? L.cout * L.kp : L.cinp * 9 * L.cout;
-        hipLaunchKernelGGL(k_pack, grid1(n, 256), dim3(256), 0, s, params + L.w_off, L.cin, L.cinp, L.cout, L.kp,
-                           L.up ? (uint16_t *)nullptr : g + L.g_off, L.t_off >= 0 ? t + L.t_off : (uint16_t *)nullptr);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        if (L.up) {
-            hipLaunchKernelGGL(k_pack_up, grid1(16L * L.cout * L.cinp, 256), dim3(256), 0, s, params + L.w_off, L.cin,
-                               L.cinp, L.cout, g + L.g_off);
-            e = hipGetLastError();
-            if (e != hipSuccess) return e;
-        }
+        PackJob &p = J.job[l];
+        p.w = params + L.w_off;
+        p.g = g + L.g_off;
+        p.t = L.t_off >= 0 ? t + L.t_off : nullptr;
+        p.cin = L.cin;
+        p.cinp = L.cinp;
+        p.cout = L.cout;
+        p.kp = L.kp;
+        p.up = L.up;
+        p.n_g = L.up ? 16 * L.cout * L.cinp : L.cout * L.kp;
+        p.n_t = p.t ? L.cinp * 9 * L.cout : 0;
+        J.start[l] = at;
+        at += p.n_g > p.n_t ? p.n_g : p.n_t;
     }
-    return hipSuccess;
+    J.start[kLayers - 1] = at;
+    hipLaunchKernelGGL(k_pack, grid1(at, 256), dim3(256), 0, s, J);
+    return hipGetLastError();
 }
 
 // workgroups of k_conv_fwd_up: N Hs source rows x column runs of 16 T x 4 parities x NS waves
