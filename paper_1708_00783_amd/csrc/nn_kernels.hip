@@ -186,6 +186,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_up(const uint16_t *in, int Hs,
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const uint16_t *gp = gu + (size_t)par * COUT * K4;
+#pragma unroll 2
     for (int k0 = 0; k0 < K4; k0 += 32) {
         const int k = k0 + gq * 8;
         const int q = k / CINP, ci = k - (k / CINP) * CINP;
@@ -265,6 +266,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, in
     for (int t = 0; t < T; ++t)
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
     for (int k0 = 0; k0 < KP; k0 += 32) {
         const int k = k0 + gq * 8;
         const int tap = k / CINP, ci = k - (k / CINP) * CINP;
