@@ -394,6 +394,86 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t *gpre, int
         }
 }
 
+// backward data of a stride-2 layer by input parity: input pixel
+// (2m + py, 2n + px) receives gradient only through the taps ky = 1 (py = 0)
+// or ky in {0, 2} (py = 1), likewise kx, from output pixel
+// ((iy + 1 - ky) / 2, (ix + 1 - kx) / 2) -- 1, 2 or 4 of the 9 taps.  A wave
+// takes 32 same-parity columns of one input row and CIN / NS channels; the
+// skip gradient and the relu mask are fused as in k_conv_bwd_data.
+template <int CIN, int COUT, bool SKIP, int NS>
+__global__ __launch_bounds__(256) void k_conv_bwd_data_s2(const uint16_t *gpre, int Ho, int Wo, const uint16_t *tw,
+                                                          const uint16_t *skipg, const uint16_t *act, uint16_t *gout,
+                                                          int N, int Hq, int Wq)
+{
+    static_assert(NS == 1 || NS == 2 || NS == 4, "channel split must divide the 4 waves of a workgroup");
+    static_assert(COUT % 32 == 0, "a K step is 32 output channels of one tap");
+    constexpr int K9 = 9 * COUT;
+    constexpr int NT = CIN / 16 / NS;
+    const int lane = (int)threadIdx.x & 63, r = lane & 15, gq = lane >> 4;
+    const int Wh = (Wq + 1) >> 1, runs = (Wh + 31) >> 5;
+    const long wid = (long)blockIdx.x * 4 + ((int)threadIdx.x >> 6);
+    const long grp = wid / NS;
+    if (grp >= (long)N * Hq * 2 * runs) return;
+    const int cbase = (int)(wid % NS) * (CIN / NS);
+    const int run = (int)(grp % runs);
+    const long rp = grp / runs;
+    const int px = (int)(rp & 1);
+    const long ni = rp >> 1;   // image * Hq + input row
+    const int nimg = (int)(ni / Hq), iy = (int)(ni - (long)nimg * Hq);
+    const int py = iy & 1;
+    f32x4 acc[2][NT];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int nty = py ? 2 : 1, ntx = px ? 2 : 1;
+    for (int a = 0; a < nty; ++a) {
+        const int ky = py ? 2 * a : 1;
+        const int oy = (iy + 1 - ky) >> 1;
+        const bool rowok = oy >= 0 && oy < Ho;
+        for (int b = 0; b < ntx; ++b) {
+            const int kx = px ? 2 * b : 1;
+            const int tap = ky * 3 + kx;
+            for (int co0 = 0; co0 < COUT; co0 += 32) {
+                const int co = co0 + gq * 8;
+                bf16x8 av[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int ix = 2 * (run * 32 + t * 16 + r) + px;
+                    const int ox = (ix + 1 - kx) >> 1;
+                    u32x4 v = {0u, 0u, 0u, 0u};
+                    if (rowok && ix < Wq && ox >= 0 && ox < Wo)
+                        v = ld16(gpre + (((size_t)nimg * Ho + oy) * Wo + ox) * COUT + co);
+                    av[t] = as_bf(v);
+                }
+#pragma unroll
+                for (int j = 0; j < NT; ++j) {
+                    const bf16x8 bv = as_bf(ld16(tw + (size_t)(cbase + j * 16 + r) * K9 + tap * COUT + co));
+                    acc[0][j] = mfma(av[0], bv, acc[0][j]);
+                    acc[1][j] = mfma(av[1], bv, acc[1][j]);
+                }
+            }
+        }
+    }
+    const size_t prow = ((size_t)nimg * Hq + iy) * Wq;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int c = cbase + j * 16 + r;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ix = 2 * (run * 32 + t * 16 + gq * 4 + i) + px;
+                if (ix >= Wq) continue;
+                const size_t p = prow + ix;
+                float v = acc[t][j][i];
+                if (SKIP) v += bf2f(skipg[p * CIN + c]);
+                if (!(bf2f(act[p * CIN + c]) > 0.0f)) v = 0.0f;
+                gout[p * CIN + c] = f2bf(v);
+            }
+        }
+}
+
 // ============================================================================
 // weight gradient of one tap over one pixel chunk:
 // partial[chunk][co][tap][ci] = sum_p gpre[p][co] * in_tap(p)[ci]; the bias
@@ -867,16 +947,24 @@ hipError_t launch_head_wgrad(const float *ddelta, const uint16_t *d1, int N, int
     return hipGetLastError();
 }
 
+// workgroups of k_conv_bwd_data_s2: N Hq input rows x 2 column parities x runs of 32 x NS waves
+static dim3 s2_grid(int N, int Hq, int Wq, int NS)
+{
+    const long waves = (long)N * Hq * 2 * ((((Wq + 1) >> 1) + 31) >> 5) * NS;
+    return dim3((unsigned)((waves + 3) / 4));
+}
+
 hipError_t launch_conv_bwd_data(int layer, const uint16_t *gpre, int Ho, int Wo, const uint16_t *t,
                                 const uint16_t *skipg, const uint16_t *act, uint16_t *gout, int N, int Hq, int Wq,
                                 hipStream_t s)
 {
     const long P = (long)N * Hq * Wq;
-    const dim3 g1 = grid1(P, 128), g2 = grid1(P, 64), g4 = grid1(P, 32), b(256);
+    const dim3 g1 = grid1(P, 128), g4 = grid1(P, 32), b(256);
     switch (layer) {
-    case 1: hipLaunchKernelGGL((k_conv_bwd_data<32, 64, 2, false, true, 1>), g1, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
-    case 2: hipLaunchKernelGGL((k_conv_bwd_data<64, 64, 2, false, true, 1>), g1, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
-    case 3: hipLaunchKernelGGL((k_conv_bwd_data<64, 128, 2, false, true, 2>), g2, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
+    // stride-2 layers: only the taps of each input parity
+    case 1: hipLaunchKernelGGL((k_conv_bwd_data_s2<32, 64, true, 1>), s2_grid(N, Hq, Wq, 1), b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
+    case 2: hipLaunchKernelGGL((k_conv_bwd_data_s2<64, 64, true, 1>), s2_grid(N, Hq, Wq, 1), b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
+    case 3: hipLaunchKernelGGL((k_conv_bwd_data_s2<64, 128, true, 2>), s2_grid(N, Hq, Wq, 2), b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
     case 4: hipLaunchKernelGGL((k_conv_bwd_data<128, 64, 1, true, false, 4>), g4, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
     case 5: hipLaunchKernelGGL((k_conv_bwd_data<64, 64, 1, true, false, 1>), g1, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
     case 6: hipLaunchKernelGGL((k_conv_bwd_data<64, 32, 1, true, false, 1>), g1, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
