@@ -95,6 +95,86 @@ __global__ __launch_bounds__(256) void k_make_input(const void *depth, int N, in
 }
 
 // ============================================================================
+// epilogue of the implicit-GEMM convolutions.  In the MFMA result a lane holds
+// 4 pixels of one channel per 16x16 tile, so the per-element bias / skip /
+// activation reads and the output writes would be 2-byte accesses.  A wave
+// stages each 16-pixel row tile in its own LDS tile instead; every lane then
+// handles whole 16-byte vectors (one pixel, 8 channels).  All 4 waves of the
+// workgroup call it the same number of times (it holds workgroup barriers).
+// ============================================================================
+template <int NT>
+struct alignas(16) EpiTile {
+    float v[16][NT * 16 + 4];   // +4: the staging writes of one instruction hit distinct banks
+};
+
+template <int NT, typename F>
+__device__ __forceinline__ void epilogue_tile(EpiTile<NT> &st, const f32x4 (&a)[NT], int lane, F &&emit)
+{
+    const int r = lane & 15, gq = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) st.v[gq * 4 + i][j * 16 + r] = a[j][i];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < (32 * NT + 63) / 64; ++u) {
+        const int v = lane + 64 * u;   // 16 pixels x 2 NT vectors of 8 channels
+        if (v < 32 * NT) {
+            const int pix = v / (2 * NT), c8 = (v - pix * 2 * NT) * 8;
+            const f32x4 lo = *reinterpret_cast<const f32x4 *>(&st.v[pix][c8]);
+            const f32x4 hi = *reinterpret_cast<const f32x4 *>(&st.v[pix][c8 + 4]);
+            emit(pix, c8, lo, hi);
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t bf2(float a, float b) { return (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16); }
+
+// forward: o[e] = bf16(relu(x[e] + bias[e] (+ skip[e]))), e = 0..7
+template <bool SKIP>
+__device__ __forceinline__ void fwd_store8(uint16_t *o, f32x4 lo, f32x4 hi, const float *bias, const uint16_t *skip)
+{
+    const float x[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    u32x4 sk = {0u, 0u, 0u, 0u};
+    if (SKIP) sk = ld16(skip);
+    u32x4 ov;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        float v0 = x[2 * e] + bias[2 * e], v1 = x[2 * e + 1] + bias[2 * e + 1];
+        if (SKIP) {
+            v0 += bf2f((uint16_t)(sk[e] & 0xffffu));
+            v1 += bf2f((uint16_t)(sk[e] >> 16));
+        }
+        ov[e] = bf2(v0 > 0.0f ? v0 : 0.0f, v1 > 0.0f ? v1 : 0.0f);
+    }
+    *reinterpret_cast<u32x4 *>(o) = ov;
+}
+
+// backward data: o[e] = bf16(x[e] (+ skipg[e])), zero where act[e] <= 0
+template <bool SKIP>
+__device__ __forceinline__ void bwd_store8(uint16_t *o, f32x4 lo, f32x4 hi, const uint16_t *skipg, const uint16_t *act)
+{
+    const float x[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    u32x4 sk = {0u, 0u, 0u, 0u};
+    if (SKIP) sk = ld16(skipg);
+    const u32x4 av = ld16(act);
+    u32x4 ov;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        float v0 = x[2 * e], v1 = x[2 * e + 1];
+        if (SKIP) {
+            v0 += bf2f((uint16_t)(sk[e] & 0xffffu));
+            v1 += bf2f((uint16_t)(sk[e] >> 16));
+        }
+        if (!(bf2f((uint16_t)(av[e] & 0xffffu)) > 0.0f)) v0 = 0.0f;
+        if (!(bf2f((uint16_t)(av[e] >> 16)) > 0.0f)) v1 = 0.0f;
+        ov[e] = bf2(v0, v1);
+    }
+    *reinterpret_cast<u32x4 *>(o) = ov;
+}
+
+// ============================================================================
 // fp32 master weights -> bf16 GEMM operands of every conv layer
 // ============================================================================
 __device__ __forceinline__ void pack_g(const float *w, int cin, int cinp, int kp, int i, uint16_t *g)
@@ -169,8 +249,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd_up(const uint16_t *in, int Hs,
     const int lane = (int)threadIdx.x & 63, r = lane & 15, gq = lane >> 4;
     const int runs = (Ws + 16 * T - 1) / (16 * T);
     const long wid = (long)blockIdx.x * 4 + ((int)threadIdx.x >> 6);
-    const long grp = wid / NS;
-    if (grp >= (long)N * Hs * runs * 4) return;
+    const bool live = wid / NS < (long)N * Hs * runs * 4;   // dead waves still join the epilogue barriers
+    const long grp = live ? wid / NS : 0;
     const int cbase = (int)(wid % NS) * (COUT / NS);
     const int par = (int)(grp & 3);
     const long rowrun = grp >> 2;
@@ -209,23 +289,16 @@ __global__ __launch_bounds__(256) void k_conv_fwd_up(const uint16_t *in, int Hs,
         }
     }
     const size_t orow = ((size_t)nimg * Ho + 2 * m + py) * Wo;
+    __shared__ EpiTile<NT> st[4];
 #pragma unroll
     for (int t = 0; t < T; ++t)
-#pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const int co = cbase + j * 16 + r;
-            const float bb = bias[co];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int nn = c0 + t * 16 + gq * 4 + i;
-                if (nn >= Ws) continue;
-                const size_t p = orow + 2 * nn + px;
-                float v = acc[t][j][i] + bb;
-                if (SKIP) v += bf2f(skip[p * COUT + co]);
-                v = v > 0.0f ? v : 0.0f;
-                out[p * COUT + co] = f2bf(v);
-            }
-        }
+        epilogue_tile(st[threadIdx.x >> 6], acc[t], lane, [&](int pix, int c8, f32x4 lo, f32x4 hi) {
+            const int nn = c0 + t * 16 + pix;
+            if (!live || nn >= Ws) return;
+            const size_t p = orow + 2 * nn + px;
+            const int co = cbase + c8;
+            fwd_store8<SKIP>(out + p * COUT + co, lo, hi, bias + co, SKIP ? skip + p * COUT + co : nullptr);
+        });
 }
 
 // ============================================================================
@@ -245,8 +318,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, in
     const long P = (long)N * Ho * Wo;
     const int wid = (int)blockIdx.x * 4 + ((int)threadIdx.x >> 6);
     const int cbase = (wid % NS) * (COUT / NS);
-    const long p0 = (long)(wid / NS) * (16 * T);
-    if (p0 >= P) return;
+    const long p0 = (long)(wid / NS) * (16 * T);   // waves past P load nothing and store nothing
     const int r = lane & 15, gq = lane >> 4;
     const int Hc = UP ? 2 * Hs : Hs, Wc = UP ? 2 * Ws : Ws;   // conv input size
     int pn[T], py[T], px[T];
@@ -289,22 +361,15 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, in
             for (int t = 0; t < T; ++t) acc[t][j] = mfma(a[t], b, acc[t][j]);
         }
     }
+    __shared__ EpiTile<NT> st[4];
 #pragma unroll
     for (int t = 0; t < T; ++t)
-#pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const int co = cbase + j * 16 + r;
-            const float bb = bias[co];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const long p = p0 + t * 16 + gq * 4 + i;
-                if (p >= P) continue;
-                float v = acc[t][j][i] + bb;
-                if (SKIP) v += bf2f(skip[(size_t)p * COUT + co]);
-                v = v > 0.0f ? v : 0.0f;
-                out[(size_t)p * COUT + co] = f2bf(v);
-            }
-        }
+        epilogue_tile(st[threadIdx.x >> 6], acc[t], lane, [&](int pix, int c8, f32x4 lo, f32x4 hi) {
+            const long p = p0 + t * 16 + pix;
+            if (p >= P) return;
+            const int co = cbase + c8;
+            fwd_store8<SKIP>(out + (size_t)p * COUT + co, lo, hi, bias + co, SKIP ? skip + (size_t)p * COUT + co : nullptr);
+        });
 }
 
 // ============================================================================
@@ -327,8 +392,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t *gpre, int
     const long P = (long)N * Hq * Wq;
     const int wid = (int)blockIdx.x * 4 + ((int)threadIdx.x >> 6);
     const int cbase = (wid % NS) * (CIN / NS);
-    const long p0 = (long)(wid / NS) * 32;
-    if (p0 >= P) return;
+    const long p0 = (long)(wid / NS) * 32;   // waves past P load nothing and store nothing
     const int r = lane & 15, gq = lane >> 4;
     int pn[2], py[2], px[2];
     bool pv[2];
@@ -377,21 +441,15 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t *gpre, int
             acc[1][j] = mfma(a[1], b, acc[1][j]);
         }
     }
+    __shared__ EpiTile<NT> st[4];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const int c = cbase + j * 16 + r;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const long p = p0 + t * 16 + gq * 4 + i;
-                if (p >= P) continue;
-                float v = acc[t][j][i];
-                if (SKIP) v += bf2f(skipg[(size_t)p * CIN + c]);
-                if (!(bf2f(act[(size_t)p * CIN + c]) > 0.0f)) v = 0.0f;
-                gout[(size_t)p * CIN + c] = f2bf(v);
-            }
-        }
+        epilogue_tile(st[threadIdx.x >> 6], acc[t], lane, [&](int pix, int c8, f32x4 lo, f32x4 hi) {
+            const long p = p0 + t * 16 + pix;
+            if (p >= P) return;
+            const size_t o = (size_t)p * CIN + cbase + c8;
+            bwd_store8<SKIP>(gout + o, lo, hi, SKIP ? skipg + o : nullptr, act + o);
+        });
 }
 
 // backward data of a stride-2 layer by input parity: input pixel
@@ -412,8 +470,8 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data_s2(const uint16_t *gpre, 
     const int lane = (int)threadIdx.x & 63, r = lane & 15, gq = lane >> 4;
     const int Wh = (Wq + 1) >> 1, runs = (Wh + 31) >> 5;
     const long wid = (long)blockIdx.x * 4 + ((int)threadIdx.x >> 6);
-    const long grp = wid / NS;
-    if (grp >= (long)N * Hq * 2 * runs) return;
+    const bool live = wid / NS < (long)N * Hq * 2 * runs;   // dead waves still join the epilogue barriers
+    const long grp = live ? wid / NS : 0;
     const int cbase = (int)(wid % NS) * (CIN / NS);
     const int run = (int)(grp % runs);
     const long rp = grp / runs;
@@ -456,22 +514,15 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data_s2(const uint16_t *gpre, 
         }
     }
     const size_t prow = ((size_t)nimg * Hq + iy) * Wq;
+    __shared__ EpiTile<NT> st[4];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const int c = cbase + j * 16 + r;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int ix = 2 * (run * 32 + t * 16 + gq * 4 + i) + px;
-                if (ix >= Wq) continue;
-                const size_t p = prow + ix;
-                float v = acc[t][j][i];
-                if (SKIP) v += bf2f(skipg[p * CIN + c]);
-                if (!(bf2f(act[p * CIN + c]) > 0.0f)) v = 0.0f;
-                gout[p * CIN + c] = f2bf(v);
-            }
-        }
+        epilogue_tile(st[threadIdx.x >> 6], acc[t], lane, [&](int pix, int c8, f32x4 lo, f32x4 hi) {
+            const int ix = 2 * (run * 32 + t * 16 + pix) + px;
+            if (!live || ix >= Wq) return;
+            const size_t o = (prow + ix) * CIN + cbase + c8;
+            bwd_store8<SKIP>(gout + o, lo, hi, SKIP ? skipg + o : nullptr, act + o);
+        });
 }
 
 // ============================================================================
