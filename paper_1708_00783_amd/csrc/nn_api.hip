@@ -101,7 +101,7 @@ bool nlayout(const Net &net, uint32_t B, uint32_t H, uint32_t W, int training, N
         }
         L.partial = take(4 * mx);
         L.hpartial = take(4 * (size_t)kHeadChunks * 289);
-        L.scratch = take(16);
+        L.scratch = take(4 * loss_scratch_words((long)px));
         L.loss = take(16);
     }
     L.total = o;
@@ -211,7 +211,6 @@ int tf_nn_set_params(tf_nn *nn, const float *d_params, tf_stream stream)
         // fresh optimiser state (not a graph-captured call)
         e = hipMemsetAsync(nn->m, 0, 4 * n, s);
         if (e == hipSuccess) e = hipMemsetAsync(nn->v, 0, 4 * n, s);
-        if (e == hipSuccess) e = hipMemsetAsync(nn->scratch, 0, 16, s);
         nn->step = 0;
     }
     if (e == hipSuccess) e = launch_pack(nn->net, nn->params, nn->g, nn->t, s);

@@ -78,6 +78,9 @@ hipError_t launch_conv_fwd(int layer, const uint16_t *in, int Hs, int Ws, const 
                            const uint16_t *skip, uint16_t *out, int N, int Ho, int Wo, hipStream_t s);
 hipError_t launch_head_fwd(const uint16_t *d1, const float *w, const float *b, const float *dm, float *out, int N,
                            int H, int W, hipStream_t s);
+// 32-bit words of loss scratch for n_pix pixels: the count, padding, and a
+// count and a sum per 256-pixel workgroup
+inline size_t loss_scratch_words(long n_pix) { return 4 + 2 * (size_t)((n_pix + 255) / 256); }
 hipError_t launch_loss(const float *out, const float *dm, const float *target, int n_pix, float *ddelta,
                        float *scratch, float *loss, hipStream_t s);
 hipError_t launch_head_bwd(const float *ddelta, const float *w, const uint16_t *d1, uint16_t *g_d1, int N, int H,

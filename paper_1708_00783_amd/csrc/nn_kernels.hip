@@ -709,45 +709,68 @@ __global__ __launch_bounds__(256) void k_head_fwd(const uint16_t *d1, const floa
     out[p] = d > 0.0f ? d + kCorrScale * s : 0.0f;
 }
 
-// masked L1: count, then gradient and sum, then the mean
-__global__ __launch_bounds__(256) void k_loss_count(const float *dm, const float *target, int n, unsigned *cnt)
+// masked L1 in four fixed-order steps (no atomics; the same sums every run):
+// per-workgroup valid counts, their total, per-workgroup |out - target| sums
+// with the gradient, then the mean
+__global__ __launch_bounds__(256) void k_loss_count(const float *dm, const float *target, int n, unsigned *part)
 {
-    __shared__ unsigned c;
-    if (threadIdx.x == 0) c = 0u;
-    __syncthreads();
     const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p < n && dm[p] > 0.0f && target[p] > 0.0f) atomicAdd(&c, 1u);
+    const int c = __syncthreads_count(p < n && dm[p] > 0.0f && target[p] > 0.0f);
+    if (threadIdx.x == 0) part[blockIdx.x] = (unsigned)c;
+}
+
+__global__ __launch_bounds__(256) void k_loss_total(const unsigned *part, int nwg, unsigned *cnt)
+{
+    __shared__ unsigned red[256];
+    unsigned c = 0u;
+    for (int i = (int)threadIdx.x; i < nwg; i += 256) c += part[i];
+    red[threadIdx.x] = c;
     __syncthreads();
-    if (threadIdx.x == 0 && c) atomicAdd(cnt, c);
+    for (int m = 128; m > 0; m >>= 1) {
+        if ((int)threadIdx.x < m) red[threadIdx.x] += red[threadIdx.x + m];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cnt[0] = red[0];
 }
 
 __global__ __launch_bounds__(256) void k_loss_grad(const float *out, const float *dm, const float *target, int n,
-                                                   const unsigned *cnt, float *ddelta, float *sum)
+                                                   const unsigned *cnt, float *ddelta, float *part)
 {
-    __shared__ float s;
-    if (threadIdx.x == 0) s = 0.0f;
-    __syncthreads();
+    __shared__ float red[4];
     const int p = blockIdx.x * 256 + threadIdx.x;
     const float inv_n = *cnt ? 1.0f / (float)*cnt : 0.0f;
+    float a = 0.0f;
     if (p < n) {
         float g = 0.0f;
         if (dm[p] > 0.0f && target[p] > 0.0f) {
             const float diff = out[p] - target[p];
             g = diff > 0.0f ? inv_n : (diff < 0.0f ? -inv_n : 0.0f);
-            atomicAdd(&s, diff < 0.0f ? -diff : diff);
+            a = diff < 0.0f ? -diff : diff;
         }
         ddelta[p] = kCorrScale * g;
     }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) a += __shfl_xor(a, m);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
     __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(sum, s);
+    if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ void k_loss_final(unsigned *cnt, float *sum, float *loss)
+__global__ __launch_bounds__(256) void k_loss_final(const float *part, int nwg, const unsigned *cnt, float *loss)
 {
-    loss[0] = *cnt ? sum[0] / (float)*cnt : 0.0f;
-    loss[1] = (float)*cnt;
-    *cnt = 0u;
-    sum[0] = 0.0f;
+    __shared__ float red[256];
+    float s = 0.0f;
+    for (int i = (int)threadIdx.x; i < nwg; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int m = 128; m > 0; m >>= 1) {
+        if ((int)threadIdx.x < m) red[threadIdx.x] += red[threadIdx.x + m];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        loss[0] = *cnt ? red[0] / (float)*cnt : 0.0f;
+        loss[1] = (float)*cnt;
+    }
 }
 
 // gradient at d1 through the head: g[p][c] = sum_tap ddelta[p - tap + 1] w[tap][c], relu mask of d1
@@ -968,15 +991,19 @@ hipError_t launch_head_fwd(const uint16_t *d1, const float *w, const float *b, c
     return hipGetLastError();
 }
 
-// scratch: [0] count (uint32), [1] sum; loss: [0] mean, [1] count
+// scratch: [0] the valid count (uint32), then loss_scratch_words(n_pix) - 4
+// words of per-workgroup counts and sums; loss: [0] mean, [1] count
 hipError_t launch_loss(const float *out, const float *dm, const float *target, int n_pix, float *ddelta,
                        float *scratch, float *loss, hipStream_t s)
 {
+    const int nwg = (n_pix + 255) / 256;
     unsigned *cnt = reinterpret_cast<unsigned *>(scratch);
-    hipLaunchKernelGGL(k_loss_count, grid1(n_pix, 256), dim3(256), 0, s, dm, target, n_pix, cnt);
-    hipLaunchKernelGGL(k_loss_grad, grid1(n_pix, 256), dim3(256), 0, s, out, dm, target, n_pix, cnt, ddelta,
-                       scratch + 1);
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1), 0, s, cnt, scratch + 1, loss);
+    unsigned *pc = cnt + 4;
+    float *ps = scratch + 4 + nwg;
+    hipLaunchKernelGGL(k_loss_count, dim3(nwg), dim3(256), 0, s, dm, target, n_pix, pc);
+    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, s, pc, nwg, cnt);
+    hipLaunchKernelGGL(k_loss_grad, dim3(nwg), dim3(256), 0, s, out, dm, target, n_pix, cnt, ddelta, ps);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, ps, nwg, cnt, loss);
     return hipGetLastError();
 }
 
