@@ -45,7 +45,7 @@ Net make_net()
             // upsampled layers: the forward reads parity-folded 2x2 weights
             go += L.up ? 4 * L.cout * 4 * L.cinp : L.cout * L.kp;
             L.t_off = l > 0 ? to : -1;
-            if (l > 0) to += L.cinp * 9 * L.cout;
+            if (l > 0) to += L.cinp * (L.up ? 16 : 9) * L.cout;   // up layers: folded, [ci][par][a][b][co]
         } else {
             L.g_off = L.t_off = -1;
         }

@@ -9,7 +9,10 @@
 // W[cout][3][3][cin] then b[cout], layers in forward order) and packed to
 // bf16 GEMM operands: G[cout][KP] with k = tap * CINP + ci (KP = 9 CINP
 // rounded up to 32) for the forward pass, T[cin][9 cout] with k = tap * cout
-// + co for the backward-data pass.
+// + co for the backward-data pass.  A layer that reads the 2x upsampled
+// source instead packs its taps folded by output parity (the sum of the taps
+// that land on each 2x2 source offset): G[4 parities][cout][4 CINP] and
+// T[cin][16 cout].
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -40,8 +43,9 @@ struct LayerDesc {
     int skip;                           // activation index added before the relu (-1 none)
     int w_off, b_off;                   // fp32 parameter offsets
     int kp;                             // forward GEMM K (padded)
-    int g_off, t_off;                   // bf16 packed-weight offsets (elements); g of an up layer is
-                                        // parity-folded: [4 parities][cout][4 source taps x cinp]
+    int g_off, t_off;                   // bf16 packed-weight offsets (elements); an up layer's are
+                                        // parity-folded: [4 parities][cout][4 offsets x cinp] and
+                                        // [cinp][4 parities x 4 offsets x cout]
     int scale;                          // output resolution divisor (1, 2, 4, 8)
 };
 

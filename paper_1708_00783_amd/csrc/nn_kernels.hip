@@ -2,16 +2,19 @@
 //
 // The 3x3 convolutions are implicit GEMMs on the bf16 matrix cores
 // (v_mfma_f32_16x16x32_bf16, fp32 accumulation):
-//   k_conv_fwd       M = output pixels, N = cout, K = (tap, ci); the operand
-//                    gather applies the stride and the nearest upsampling of
-//                    the decoder; bias, skip add and relu fused on the way out
-//   k_conv_bwd_data  M = input pixels, N = cin, K = (tap, co) -- stride-2
-//                    taps of the wrong parity read zero, and for an upsampled
-//                    input the four children of a source pixel are summed as
-//                    four more K blocks; skip gradient and relu mask fused
-//   k_conv_wgrad     M = cout, N = cin of one tap, K = pixels of one chunk:
-//                    both operands are staged transposed in LDS; per-chunk
-//                    partial sums are reduced in a fixed order
+//   k_conv_fwd          encoder: M = output pixels, N = cout, K = (tap, ci);
+//                       the operand gather applies the stride
+//   k_conv_fwd_up       decoder (nearest 2x upsampling, then 3x3): per output
+//                       parity a 2x2 convolution of the source on folded
+//                       weights, K = (source offset, ci)
+//   k_conv_bwd_data_s2  stride-2 layers: M = input pixels, N = cin, K = the
+//                       taps that reach the input pixel's parity x co
+//   k_conv_bwd_data_up  decoder: the adjoint of the folded forward, K = 16 co
+//   k_conv_wgrad        M = cout, N = cin of one tap, K = pixels of one chunk:
+//                       both operands are staged transposed in LDS; per-chunk
+//                       partial sums are reduced in a fixed order
+// Bias, skip add / skip gradient and relu (mask) are fused into every
+// epilogue, which is staged in LDS and written as 16-byte pixel vectors.
 // The 32->1 head, the loss, input packing and Adam are plain VALU kernels.
 //
 // MFMA 16x16x32 operand layout (per lane l of the wave): A row l%16, k
@@ -197,11 +200,8 @@ __device__ __forceinline__ void pack_t(const float *w, int cin, int cout, int i,
 // bf16-rounded weights of the taps that land there (ascending ky, kx),
 // rounded to bf16.  Zero padding agrees: a source row is outside the image
 // exactly when every tap landing on it is.
-__device__ __forceinline__ void pack_up(const float *w, int cin, int cinp, int cout, int i, uint16_t *gu)
+__device__ __forceinline__ uint16_t folded_weight(const float *w, int cin, int par, int co, int q, int ci)
 {
-    const int k4 = 4 * cinp;
-    const int par = i / (cout * k4), rem = i - par * cout * k4;
-    const int co = rem / k4, k = rem - co * k4, q = k / cinp, ci = k - (k / cinp) * cinp;
     const int py = par >> 1, px = par & 1, a = q >> 1, b = q & 1;
     float s = 0.0f;
     if (ci < cin)
@@ -212,7 +212,23 @@ __device__ __forceinline__ void pack_up(const float *w, int cin, int cinp, int c
                 s += bf2f(f2bf(w[(co * 9 + ky * 3 + kx) * cin + ci]));
             }
         }
-    gu[i] = f2bf(s);
+    return f2bf(s);
+}
+
+// forward operand gu[par][co][q * cinp + ci], q = a * 2 + b
+__device__ __forceinline__ void pack_up(const float *w, int cin, int cinp, int cout, int i, uint16_t *gu)
+{
+    const int k4 = 4 * cinp;
+    const int par = i / (cout * k4), rem = i - par * cout * k4;
+    const int co = rem / k4, k = rem - co * k4, q = k / cinp, ci = k - (k / cinp) * cinp;
+    gu[i] = folded_weight(w, cin, par, co, q, ci);
+}
+
+// backward-data operand of the same folded weights: tu[ci][(par * 4 + q) * cout + co]
+__device__ __forceinline__ void pack_tu(const float *w, int cin, int cout, int i, uint16_t *tu)
+{
+    const int ci = i / (16 * cout), rem = i - ci * 16 * cout, pq = rem / cout, co = rem - (rem / cout) * cout;
+    tu[i] = folded_weight(w, cin, pq >> 2, co, pq & 3, ci);
 }
 
 // every conv layer's packed weights in one launch: thread i belongs to the
@@ -231,7 +247,12 @@ __global__ __launch_bounds__(256) void k_pack(PackJobs J)
         else
             pack_g(p.w, p.cin, p.cinp, p.kp, li, p.g);
     }
-    if (p.t && li < p.n_t) pack_t(p.w, p.cin, p.cout, li, p.t);
+    if (p.t && li < p.n_t) {
+        if (p.up)
+            pack_tu(p.w, p.cin, p.cout, li, p.t);
+        else
+            pack_t(p.w, p.cin, p.cout, li, p.t);
+    }
 }
 
 // forward of an upsampled layer on the parity-folded weights: a wave takes
@@ -306,7 +327,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_up(const uint16_t *in, int Hs,
 // output channels (T row tiles share every weight fragment it loads; the NS
 // waves of a pixel group sit in one workgroup and share its input loads in L1)
 // ============================================================================
-template <int CINP, int COUT, int STRIDE, bool UP, bool SKIP, int T, int NS>
+template <int CINP, int COUT, int STRIDE, bool SKIP, int T, int NS>
 __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, int Ws, const uint16_t *g,
                                                   const float *bias, const uint16_t *skip, uint16_t *out, int N,
                                                   int Ho, int Wo)
@@ -320,7 +341,6 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, in
     const int cbase = (wid % NS) * (COUT / NS);
     const long p0 = (long)(wid / NS) * (16 * T);   // waves past P load nothing and store nothing
     const int r = lane & 15, gq = lane >> 4;
-    const int Hc = UP ? 2 * Hs : Hs, Wc = UP ? 2 * Ws : Ws;   // conv input size
     int pn[T], py[T], px[T];
     bool pv[T];
 #pragma unroll
@@ -348,10 +368,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, in
         for (int t = 0; t < T; ++t) {
             const int iy = STRIDE * py[t] + ky - 1, ix = STRIDE * px[t] + kx - 1;
             u32x4 v = {0u, 0u, 0u, 0u};
-            if (tap < 9 && pv[t] && iy >= 0 && iy < Hc && ix >= 0 && ix < Wc) {
-                const int sy = UP ? (iy >> 1) : iy, sx = UP ? (ix >> 1) : ix;
-                v = ld16(in + (((size_t)pn[t] * Hs + sy) * Ws + sx) * CINP + ci);
-            }
+            if (tap < 9 && pv[t] && iy >= 0 && iy < Hs && ix >= 0 && ix < Ws)
+                v = ld16(in + (((size_t)pn[t] * Hs + iy) * Ws + ix) * CINP + ci);
             a[t] = as_bf(v);
         }
 #pragma unroll
@@ -373,72 +391,66 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, in
 }
 
 // ============================================================================
-// backward data: gradient at the conv input (or, for an upsampled input, at
-// its source), then + skip gradient, then the source's relu mask
+// backward data: gradient at the conv input (the source, for an upsampled
+// input), then + skip gradient, then the source's relu mask
 // ============================================================================
-// A wave takes 32 pixels and CIN / NS of the input channels: NS waves of one
-// workgroup share a pixel group (its gradient operand loads hit L1), so layers
-// with few pixels still fill the chip.
-template <int CIN, int COUT, int STRIDE, bool UPSUM, bool SKIP, int NS>
-__global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t *gpre, int Ho, int Wo, const uint16_t *tw,
-                                                       const uint16_t *skipg, const uint16_t *act, uint16_t *gout,
-                                                       int N, int Hq, int Wq)
+// backward data of an upsampled layer: the adjoint of the parity-folded
+// forward.  Source pixel (m, n) collects, for each output parity (py, px)
+// and source offset (a, b), the output pixel (2 m' + py, 2 n' + px) with
+// m' = m + 1 - py - a, n' = n + 1 - px - b: K = 16 COUT instead of 4 x 9 COUT,
+// on the same folded bf16 weights as the forward.  Then the source's relu
+// mask.  A wave takes 32 source pixels and CIN / NS channels.
+template <int CIN, int COUT, int NS>
+__global__ __launch_bounds__(256) void k_conv_bwd_data_up(const uint16_t *gpre, const uint16_t *tu,
+                                                          const uint16_t *act, uint16_t *gout, int N, int Hs, int Ws)
 {
     static_assert(NS == 1 || NS == 2 || NS == 4, "channel split must divide the 4 waves of a workgroup");
-    constexpr int K9 = 9 * COUT;
-    constexpr int KT = (UPSUM ? 4 : 1) * K9;
+    static_assert(COUT % 32 == 0, "a K step is 32 output channels of one (parity, offset)");
+    constexpr int K16 = 16 * COUT;
     constexpr int NT = CIN / 16 / NS;
-    const int lane = (int)threadIdx.x & 63;
-    const long P = (long)N * Hq * Wq;
+    const int lane = (int)threadIdx.x & 63, r = lane & 15, gq = lane >> 4;
+    const long P = (long)N * Hs * Ws;
+    const int Ho = 2 * Hs, Wo = 2 * Ws;
     const int wid = (int)blockIdx.x * 4 + ((int)threadIdx.x >> 6);
     const int cbase = (wid % NS) * (CIN / NS);
     const long p0 = (long)(wid / NS) * 32;   // waves past P load nothing and store nothing
-    const int r = lane & 15, gq = lane >> 4;
-    int pn[2], py[2], px[2];
+    int pn[2], pm[2], pnn[2];
     bool pv[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         long p = p0 + t * 16 + r;
         pv[t] = p < P;
         if (!pv[t]) p = 0;
-        pn[t] = (int)(p / ((long)Hq * Wq));
-        const int rem = (int)(p - (long)pn[t] * Hq * Wq);
-        py[t] = rem / Wq;
-        px[t] = rem - py[t] * Wq;
+        pn[t] = (int)(p / ((long)Hs * Ws));
+        const int rem = (int)(p - (long)pn[t] * Hs * Ws);
+        pm[t] = rem / Ws;
+        pnn[t] = rem - pm[t] * Ws;
     }
     f32x4 acc[2][NT];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < KT; k0 += 32) {
-        const int k = k0 + gq * 8;
-        const int child = k / K9, rem = k - (k / K9) * K9;
-        const int tap = rem / COUT, co = rem - (rem / COUT) * COUT;
-        const int ky = tap / 3, kx = tap - (tap / 3) * 3;
-        bf16x8 a[2];
+    for (int pq = 0; pq < 16; ++pq) {
+        const int py = pq >> 3, px = (pq >> 2) & 1, a = (pq >> 1) & 1, b = pq & 1;
+#pragma unroll 2
+        for (int co0 = 0; co0 < COUT; co0 += 32) {
+            const int co = co0 + gq * 8;
+            bf16x8 av[2];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            // conv-input pixel, then the output pixel whose tap reads it
-            const int iy = UPSUM ? 2 * py[t] + (child >> 1) : py[t];
-            const int ix = UPSUM ? 2 * px[t] + (child & 1) : px[t];
-            int oy = iy - ky + 1, ox = ix - kx + 1;
-            bool ok = pv[t];
-            if (STRIDE == 2) {
-                ok = ok && !(oy & 1) && !(ox & 1);
-                oy >>= 1;
-                ox >>= 1;
+            for (int t = 0; t < 2; ++t) {
+                const int mo = pm[t] + 1 - py - a, no = pnn[t] + 1 - px - b;
+                u32x4 v = {0u, 0u, 0u, 0u};
+                if (pv[t] && mo >= 0 && mo < Hs && no >= 0 && no < Ws)
+                    v = ld16(gpre + (((size_t)pn[t] * Ho + 2 * mo + py) * Wo + 2 * no + px) * COUT + co);
+                av[t] = as_bf(v);
             }
-            ok = ok && oy >= 0 && oy < Ho && ox >= 0 && ox < Wo;
-            u32x4 v = {0u, 0u, 0u, 0u};
-            if (ok) v = ld16(gpre + (((size_t)pn[t] * Ho + oy) * Wo + ox) * COUT + co);
-            a[t] = as_bf(v);
-        }
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const bf16x8 b = as_bf(ld16(tw + (size_t)(cbase + j * 16 + r) * K9 + rem));
-            acc[0][j] = mfma(a[0], b, acc[0][j]);
-            acc[1][j] = mfma(a[1], b, acc[1][j]);
+            for (int j = 0; j < NT; ++j) {
+                const bf16x8 bv = as_bf(ld16(tu + (size_t)(cbase + j * 16 + r) * K16 + pq * COUT + co));
+                acc[0][j] = mfma(av[0], bv, acc[0][j]);
+                acc[1][j] = mfma(av[1], bv, acc[1][j]);
+            }
         }
     }
     __shared__ EpiTile<NT> st[4];
@@ -448,7 +460,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const uint16_t *gpre, int
             const long p = p0 + t * 16 + pix;
             if (p >= P) return;
             const size_t o = (size_t)p * CIN + cbase + c8;
-            bwd_store8<SKIP>(gout + o, lo, hi, SKIP ? skipg + o : nullptr, act + o);
+            bwd_store8<false>(gout + o, lo, hi, nullptr, act + o);
         });
 }
 
@@ -946,7 +958,7 @@ hipError_t launch_pack(const Net &net, const float *params, uint16_t *g, uint16_
         p.kp = L.kp;
         p.up = L.up;
         p.n_g = L.up ? 16 * L.cout * L.cinp : L.cout * L.kp;
-        p.n_t = p.t ? L.cinp * 9 * L.cout : 0;
+        p.n_t = p.t ? L.cinp * (L.up ? 16 : 9) * L.cout : 0;
         J.start[l] = at;
         at += p.n_g > p.n_t ? p.n_g : p.n_t;
     }
@@ -971,10 +983,10 @@ hipError_t launch_conv_fwd(int layer, const uint16_t *in, int Hs, int Ws, const 
     const dim3 g4 = grid1(P, 256), g2 = grid1(P, 128), g2s4 = grid1(P, 32), b(256);
     if (layer >= 4 && (Ho != 2 * Hs || Wo != 2 * Ws)) return hipErrorInvalidValue;
     switch (layer) {
-    case 0: hipLaunchKernelGGL((k_conv_fwd<8, 32, 1, false, false, 4, 1>), g4, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 1: hipLaunchKernelGGL((k_conv_fwd<32, 64, 2, false, false, 2, 1>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 2: hipLaunchKernelGGL((k_conv_fwd<64, 64, 2, false, false, 2, 1>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 3: hipLaunchKernelGGL((k_conv_fwd<64, 128, 2, false, false, 2, 4>), g2s4, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 0: hipLaunchKernelGGL((k_conv_fwd<8, 32, 1, false, 4, 1>), g4, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 1: hipLaunchKernelGGL((k_conv_fwd<32, 64, 2, false, 2, 1>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 2: hipLaunchKernelGGL((k_conv_fwd<64, 64, 2, false, 2, 1>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 3: hipLaunchKernelGGL((k_conv_fwd<64, 128, 2, false, 2, 4>), g2s4, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
     // upsampled layers: parity-folded weights, one wave per (source row, parity, column run)
     case 4: hipLaunchKernelGGL((k_conv_fwd_up<128, 64, true, 2, 2>), up_grid(N, Hs, Ws, 2, 2), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
     case 5: hipLaunchKernelGGL((k_conv_fwd_up<64, 64, true, 2, 1>), up_grid(N, Hs, Ws, 2, 1), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
@@ -1038,14 +1050,16 @@ hipError_t launch_conv_bwd_data(int layer, const uint16_t *gpre, int Ho, int Wo,
 {
     const long P = (long)N * Hq * Wq;
     const dim3 g1 = grid1(P, 128), g4 = grid1(P, 32), b(256);
+    if (layer >= 4 && (Ho != 2 * Hq || Wo != 2 * Wq)) return hipErrorInvalidValue;
     switch (layer) {
     // stride-2 layers: only the taps of each input parity
     case 1: hipLaunchKernelGGL((k_conv_bwd_data_s2<32, 64, true, 1>), s2_grid(N, Hq, Wq, 1), b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
     case 2: hipLaunchKernelGGL((k_conv_bwd_data_s2<64, 64, true, 1>), s2_grid(N, Hq, Wq, 1), b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
     case 3: hipLaunchKernelGGL((k_conv_bwd_data_s2<64, 128, true, 2>), s2_grid(N, Hq, Wq, 2), b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
-    case 4: hipLaunchKernelGGL((k_conv_bwd_data<128, 64, 1, true, false, 4>), g4, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
-    case 5: hipLaunchKernelGGL((k_conv_bwd_data<64, 64, 1, true, false, 1>), g1, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
-    case 6: hipLaunchKernelGGL((k_conv_bwd_data<64, 32, 1, true, false, 1>), g1, b, 0, s, gpre, Ho, Wo, t, skipg, act, gout, N, Hq, Wq); break;
+    // upsampled layers: the adjoint of the parity-folded forward (t holds the folded weights)
+    case 4: hipLaunchKernelGGL((k_conv_bwd_data_up<128, 64, 4>), g4, b, 0, s, gpre, t, act, gout, N, Hq, Wq); break;
+    case 5: hipLaunchKernelGGL((k_conv_bwd_data_up<64, 64, 1>), g1, b, 0, s, gpre, t, act, gout, N, Hq, Wq); break;
+    case 6: hipLaunchKernelGGL((k_conv_bwd_data_up<64, 32, 1>), g1, b, 0, s, gpre, t, act, gout, N, Hq, Wq); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

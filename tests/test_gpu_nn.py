@@ -2,8 +2,8 @@
 fp32 accumulation) against the oracle.
 
 Per layer, the oracle recomputes the GPU's result from the GPU's own bf16
-operands (inputs, bf16-rounded weights -- parity-folded for the forward of an
-upsampled layer --, upstream gradients) in float64, so
+operands (inputs, bf16-rounded weights -- parity-folded for the forward and
+the input gradient of an upsampled layer --, upstream gradients) in float64, so
 the only differences are accumulation order and the final bf16 rounding:
 outputs within 1 bf16 ulp-scale (0.8% relative plus a small absolute floor),
 weight gradients within 1e-3 relative.  End to end against the float64
@@ -19,7 +19,7 @@ import numpy as np
 import pytest
 
 from oracle import denoise as D
-from upfold import fold, folded_forward
+from upfold import fold, folded_backward_data, folded_forward
 
 pytestmark = pytest.mark.gpu
 
@@ -142,7 +142,9 @@ def test_backward_layers_match_oracle():
         if name == "e1":
             continue
         if up:
-            dx = D.up2_backward(dx)
+            # the kernel's operands: the folded weights of the forward (adjoint
+            # checked against conv_backward + up2_backward in test_upsample_fold)
+            dx = folded_backward_data(g, D.to_bf16(fold(wb, np.float32)).astype(np.float64))
         if src in skip_to:
             dx = dx + _bf(net, "grad_" + skip_to[src])
         _close(_bf(net, "grad_" + src), dx * (a > 0), "grad_" + src)

@@ -38,3 +38,21 @@ def folded_forward(x, f, bias):
                     acc += src @ f[py, px, :, a, b, :].astype(np.float64).T
             y[:, py::2, px::2] = acc
     return y
+
+
+def folded_backward_data(g, f):
+    """gradient at the (N, Hs, Ws, cin) source of folded_forward for the
+    upstream gradient g (N, 2 Hs, 2 Ws, cout): source pixel (m, n) collects
+    output (2 m' + py, 2 n' + px) with m' = m + 1 - py - a, n' = n + 1 - px - b"""
+    N, Ho, Wo, cout = g.shape
+    Hs, Ws = Ho // 2, Wo // 2
+    cin = f.shape[-1]
+    dx = np.zeros((N, Hs + 2, Ws + 2, cin))
+    for py in range(2):
+        for px in range(2):
+            gp = g[:, py::2, px::2]   # (N, Hs, Ws, cout) at m', n'
+            for a in range(2):
+                for b in range(2):
+                    # output m' feeds source m' + py - 1 + a (padded index + 1)
+                    dx[:, py + a:py + a + Hs, px + b:px + b + Ws] += gp @ f[py, px, :, a, b, :].astype(np.float64)
+    return dx[:, 1:-1, 1:-1]
