@@ -95,8 +95,12 @@ bool nlayout(const Net &net, uint32_t B, uint32_t H, uint32_t W, int training, N
         L.v = take(4 * (size_t)net.n_params);
         size_t mx = 0;
         for (int l = 0; l < kLayers - 1; ++l) {
-            const size_t P = (size_t)B * (H / net.L[l].scale) * (W / net.L[l].scale);
-            const size_t e = (size_t)wgrad_chunks((long)P) * ((size_t)net.L[l].cout * 9 * net.L[l].cinp + net.L[l].cout);
+            // the decoder layers reduce 16 (parity, offset) taps over the source grid, 4 bias partials
+            const LayerDesc &Ll = net.L[l];
+            const size_t P = Ll.up ? (size_t)B * (H / (2 * Ll.scale)) * (W / (2 * Ll.scale))
+                                   : (size_t)B * (H / Ll.scale) * (W / Ll.scale);
+            const size_t e = (size_t)wgrad_chunks((long)P, Ll.up ? kWgradFoldChunkPix : kWgradChunkPix) *
+                             ((size_t)Ll.cout * (Ll.up ? 16 : 9) * Ll.cinp + (Ll.up ? 4 : 1) * Ll.cout);
             if (e > mx) mx = e;
         }
         L.partial = take(4 * mx);
@@ -272,7 +276,8 @@ int tf_nn_backward(tf_nn *nn, const float *d_target, float *d_loss, tf_stream st
         const int ss = act_scale(L.src);
         const int Hs = H / ss, Ws = W / ss, Ho = H / L.scale, Wo = W / L.scale;
         uint16_t *gpre = nn->grad[l + 1];
-        e = launch_conv_wgrad(l, gpre, nn->act[L.src], Hs, Ws, N, Ho, Wo, nn->partial, wgrad_chunks((long)N * Ho * Wo),
+        e = launch_conv_wgrad(l, gpre, nn->act[L.src], Hs, Ws, N, Ho, Wo, nn->partial,
+                              L.up ? wgrad_chunks((long)N * Hs * Ws, kWgradFoldChunkPix) : wgrad_chunks((long)N * Ho * Wo),
                               nn->grads + L.w_off, nn->grads + L.b_off, s);
         if (e == hipSuccess && l > 0)
             e = launch_conv_bwd_data(l, gpre, Ho, Wo, nn->t + L.t_off,

@@ -28,10 +28,12 @@ constexpr float kCorrScale = 0.05f;     // metres: unit of the head's depth corr
 constexpr int kWgradStep = 64;          // pixels per LDS staging round of the conv weight gradient
 constexpr int kWgradChunkPix = 512;     // target pixels per chunk of a conv weight-gradient reduction
 
-// pixel chunks of a conv weight-gradient reduction over P output pixels
-inline int wgrad_chunks(long P)
+constexpr int kWgradFoldChunkPix = 2048; // the same for the folded decoder layers (16 taps per chunk)
+
+// pixel chunks of a conv weight-gradient reduction over P pixels
+inline int wgrad_chunks(long P, int pix_per_chunk = kWgradChunkPix)
 {
-    const long c = P / kWgradChunkPix;
+    const long c = P / pix_per_chunk;
     return (int)(c < 64 ? 64 : (c > 512 ? 512 : c));
 }
 

@@ -542,12 +542,14 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data_s2(const uint16_t *gpre, 
 // partial[chunk][co][tap][ci] = sum_p gpre[p][co] * in_tap(p)[ci]; the bias
 // gradient partial[chunk][co] comes from the tap-0 workgroups
 // ============================================================================
-template <int CINP, int COUT, int STRIDE, bool UP>
+template <int CINP, int COUT, int STRIDE, bool UP, bool FOLD>
 __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *gpre, const uint16_t *in, int Hs, int Ws, int N,
                                                     int Ho, int Wo, float *partial, float *partial_b, int chunk_pix,
                                                     int nchunk)
 {
+    static_assert(!FOLD || (UP && STRIDE == 1), "the parity fold is for upsampled stride-1 layers");
     constexpr int CT = CINP < 16 ? 16 : CINP;
+    constexpr int NTAP = FOLD ? 16 : 9;   // taps, or (output parity, source offset) pairs
     constexpr int MT = COUT / 16, NTT = CT / 16, TILES = MT * NTT, TPW = (TILES + 3) / 4;
     constexpr int KS = kWgradStep;   // pixels staged per round (4 MFMA k-steps)
     constexpr int LD = KS + 8;       // LDS row pitch in bf16 elements (16-byte aligned rows)
@@ -561,13 +563,17 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *gpre, const 
     __shared__ uint16_t gT[COUT][LD];
     __shared__ uint16_t iT[CT][LD];
     // workgroups are dealt to the 8 XCDs round-robin by their linear index:
-    // the 9 taps of a chunk get indices of one residue mod 8, so they run on
-    // one XCD and read the chunk's gradient and input through the same L2
+    // the NTAP taps of a chunk get indices of one residue mod 8, so they run
+    // on one XCD and read the chunk's gradient and input through the same L2
     const int id = (int)blockIdx.x, slot = id >> 3;
-    const int chunk = (id & 7) + 8 * (slot / 9), tap = slot - (slot / 9) * 9;
+    const int chunk = (id & 7) + 8 * (slot / NTAP), tap = slot - (slot / NTAP) * NTAP;
     if (chunk >= nchunk) return;
     const int ky = tap / 3, kx = tap - (tap / 3) * 3;
-    const long P = (long)N * Ho * Wo;
+    // FOLD: tap = (py * 2 + px) * 4 + a * 2 + b; the pixels are the source
+    // grid (m, n), read at output (2m + py, 2n + px) and source
+    // (m + py - 1 + a, n + px - 1 + b)
+    const int fpy = tap >> 3, fpx = (tap >> 2) & 1, fa = (tap >> 1) & 1, fb = tap & 1;
+    const long P = FOLD ? (long)N * Hs * Ws : (long)N * Ho * Wo;
     const long c0 = (long)chunk * chunk_pix;
     const long c1 = c0 + chunk_pix < P ? c0 + chunk_pix : P;
     const int w = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63, r = lane & 15, gq = lane >> 4;
@@ -584,7 +590,16 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *gpre, const 
             const int pi = v / (COUT / 8), cv = (v - pi * (COUT / 8)) * 8;
             const long p = pb + pi;
             gv[q] = u32x4{0u, 0u, 0u, 0u};
-            if (v < GV && p < c1) gv[q] = ld16(gpre + (size_t)p * COUT + cv);
+            if (v < GV && p < c1) {
+                size_t po = (size_t)p;
+                if (FOLD) {
+                    const int n = (int)(p / ((long)Hs * Ws));
+                    const int rem = (int)(p - (long)n * Hs * Ws);
+                    const int m = rem / Ws, nn = rem - (rem / Ws) * Ws;
+                    po = ((size_t)n * Ho + 2 * m + fpy) * Wo + 2 * nn + fpx;
+                }
+                gv[q] = ld16(gpre + po * COUT + cv);
+            }
         }
 #pragma unroll
         for (int q = 0; q < (IV + 255) / 256; ++q) {
@@ -592,7 +607,14 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *gpre, const 
             const int pi = v / (CT / 8), cv = (v - pi * (CT / 8)) * 8;
             const long p = pb + pi;
             iv[q] = u32x4{0u, 0u, 0u, 0u};
-            if (v < IV && p < c1 && cv < CINP) {
+            if (FOLD && v < IV && p < c1 && cv < CINP) {
+                const int n = (int)(p / ((long)Hs * Ws));
+                const int rem = (int)(p - (long)n * Hs * Ws);
+                const int m = rem / Ws, nn = rem - (rem / Ws) * Ws;
+                const int sy = m + fpy - 1 + fa, sx = nn + fpx - 1 + fb;
+                if (sy >= 0 && sy < Hs && sx >= 0 && sx < Ws)
+                    iv[q] = ld16(in + (((size_t)n * Hs + sy) * Ws + sx) * CINP + cv);
+            } else if (!FOLD && v < IV && p < c1 && cv < CINP) {
                 const int n = (int)(p / ((long)Ho * Wo));
                 const int rem = (int)(p - (long)n * Ho * Wo);
                 const int oy = rem / Wo, ox = rem - (rem / Wo) * Wo;
@@ -620,7 +642,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *gpre, const 
                 for (int e = 0; e < 8; ++e) iT[cv + e][pi ^ swz(cv + e)] = (uint16_t)(iv[q][e >> 1] >> (16 * (e & 1)));
         }
         __syncthreads();
-        if (tap == 0 && (int)threadIdx.x < COUT)
+        if ((FOLD ? (tap & 3) : tap) == 0 && (int)threadIdx.x < COUT)
             for (int k = 0; k < KS; ++k) bpart += bf2f(gT[threadIdx.x][k ^ swz((int)threadIdx.x)]);
 #pragma unroll
         for (int kk = 0; kk < KS; kk += 32)
@@ -646,16 +668,20 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *gpre, const 
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int co = mt * 16 + gq * 4 + i;
-            partial[(((size_t)chunk * COUT + co) * 9 + tap) * CINP + ci] = acc[j][i];
+            partial[(((size_t)chunk * COUT + co) * NTAP + tap) * CINP + ci] = acc[j][i];
         }
     }
-    if (tap == 0 && (int)threadIdx.x < COUT) partial_b[(size_t)chunk * COUT + threadIdx.x] = bpart;
+    // bias partials: one per chunk, or one per chunk and output parity (FOLD)
+    if (FOLD && (tap & 3) == 0 && (int)threadIdx.x < COUT)
+        partial_b[((size_t)chunk * 4 + (tap >> 2)) * COUT + threadIdx.x] = bpart;
+    if (!FOLD && tap == 0 && (int)threadIdx.x < COUT) partial_b[(size_t)chunk * COUT + threadIdx.x] = bpart;
 }
 
 // fixed-order sum of the chunk partials into the fp32 gradient vector: a
 // workgroup takes 64 consecutive partial entries j (weights with the padded
 // input channels, then the biases); wave sl sums chunks sl, sl + 4, ... with
 // eight loads in flight per lane, and the four wave sums are added in LDS
+template <bool FOLD>
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float *partial, const float *partial_b, int chunks,
                                                       int cout, int cin, int cinp, float *dw, float *db)
 {
@@ -664,7 +690,7 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float *partial, cons
     const int j = (int)blockIdx.x * 64 + ((int)threadIdx.x & 63), sl = (int)threadIdx.x >> 6;
     const bool isw = j < nw, valid = j < nw + cout;
     float s = 0.0f;
-    if (valid) {
+    if (valid && !FOLD) {
         const float *src = isw ? partial + j : partial_b + (j - nw);
         const size_t stride = isw ? (size_t)nw : (size_t)cout;
         float a[8];
@@ -676,6 +702,44 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float *partial, cons
             for (int k = 0; k < 8; ++k) a[k] += src[(size_t)(c + 4 * k) * stride];
         for (; c < chunks; c += 4) a[0] += src[(size_t)c * stride];
         s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    } else if (valid) {
+        // FOLD: partial[chunk][co][16][cinp] over (output parity, source
+        // offset); tap (ky, kx) of parity (py, px) sits at offset
+        // a = floor((py + ky - 1) / 2) + 1 - py, likewise b; bias partials
+        // [chunk][4 parities][cout]
+        int off[4];
+        size_t stride;
+        const float *src;
+        if (isw) {
+            const int co = j / (9 * cinp), rem = j - co * 9 * cinp, tap = rem / cinp, ci = rem - (rem / cinp) * cinp;
+            const int ky = tap / 3, kx = tap - (tap / 3) * 3;
+#pragma unroll
+            for (int par = 0; par < 4; ++par) {
+                const int py = par >> 1, px = par & 1;
+                const int fa = ((py + ky - 1) >> 1) + 1 - py, fb = ((px + kx - 1) >> 1) + 1 - px;
+                off[par] = ((co * 16 + par * 4 + fa * 2 + fb) * cinp) + ci;
+            }
+            src = partial;
+            stride = (size_t)cout * 16 * cinp;
+        } else {
+#pragma unroll
+            for (int par = 0; par < 4; ++par) off[par] = par * cout + (j - nw);
+            src = partial_b;
+            stride = (size_t)4 * cout;
+        }
+        float a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        int c = sl;
+        for (; c + 12 < chunks; c += 16)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float *q = src + (size_t)(c + 4 * k) * stride;
+                a[k] += (q[off[0]] + q[off[1]]) + (q[off[2]] + q[off[3]]);
+            }
+        for (; c < chunks; c += 4) {
+            const float *q = src + (size_t)c * stride;
+            a[0] += (q[off[0]] + q[off[1]]) + (q[off[2]] + q[off[3]]);
+        }
+        s = (a[0] + a[1]) + (a[2] + a[3]);
     }
     red[sl][threadIdx.x & 63] = s;
     __syncthreads();
@@ -1068,34 +1132,42 @@ hipError_t launch_conv_bwd_data(int layer, const uint16_t *gpre, int Ho, int Wo,
 hipError_t launch_conv_wgrad(int layer, const uint16_t *gpre, const uint16_t *in, int Hs, int Ws, int N, int Ho,
                              int Wo, float *partial, int chunks, float *dw, float *db, hipStream_t s)
 {
-    const long P = (long)N * Ho * Wo;
+    // the decoder layers (4-6) run folded: 16 (parity, offset) taps over the source grid
+    const bool fold = layer >= 4;
+    const int ntap = fold ? 16 : 9;
+    const long P = fold ? (long)N * Hs * Ws : (long)N * Ho * Wo;
+    if (fold && (Ho != 2 * Hs || Wo != 2 * Ws)) return hipErrorInvalidValue;
     int per = (int)((P + chunks - 1) / chunks);
     per = ((per + kWgradStep - 1) / kWgradStep) * kWgradStep;
     const int nc = (int)((P + per - 1) / per);
     float *pb = partial;   // bias partials after the weight partials
-    const dim3 gr(9 * ((nc + 7) / 8) * 8), b(256);   // (tap, chunk) pairs, chunks padded to a multiple of 8
+    const dim3 gr(ntap * ((nc + 7) / 8) * 8), b(256);   // (tap, chunk) pairs, chunks padded to a multiple of 8
     int cout = 0, cin = 0, cinp = 0;
     switch (layer) {
     case 0: cout = 32; cin = 3; cinp = 8; pb += (size_t)nc * 32 * 9 * 8;
-        hipLaunchKernelGGL((k_conv_wgrad<8, 32, 1, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
+        hipLaunchKernelGGL((k_conv_wgrad<8, 32, 1, false, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
     case 1: cout = 64; cin = cinp = 32; pb += (size_t)nc * 64 * 9 * 32;
-        hipLaunchKernelGGL((k_conv_wgrad<32, 64, 2, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
+        hipLaunchKernelGGL((k_conv_wgrad<32, 64, 2, false, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
     case 2: cout = 64; cin = cinp = 64; pb += (size_t)nc * 64 * 9 * 64;
-        hipLaunchKernelGGL((k_conv_wgrad<64, 64, 2, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
+        hipLaunchKernelGGL((k_conv_wgrad<64, 64, 2, false, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
     case 3: cout = 128; cin = cinp = 64; pb += (size_t)nc * 128 * 9 * 64;
-        hipLaunchKernelGGL((k_conv_wgrad<64, 128, 2, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
-    case 4: cout = 64; cin = cinp = 128; pb += (size_t)nc * 64 * 9 * 128;
-        hipLaunchKernelGGL((k_conv_wgrad<128, 64, 1, true>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
-    case 5: cout = 64; cin = cinp = 64; pb += (size_t)nc * 64 * 9 * 64;
-        hipLaunchKernelGGL((k_conv_wgrad<64, 64, 1, true>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
-    case 6: cout = 32; cin = cinp = 64; pb += (size_t)nc * 32 * 9 * 64;
-        hipLaunchKernelGGL((k_conv_wgrad<64, 32, 1, true>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
+        hipLaunchKernelGGL((k_conv_wgrad<64, 128, 2, false, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
+    case 4: cout = 64; cin = cinp = 128; pb += (size_t)nc * 64 * 16 * 128;
+        hipLaunchKernelGGL((k_conv_wgrad<128, 64, 1, true, true>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
+    case 5: cout = 64; cin = cinp = 64; pb += (size_t)nc * 64 * 16 * 64;
+        hipLaunchKernelGGL((k_conv_wgrad<64, 64, 1, true, true>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
+    case 6: cout = 32; cin = cinp = 64; pb += (size_t)nc * 32 * 16 * 64;
+        hipLaunchKernelGGL((k_conv_wgrad<64, 32, 1, true, true>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
     default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_wgrad_reduce, grid1((long)cout * 9 * cinp + cout, 64), dim3(256), 0, s, partial, pb, nc,
-                       cout, cin, cinp, dw, db);
+    if (fold)
+        hipLaunchKernelGGL(k_wgrad_reduce<true>, grid1((long)cout * 9 * cinp + cout, 64), dim3(256), 0, s, partial, pb,
+                           nc, cout, cin, cinp, dw, db);
+    else
+        hipLaunchKernelGGL(k_wgrad_reduce<false>, grid1((long)cout * 9 * cinp + cout, 64), dim3(256), 0, s, partial, pb,
+                           nc, cout, cin, cinp, dw, db);
     return hipGetLastError();
 }
 
