@@ -677,6 +677,108 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *gpre, const 
     if (!FOLD && tap == 0 && (int)threadIdx.x < COUT) partial_b[(size_t)chunk * COUT + threadIdx.x] = bpart;
 }
 
+// weight gradient of the first layer (8 padded input channels, stride 1):
+// all 9 taps in one workgroup as the N rows tap * 8 + ci (72 rows, padded to
+// 80 with zeros), so the gradient operand is staged once per chunk instead of
+// once per tap; same partial layout as k_conv_wgrad ([chunk][co][tap][ci])
+template <int COUT>
+__global__ __launch_bounds__(256) void k_conv_wgrad_c8(const uint16_t *gpre, const uint16_t *in, int H, int W, int N,
+                                                       float *partial, float *partial_b, int chunk_pix, int nchunk)
+{
+    constexpr int KS = kWgradStep;
+    constexpr int LD = KS + 8;
+    constexpr int NR = 80;   // 72 (tap, ci) rows + 8 zero rows
+    constexpr int MT = COUT / 16, NTT = NR / 16, TILES = MT * NTT, TPW = (TILES + 3) / 4;
+    constexpr int GV = KS * (COUT / 8), IV = KS * 9;   // 16-byte vectors staged per round
+    static_assert(KS == 64, "one staging vector per (tap, pixel): pixel = v % 64");
+    auto swz = [](int row) { return ((row >> 3) & 7) << 3; };
+    __shared__ uint16_t gT[COUT][LD];
+    __shared__ uint16_t iT[NR][LD];
+    const int chunk = (int)blockIdx.x;
+    if (chunk >= nchunk) return;
+    const long P = (long)N * H * W;
+    const long c0 = (long)chunk * chunk_pix;
+    const long c1 = c0 + chunk_pix < P ? c0 + chunk_pix : P;
+    const int w = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63, r = lane & 15, gq = lane >> 4;
+    for (int i = (int)threadIdx.x; i < 8 * LD; i += 256) iT[72 + i / LD][i % LD] = 0;
+    f32x4 acc[TPW];
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bpart = 0.0f;
+    for (long pb = c0; pb < c1; pb += KS) {
+        u32x4 gv[(GV + 255) / 256], iv[(IV + 255) / 256];
+#pragma unroll
+        for (int q = 0; q < (GV + 255) / 256; ++q) {
+            const int v = (int)threadIdx.x + 256 * q;
+            const int pi = v / (COUT / 8), cv = (v - pi * (COUT / 8)) * 8;
+            const long p = pb + pi;
+            gv[q] = u32x4{0u, 0u, 0u, 0u};
+            if (v < GV && p < c1) gv[q] = ld16(gpre + (size_t)p * COUT + cv);
+        }
+#pragma unroll
+        for (int q = 0; q < (IV + 255) / 256; ++q) {
+            const int v = (int)threadIdx.x + 256 * q;
+            const int tap = v / KS, pi = v - (v / KS) * KS;
+            const long p = pb + pi;
+            iv[q] = u32x4{0u, 0u, 0u, 0u};
+            if (v < IV && p < c1) {
+                const int n = (int)(p / ((long)H * W));
+                const int rem = (int)(p - (long)n * H * W);
+                const int y = rem / W, x = rem - (rem / W) * W;
+                const int iy = y + tap / 3 - 1, ix = x + tap % 3 - 1;
+                if (iy >= 0 && iy < H && ix >= 0 && ix < W) iv[q] = ld16(in + (((size_t)n * H + iy) * W + ix) * 8);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < (GV + 255) / 256; ++q) {
+            const int v = (int)threadIdx.x + 256 * q;
+            const int pi = v / (COUT / 8), cv = (v - pi * (COUT / 8)) * 8;
+            if (v < GV)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) gT[cv + e][pi ^ swz(cv + e)] = (uint16_t)(gv[q][e >> 1] >> (16 * (e & 1)));
+        }
+#pragma unroll
+        for (int q = 0; q < (IV + 255) / 256; ++q) {
+            const int v = (int)threadIdx.x + 256 * q;
+            const int tap = v / KS, pi = v - (v / KS) * KS;
+            if (v < IV)
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    iT[tap * 8 + e][pi ^ swz(tap * 8 + e)] = (uint16_t)(iv[q][e >> 1] >> (16 * (e & 1)));
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < COUT)
+            for (int k = 0; k < KS; ++k) bpart += bf2f(gT[threadIdx.x][k ^ swz((int)threadIdx.x)]);
+#pragma unroll
+        for (int kk = 0; kk < KS; kk += 32)
+#pragma unroll
+            for (int j = 0; j < TPW; ++j) {
+                const int tile = w * TPW + j;
+                if (tile < TILES) {
+                    const int mt = tile / NTT, nt = tile - (tile / NTT) * NTT;
+                    const bf16x8 a = as_bf(*reinterpret_cast<const u32x4 *>(&gT[mt * 16 + r][(kk + gq * 8) ^ swz(mt * 16 + r)]));
+                    const bf16x8 b = as_bf(*reinterpret_cast<const u32x4 *>(&iT[nt * 16 + r][(kk + gq * 8) ^ swz(nt * 16 + r)]));
+                    acc[j] = mfma(a, b, acc[j]);
+                }
+            }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+        const int tile = w * TPW + j;
+        if (tile >= TILES) continue;
+        const int mt = tile / NTT, nt = tile - (tile / NTT) * NTT;
+        const int row = nt * 16 + r;   // tap * 8 + ci
+        if (row >= 72) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int co = mt * 16 + gq * 4 + i;
+            partial[((size_t)chunk * COUT + co) * 72 + row] = acc[j][i];
+        }
+    }
+    if ((int)threadIdx.x < COUT) partial_b[(size_t)chunk * COUT + threadIdx.x] = bpart;
+}
+
 // fixed-order sum of the chunk partials into the fp32 gradient vector: a
 // workgroup takes 64 consecutive partial entries j (weights with the padded
 // input channels, then the biases); wave sl sums chunks sl, sl + 4, ... with
@@ -1144,8 +1246,8 @@ hipError_t launch_conv_wgrad(int layer, const uint16_t *gpre, const uint16_t *in
     const dim3 gr(ntap * ((nc + 7) / 8) * 8), b(256);   // (tap, chunk) pairs, chunks padded to a multiple of 8
     int cout = 0, cin = 0, cinp = 0;
     switch (layer) {
-    case 0: cout = 32; cin = 3; cinp = 8; pb += (size_t)nc * 32 * 9 * 8;
-        hipLaunchKernelGGL((k_conv_wgrad<8, 32, 1, false, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
+    case 0: cout = 32; cin = 3; cinp = 8; pb += (size_t)nc * 32 * 9 * 8;   // all taps per workgroup
+        hipLaunchKernelGGL((k_conv_wgrad_c8<32>), dim3(nc), b, 0, s, gpre, in, Ho, Wo, N, partial, pb, per, nc); break;
     case 1: cout = 64; cin = cinp = 32; pb += (size_t)nc * 64 * 9 * 32;
         hipLaunchKernelGGL((k_conv_wgrad<32, 64, 2, false, false>), gr, b, 0, s, gpre, in, Hs, Ws, N, Ho, Wo, partial, pb, per, nc); break;
     case 2: cout = 64; cin = cinp = 64; pb += (size_t)nc * 64 * 9 * 64;
