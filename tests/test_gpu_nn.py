@@ -30,7 +30,8 @@ def _log(*a):
     print(*a, flush=True)
 
 
-def _setup(seed=0):
+def _setup(seed=0, shape=(N, H, W)):
+    nb, h, w = shape
     import torch
     import paper_1708_00783_amd as T
     rng = np.random.default_rng(seed)
@@ -41,14 +42,14 @@ def _setup(seed=0):
     P["head.w"] = rng.standard_normal(P["head.w"].shape) * 0.05
     P = {k: v.astype(np.float32).astype(np.float64) for k, v in P.items()}
     # a smooth surface with depth-sensor-like noise and holes (realistic input scale)
-    yy, xx = np.mgrid[0:H, 0:W]
-    depth = np.stack([1.2 + 1.5 * n + 0.3 * np.sin(xx / (7.0 + n)) + 0.2 * np.cos(yy / 5.0) for n in range(N)])
+    yy, xx = np.mgrid[0:h, 0:w]
+    depth = np.stack([1.2 + 1.5 * n + 0.3 * np.sin(xx / (7.0 + n)) + 0.2 * np.cos(yy / 5.0) for n in range(nb)])
     depth = (depth + rng.normal(0, 0.004, depth.shape)).astype(np.float32)
     depth[0, 5:9, 10:20] = 0.0
     depth[1, :, :3] = 0.0
     target = (depth + rng.normal(0, 0.02, depth.shape)).astype(np.float32)
     target[0, 20:24] = 0.0
-    net = T.Denoiser(N, H, W, training=True)
+    net = T.Denoiser(nb, h, w, training=True)
     net.set_params(T.nn_flatten(P))
     d_depth = torch.from_numpy(depth).cuda()
     out = net.forward(d_depth)
@@ -76,8 +77,14 @@ LAYER_IO = {"e1": ("input", 1, False, None), "e2": ("e1", 2, False, None), "e3":
             "d1": ("d2", 1, True, "e1")}
 
 
-def test_forward_layers_match_oracle():
-    T, net, P, depth, target, out = _setup(1)
+# 40 x 56: the deepest source is 5 x 7, so the folded decoder kernels and the
+# stride-2 parity split meet odd sizes and ragged column runs
+SHAPES = [(N, H, W), (2, 40, 56)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_forward_layers_match_oracle(shape):
+    T, net, P, depth, target, out = _setup(1, shape)
     x = _bf(net, "input")
     assert np.array_equal(x[..., 0], D.to_bf16(depth * 0.25)) and np.array_equal(x[..., 1], (depth > 0) * 1.0)
     hp = D.make_input(depth.astype(np.float64))[..., 2]
@@ -108,14 +115,15 @@ def test_forward_layers_match_oracle():
     assert np.all(got[depth == 0] == 0)
 
 
-def test_backward_layers_match_oracle():
+@pytest.mark.parametrize("shape", SHAPES)
+def test_backward_layers_match_oracle(shape):
     import torch
-    T, net, P, depth, target, out = _setup(2)
+    T, net, P, depth, target, out = _setup(2, shape)
     loss = net.backward(torch.from_numpy(target).cuda()).cpu().numpy()
     o = out.cpu().numpy().astype(np.float64)
     l_ref, g_ref, n_ref = D.loss_and_grad_out(o, depth, target)
     assert int(loss[1]) == n_ref and abs(loss[0] - l_ref) < 1e-5 * max(1.0, l_ref)
-    dd = net.tensor("ddelta").cpu().numpy().astype(np.float64).reshape(N, H, W)
+    dd = net.tensor("ddelta").cpu().numpy().astype(np.float64).reshape(shape)
     assert np.allclose(dd, np.where(depth > 0, D.CORRECTION_SCALE * g_ref, 0), rtol=1e-6, atol=1e-12)
     grads = T.nn_unflatten(net.tensor("grads").cpu().numpy().reshape(-1))
     # head: gradient at d1 and head parameters
