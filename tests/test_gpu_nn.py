@@ -234,3 +234,30 @@ def test_training_reduces_loss():
     assert np.isfinite(losses).all()
     # the untrained prefilter is the identity: its loss is the raw noise; training lowers it
     assert np.mean(losses[-10:]) < 0.9 * losses[0]
+
+
+def test_training_is_deterministic():
+    """Every reduction on the training path sums in a fixed order (no atomics),
+    so the same steps from the same parameters give bit-identical weights and
+    losses."""
+    import torch
+    T, net, P, depth, target, out = _setup(6, (2, 40, 56))
+    x = torch.from_numpy(depth).cuda()
+    t = torch.from_numpy(target).cuda()
+    flat = T.nn_flatten(P)
+
+    def run():
+        net.set_params(flat)
+        losses = []
+        for _ in range(5):
+            net.forward(x)
+            losses.append(net.backward(t).cpu().numpy().copy())
+            net.adam_step(1e-3)
+        torch.cuda.synchronize()
+        return net.get_params().cpu().numpy().copy(), np.stack(losses)
+
+    p1, l1 = run()
+    p2, l2 = run()
+    assert not np.array_equal(p1, flat.astype(np.float32))   # the steps did change the weights
+    assert np.array_equal(p1.view(np.uint32), p2.view(np.uint32))
+    assert np.array_equal(l1.view(np.uint32), l2.view(np.uint32))
