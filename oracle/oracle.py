@@ -62,7 +62,7 @@ def lib():
                                                  ctypes.c_float, _I32, ctypes.c_int]),
             "or_alloc_and_visible": (None, [_VP, _F, ctypes.c_int, ctypes.c_int, _F, _F]),
             "or_integrate": (None, [_VP, _F, ctypes.c_int, ctypes.c_int, _F, _F]),
-            "or_integrate_literal": (None, [_VP, _F, ctypes.c_int, ctypes.c_int, _F, _F]),
+            "or_integrate_divide": (None, [_VP, _F, ctypes.c_int, ctypes.c_int, _F, _F]),
             "or_range": (None, [_VP, _I32, ctypes.c_int, ctypes.c_int, ctypes.c_int, _F, _F, _F, _F]),
             "or_raycast": (None, [_VP, ctypes.c_int, ctypes.c_int, _F, _F, _F, _F, _F, _F]),
             "or_trilinear": (ctypes.c_float, [_VP, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
@@ -73,6 +73,7 @@ def lib():
             "or_get_visible": (ctypes.c_int, [_VP, _I32]),
             "or_get_block_voxels": (None, [_VP, _I32, ctypes.c_int, _I16, _U8]),
             "or_get_host_block": (ctypes.c_int, [_VP, ctypes.c_int, _I16, _U8]),
+            "or_set_block_voxels": (ctypes.c_int, [_VP, ctypes.c_int, _I16, _U8]),
             "or_compose": (None, [_F, _F, _F]),
             "or_multi_range": (None, [_VP, _F, ctypes.c_int, ctypes.c_int, ctypes.c_int, _F, _F, _F, _F]),
             "or_multi_raycast": (None, [_VP, _F, ctypes.c_int, ctypes.c_int, ctypes.c_int, _F, _F, _F, _F,
@@ -186,6 +187,13 @@ class Volume:
         lib().or_get_block_voxels(self._h, _p(ids, _I32), ids.size, _p(sdf, _I16), _p(w, _U8))
         return sdf, w
 
+    def set_block_voxels(self, entry, sdf, w) -> None:
+        """overwrite one allocated entry's 512 voxels (in-block order lx + 8 ly + 64 lz)"""
+        s = np.ascontiguousarray(sdf, np.int16).reshape(512)
+        ww = np.ascontiguousarray(w, np.uint8).reshape(512)
+        if not lib().or_set_block_voxels(self._h, int(entry), _p(s, _I16), _p(ww, _U8)):
+            raise ValueError(f"entry {entry} has no device block")
+
     def allocated_positions(self) -> np.ndarray:
         """(N, 3) int block positions of entries with a device block, sorted."""
         pos, _, ptr = self.entries()
@@ -209,12 +217,12 @@ class Volume:
         M = np.ascontiguousarray(pose, np.float32).reshape(16)
         lib().or_alloc_and_visible(self._h, _p(d, _F), W, H, _p(k, _F), _p(M, _F))
 
-    def integrate(self, depth_m, intr, pose, literal=False):
+    def integrate(self, depth_m, intr, pose, divide=False):
         d = np.ascontiguousarray(depth_m, np.float32)
         H, W = d.shape
         k = np.ascontiguousarray(intr, np.float32)
         M = np.ascontiguousarray(pose, np.float32).reshape(16)
-        fn = lib().or_integrate_literal if literal else lib().or_integrate
+        fn = lib().or_integrate_divide if divide else lib().or_integrate
         fn(self._h, _p(d, _F), W, H, _p(k, _F), _p(M, _F))
 
     def range_image(self, W, H, intr, pose, blocks=None):

@@ -466,17 +466,24 @@ void or_alloc_and_visible(or_volume *v, const float *depth, int W, int H, const 
 }
 
 /* --------------------------------------------------------------------------
- * Integration (Sec. 4.3): computeUpdatedVoxelDepthInfo for every voxel of
- * every visible block.  Voxel p = 8 b + (lx, ly, lz) sits at world X = p *
- * voxel_size.  The listing's divisions are evaluated as
+ * Integration (Sec. 4.3): the running-average update of every voxel of every
+ * visible block.  Voxel p = 8 b + (lx, ly, lz) sits at world X = p *
+ * voxel_size; it is projected with the camera matrix and the pinhole model,
+ * read at the nearest pixel, and its SDF becomes the weight-averaged
+ * truncated distance.  Three quotients appear: the perspective division by
+ * z_c, eta / mu and the new average over w + 1 observations.  The pipeline
+ * evaluates them as products with reciprocals,
  *     rz  = 1 / z_c                 (one correctly rounded reciprocal)
  *     u   = (fx * x_c) * rz + cx,   v = (fy * y_c) * rz + cy
  *     f   = min(1, eta * (1/mu))
  *     avg = (w * F_old + f) * (1/(w+1))   with 1/(w+1) correctly rounded
- * which equal the listing in real arithmetic.  The short SDF is F * 32767
- * truncated toward zero; F_old = s * (1/32767).
+ * and F_old = s * (1/32767).  With `divide` set, the same update takes each
+ * quotient as one correctly rounded division instead (x / n for x * (1/n));
+ * the two agree in real arithmetic and the tests measure how often their
+ * float results differ.  The short SDF is F * 32767 truncated toward zero.
  * -------------------------------------------------------------------------- */
-void or_integrate(or_volume *v, const float *depth, int W, int H, const float *intr, const float *M)
+static void integrate_impl(or_volume *v, const float *depth, int W, int H, const float *intr, const float *M,
+                           int divide)
 {
     const float fx = intr[0], fy = intr[1], cx = intr[2], cy = intr[3];
     const float vs = v->voxel_size, mu = v->mu;
@@ -500,20 +507,27 @@ void or_integrate(or_volume *v, const float *depth, int W, int H, const float *i
             float c[3];
             transform(M, X, Y, Z, c);
             if (c[2] <= 0.0f) continue;
-            float rz = 1.0f / c[2];
-            float u = (fx * c[0]) * rz + cx;
-            float vv = (fy * c[1]) * rz + cy;
+            float u, vv;
+            if (divide) {
+                u = (fx * c[0]) / c[2] + cx;
+                vv = (fy * c[1]) / c[2] + cy;
+            } else {
+                float rz = 1.0f / c[2];
+                u = (fx * c[0]) * rz + cx;
+                vv = (fy * c[1]) * rz + cy;
+            }
             if (u < 1.0f || u > umax || vv < 1.0f || vv > vmax) continue;
             int ix = (int)(u + 0.5f), iy = (int)(vv + 0.5f);
             float d = depth[ix + iy * W];
             if (d <= 0.0f) continue;
             float eta = d - c[2];
             if (eta < neg_mu) continue;
-            float f_new = eta * inv_mu;
+            float f_new = divide ? eta / mu : eta * inv_mu;
             if (f_new > 1.0f) f_new = 1.0f;
             int w_old = Wt[l];
-            float f_old = (float)S[l] * k_sdf;
-            float avg = ((float)w_old * f_old + f_new) * rcp_w[w_old + 1];
+            float f_old = divide ? (float)S[l] / 32767.0f : (float)S[l] * k_sdf;
+            float sum = (float)w_old * f_old + f_new;
+            float avg = divide ? sum / (float)(w_old + 1) : sum * rcp_w[w_old + 1];
             int w_new = w_old + 1;
             if (w_new > max_w) w_new = max_w;
             S[l] = (int16_t)(avg * 32767.0f);
@@ -522,40 +536,16 @@ void or_integrate(or_volume *v, const float *depth, int W, int H, const float *i
     }
 }
 
-/* the same update with the listing's divisions, for the statistic that
- * compares the two evaluation orders (not used by the pipeline) */
-void or_integrate_literal(or_volume *v, const float *depth, int W, int H, const float *intr,
-                          const float *M)
+void or_integrate(or_volume *v, const float *depth, int W, int H, const float *intr, const float *M)
 {
-    const float fx = intr[0], fy = intr[1], cx = intr[2], cy = intr[3];
-    for (int k = 0; k < v->n_visible; ++k) {
-        const or_entry *e = &v->e[v->visible[k]];
-        if (e->ptr < 0) continue;
-        int16_t *S = &v->sdf[(size_t)e->ptr * OR_BLOCK_VOX];
-        uint8_t *Wt = &v->w[(size_t)e->ptr * OR_BLOCK_VOX];
-        for (int l = 0; l < OR_BLOCK_VOX; ++l) {
-            int px = 8 * e->x + (l & 7), py = 8 * e->y + ((l >> 3) & 7), pz = 8 * e->z + (l >> 6);
-            float c[3];
-            transform(M, (float)px * v->voxel_size, (float)py * v->voxel_size, (float)pz * v->voxel_size, c);
-            if (c[2] <= 0.0f) continue;
-            float u = fx * c[0] / c[2] + cx;
-            float vv = fy * c[1] / c[2] + cy;
-            if (u < 1.0f || u > (float)(W - 2) || vv < 1.0f || vv > (float)(H - 2)) continue;
-            float d = depth[(int)(u + 0.5f) + (int)(vv + 0.5f) * W];
-            if (d <= 0.0f) continue;
-            float eta = d - c[2];
-            if (eta < -v->mu) continue;
-            float old_f = (float)S[l] / 32767.0f;
-            int old_w = Wt[l];
-            float new_f = eta / v->mu < 1.0f ? eta / v->mu : 1.0f;
-            new_f = (float)old_w * old_f + new_f;
-            int new_w = old_w + 1;
-            new_f /= (float)new_w;
-            if (new_w > v->max_w) new_w = v->max_w;
-            S[l] = (int16_t)(new_f * 32767.0f);
-            Wt[l] = (uint8_t)new_w;
-        }
-    }
+    integrate_impl(v, depth, W, H, intr, M, 0);
+}
+
+/* the same update with every quotient as a division (the statistic that
+ * compares the two evaluation orders; not used by the pipeline) */
+void or_integrate_divide(or_volume *v, const float *depth, int W, int H, const float *intr, const float *M)
+{
+    integrate_impl(v, depth, W, H, intr, M, 1);
 }
 
 /* --------------------------------------------------------------------------
@@ -865,6 +855,17 @@ void or_get_block_voxels(const or_volume *v, const int32_t *entries, int n, int1
         memcpy(&sdf[(size_t)k * OR_BLOCK_VOX], &v->sdf[(size_t)p * OR_BLOCK_VOX], sizeof(int16_t) * OR_BLOCK_VOX);
         memcpy(&w[(size_t)k * OR_BLOCK_VOX], &v->w[(size_t)p * OR_BLOCK_VOX], OR_BLOCK_VOX);
     }
+}
+
+/* overwrite the voxels of one entry's device block (tests that assemble a
+ * volume block by block); 0 if the entry has no device block */
+int or_set_block_voxels(or_volume *v, int entry, const int16_t *sdf, const uint8_t *w)
+{
+    int p = v->e[entry].ptr;
+    if (p < 0) return 0;
+    memcpy(&v->sdf[(size_t)p * OR_BLOCK_VOX], sdf, sizeof(int16_t) * OR_BLOCK_VOX);
+    memcpy(&v->w[(size_t)p * OR_BLOCK_VOX], w, OR_BLOCK_VOX);
+    return 1;
 }
 
 /* host store contents of one entry (swap tests) */

@@ -113,18 +113,18 @@ def test_tilted_plane_closed_form_at_rounded_pixel(oracle_mod):
     assert upd.sum() > 10000
 
 
-def test_reciprocal_form_matches_listing(oracle_mod):
+def test_reciprocal_form_matches_division_form(oracle_mod):
     """The evaluation order used (one reciprocal of z, multiplications by
-    1/mu and 1/(w+1)) against the listing's divisions, over the ten C1 frames:
-    weights differ only where a pixel choice flips (rare), SDFs by <= 1 LSB
-    elsewhere."""
+    1/mu and 1/(w+1)) against the same update with every quotient as a
+    division, over the ten C1 frames: weights differ only where a pixel
+    choice flips (rare), SDFs by <= 1 LSB elsewhere."""
     d, p, intr, _ = configs.c1_frames()
     a = oracle_mod.Volume.from_params(VP)
     b = oracle_mod.Volume.from_params(VP)
     for k in range(len(d)):
-        for vol, lit in ((a, False), (b, True)):
+        for vol, div in ((a, False), (b, True)):
             vol.alloc_and_visible(d[k], intr.as_array(), p[k])
-            vol.integrate(d[k], intr.as_array(), p[k], literal=lit)
+            vol.integrate(d[k], intr.as_array(), p[k], divide=div)
     pa, sa, wa = a.voxels_by_position()
     pb, sb, wb = b.voxels_by_position()
     assert np.array_equal(pa, pb)

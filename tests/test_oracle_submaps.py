@@ -83,3 +83,97 @@ def test_rotated_submap_reproduces_analytic_surface(oracle_mod):
     # the grid really is rotated: its blocks are not those of the plain map
     plain, _, _, _ = _plain(oracle_mod, 10)
     assert {tuple(x) for x in vol.allocated_positions()} != {tuple(x) for x in plain.allocated_positions()}
+
+
+def _plane_submap(oracle_mod, z0, frames):
+    """a volume fused from `frames` identical frames of the fronto-parallel
+    plane z = z0 seen by the identity camera"""
+    depth = np.full((K.height, K.width), z0, np.float32)
+    pose = np.eye(4, dtype=np.float32)
+    vol = oracle_mod.Volume.from_params(VP)
+    for _ in range(frames):
+        vol.alloc_and_visible(depth, K.as_array(), pose)
+        vol.integrate(depth, K.as_array(), pose)
+    return vol
+
+
+def test_combined_field_is_weight_averaged(oracle_mod):
+    """Reading R27 (the combined field of Sec. 7.2, normalised): submap A
+    holds 9 observations of the plane z = 1.000 m, submap B 3 observations
+    of z = 1.016 m, both with identity poses.  Inside both truncation bands
+    F_A = (z_A - z) / mu and F_B = (z_B - z) / mu with weights 9 and 3, so
+    the weighted mean field vanishes at z* = (9 z_A + 3 z_B) / 12 = 1.004 m.
+    The raycast hit must sit there up to the plane raycast's own bound
+    (refinement residual v (1 - dir_z)^2 plus quantisation).  Weighting by
+    submap count puts the zero at 1.008 m, swapping the weights at 1.012 m,
+    and an unnormalised sum (F scaled by 12) breaks the distance-scaled
+    steps: each of these misses the bound by millimetres."""
+    za, na, zb, nb = 1.000, 9, 1.016, 3
+    a = _plane_submap(oracle_mod, za, na)
+    b = _plane_submap(oracle_mod, zb, nb)
+    # the premise: every voxel near z* carries exactly na (resp. nb) observations
+    _, _, wa = a.voxels_by_position()
+    _, _, wb = b.voxels_by_position()
+    assert wa.max() == na and wb.max() == nb
+    z_star = (na * za + nb * zb) / (na + nb)
+    pose = np.eye(4, dtype=np.float32)
+    m = oracle_mod.Multi([a, b], [pose, pose])
+    pts, nrm = m.raycast(K.width, K.height, K.as_array(), pose)
+    ys, xs = np.mgrid[0:K.height, 0:K.width]
+    ax = (xs - K.cx) / K.fx
+    by = (ys - K.cy) / K.fy
+    dir_z = 1.0 / np.sqrt(ax * ax + by * by + 1.0)
+    interior = (xs >= 6) & (xs < K.width - 6) & (ys >= 6) & (ys < K.height - 6)
+    hit = pts[..., 3] == 1
+    assert hit[interior].all()
+    # each submap's stored F drifts by at most one truncation per frame
+    quant = (na + nb) * VP.mu / 32767.0 + 1e-6
+    bound = VP.voxel_size * (1 - dir_z) ** 2 + quant
+    err = np.abs(pts[..., 2] - z_star)
+    assert np.all(err[interior] <= bound[interior]), float(err[interior].max())
+    # the alternatives are far outside the bound at every interior pixel
+    for wrong in ((za + zb) / 2, (nb * za + na * zb) / (na + nb)):
+        assert np.all(np.abs(pts[..., 2] - wrong)[interior] > bound[interior])
+    assert np.all(nrm[interior] == np.array([0, 0, -1, 1], np.float32))
+
+
+def test_partition_into_two_submaps_equals_plain(oracle_mod):
+    """Two identity-posed submaps that partition the plain map's blocks
+    (blocks with x < 0 in one, the rest in the other) give the plain raycast
+    wherever a hit's trilinear reads and normal taps stay on one side of the
+    cut: there a single submap contributes and the combined field is its
+    field.  The union of their blocks is the plain map's, so the allocation
+    test and the search range are the plain ones."""
+    plain, d, p, _ = _plain(oracle_mod)
+    pos, _, ptr = plain.entries()
+    ids = np.flatnonzero(ptr >= 0)
+    sdf, w = plain.block_voxels(ids)
+    parts = [oracle_mod.Volume.from_params(VP), oracle_mod.Volume.from_params(VP)]
+    for k, i in enumerate(ids):
+        bx, byy, bz = (int(c) for c in pos[i])
+        vol = parts[0] if bx < 0 else parts[1]
+        e = vol.insert(bx, byy, bz)
+        assert e >= 0
+        vol.set_block_voxels(e, sdf[k], w[k])
+    assert len(parts[0].allocated_positions()) > 50 and len(parts[1].allocated_positions()) > 50
+    V = p[-1]
+    pts0, nrm0 = plain.raycast(K.width, K.height, K.as_array(), V, blocks="all")
+    eye = np.eye(4, dtype=np.float32)
+    m = oracle_mod.Multi(parts, [eye, eye])
+    z0, z1 = plain.range_image(K.width, K.height, K.as_array(), V, blocks="all")
+    m0, m1 = m.range_image(K.width, K.height, K.as_array(), V)
+    assert np.array_equal(z0, m0) and np.array_equal(z1, m1)
+    pts1, nrm1 = m.raycast(K.width, K.height, K.as_array(), V)
+    h0 = pts0[..., 3] == 1
+    h1 = pts1[..., 3] == 1
+    # world x of the cut in voxel units is 0; keep hits whose reads (cell, +-1
+    # voxel normal taps, refinement) stay at least 3 voxels from it
+    xv = pts0[..., 0] / VP.voxel_size
+    away = h0 & (np.abs(xv) >= 3.0)
+    assert away.sum() > 1000
+    assert (h1[away]).mean() > 0.999
+    both = away & h1
+    dp = np.abs(pts0[both][:, :3] - pts1[both][:, :3]).max(axis=1)
+    assert np.mean(dp <= 1e-4) > 0.99, float(np.mean(dp <= 1e-4))
+    dn = np.abs(nrm0[both][:, :3] - nrm1[both][:, :3]).max(axis=1)
+    assert np.mean(dn <= 1e-3) > 0.99
