@@ -400,7 +400,7 @@ def run_c5(args):
         nrm = torch.empty_like(pts)
         for k in range(nf):
             vol.raycast(poses[k], K, pts, nrm)
-            tg[k] = PF.camera_depth(pts, poses[k])
+            PF.camera_depth(pts, poses[k], out=tg[k])
         vol.close()
         inputs.append(d)
         targets.append(tg)

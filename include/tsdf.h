@@ -20,7 +20,8 @@
  *     documented outputs.  Pointers named h_* are host pointers.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Work is only
  *     enqueued on it; calls return without waiting, except those documented
- *     as synchronising (tf_get_stats and the tf_export_* calls).
+ *     as synchronising (tf_get_stats, the tf_export_* calls, tf_swap_out,
+ *     tf_save and tf_load).
  *   - pose_w2c is the paper's M_d (Sec. 4.3): the 4x4 rigid world->camera
  *     transform, 16 host floats, row-major, last row (0 0 0 1).  The library
  *     inverts it itself; its rotation block must be orthonormal.
@@ -47,6 +48,7 @@ extern "C" {
 #define TF_E_HIP (-2)     /* a HIP runtime call failed */
 #define TF_E_ORDER (-3)   /* call order violated (e.g. integrate before alloc) */
 #define TF_E_SPACE (-4)   /* workspace smaller than tf_workspace_bytes() */
+#define TF_E_IO (-5)      /* file not opened, read or written, or not a volume of these parameters */
 
 /* ---- sticky overflow flags (tf_stats.flags) ---------------------------- */
 #define TF_FLAG_BLOCKS_EXHAUSTED 0x1u   /* the free-block stack ran empty (Sec. 4.2) */
@@ -332,6 +334,45 @@ int tf_multi_autotune(tf_multi *m, const void *d_depth, int depth_format, const 
 
 /* Synchronising. */
 int tf_multi_get_stats(tf_multi *m, tf_multi_stats *out, tf_stream stream);
+
+/* ==========================================================================
+ * Persistence of a volume (the scene parameters and the map of Sec. 3 and
+ * Sec. 6: hash table, free lists, voxel blocks, visible list and, with
+ * swapping, the host store of Sec. 5)
+ * ========================================================================== */
+
+/* Write the volume to the file at `path` (created or truncated): scene
+ * parameters, hash entries, both free stacks, the visible list, the
+ * occupancy bits, the voxel blocks in use (runs of consecutive block
+ * indices), the work counters and, with swapping, the host-store blocks the
+ * store holds.  Waits for `stream` first and reads the device synchronously;
+ * the volume is unchanged.  TF_E_INVAL for NULL arguments or a submap handle
+ * of a batched map; TF_E_IO when the file cannot be written. */
+int tf_save(tf_ctx *ctx, const char *path, tf_stream stream);
+
+/* Replace the volume's state by the one saved at `path`.  The context must
+ * have been created with parameters equal to the saved ones (every tf_params
+ * field), else TF_E_IO and the volume is unchanged.  Synchronising.  After a
+ * load the volume is block for block, entry for entry and counter for
+ * counter the saved one (allocation continues from the same free stacks, so
+ * a later frame allocates the same block indices); the next frame starts with
+ * tf_alloc_and_visible (tf_integrate before it returns TF_E_ORDER).  If the
+ * file ends early or holds inconsistent sizes, TF_E_IO and the volume is
+ * left reset (empty). */
+int tf_load(tf_ctx *ctx, const char *path, tf_stream stream);
+
+/* ==========================================================================
+ * Training targets of the learned prefilter (see tsdf_nn.h)
+ * ========================================================================== */
+
+/* Camera depth of raycast hit points: for each of width x height pixels,
+ * d_depth = the camera z of the world point d_points (float4 as written by
+ * tf_raycast, w = 1 on a hit) under pose_w2c, each row evaluated as
+ * ((m8 x + m9 y) + m10 z) + m11; 0 where w != 1.  d_points: width*height*4
+ * device floats (16-byte aligned), d_depth: width*height device floats.
+ * Enqueued only. */
+int tf_camera_depth(const float *d_points, int32_t width, int32_t height, const float pose_w2c[16],
+                    float *d_depth, tf_stream stream);
 
 /* Human-readable name of a status code. */
 const char *tf_status_string(int status);

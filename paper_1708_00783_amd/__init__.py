@@ -17,7 +17,7 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libtsdf.so")
 
-TF_OK, TF_E_INVAL, TF_E_HIP, TF_E_ORDER, TF_E_SPACE = 0, -1, -2, -3, -4
+TF_OK, TF_E_INVAL, TF_E_HIP, TF_E_ORDER, TF_E_SPACE, TF_E_IO = 0, -1, -2, -3, -4, -5
 TF_DEPTH_F32_M, TF_DEPTH_U16_MM = 0, 1
 TF_FLAG_BLOCKS_EXHAUSTED = 0x1
 TF_FLAG_EXCESS_EXHAUSTED = 0x2
@@ -31,7 +31,7 @@ EXPORTS = (
     "tf_destroy", "tf_reset", "tf_alloc_and_visible", "tf_integrate", "tf_raycast",
     "tf_range_image", "tf_swap_out", "tf_get_stats", "tf_export_entries", "tf_export_visible",
     "tf_export_voxels", "tf_status_string", "tf_profile_enable", "tf_profile_read",
-    "tf_export_host_voxels", "tf_profile_select",
+    "tf_export_host_voxels", "tf_profile_select", "tf_save", "tf_load", "tf_camera_depth",
     "tf_multi_workspace_bytes", "tf_multi_host_bytes", "tf_multi_create", "tf_multi_destroy",
     "tf_multi_submap", "tf_multi_set_config", "tf_multi_get_config", "tf_multi_integrate",
     "tf_multi_raycast", "tf_multi_frame", "tf_multi_range_image", "tf_multi_autotune",
@@ -138,6 +138,9 @@ def lib():
             "tf_profile_read": (ctypes.c_int, [_VP, P(tf_profile), ctypes.c_int]),
             "tf_profile_select": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32]),
             "tf_export_host_voxels": (ctypes.c_int, [_VP, _VP, ctypes.c_uint32, _VP, _VP, _VP]),
+            "tf_save": (ctypes.c_int, [_VP, ctypes.c_char_p, _VP]),
+            "tf_load": (ctypes.c_int, [_VP, ctypes.c_char_p, _VP]),
+            "tf_camera_depth": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, _F16, _VP, _VP]),
             "tf_multi_workspace_bytes": (ctypes.c_size_t, [P(tf_params), ctypes.c_uint32, ctypes.c_uint32,
                                                            ctypes.c_uint32, ctypes.c_uint32]),
             "tf_multi_host_bytes": (ctypes.c_size_t, []),
@@ -251,6 +254,14 @@ def tf_range_image(ctx, pose, intr, zmin, zmax, stream=None):
                                ctypes.c_void_p(zmax.data_ptr()), _stream_ptr(stream)), "tf_range_image")
 
 
+def tf_camera_depth(points, pose, depth, stream=None):
+    """camera z of raycast hit points (H, W, 4) under pose into depth (H, W); 0 on a miss"""
+    _, Mp = _pose_arg(pose)
+    H, W = int(points.shape[0]), int(points.shape[1])
+    check(lib().tf_camera_depth(ctypes.c_void_p(points.data_ptr()), W, H, Mp, ctypes.c_void_p(depth.data_ptr()),
+                                _stream_ptr(stream)), "tf_camera_depth")
+
+
 def tf_get_stats(ctx, stream=None) -> dict:
     st = tf_stats()
     check(lib().tf_get_stats(ctx, ctypes.byref(st), _stream_ptr(stream)), "tf_get_stats")
@@ -344,6 +355,14 @@ class Volume:
 
     def stats(self, stream=None) -> dict:
         return tf_get_stats(self.ctx, stream)
+
+    def save(self, path, stream=None):
+        """write the whole volume to `path` (synchronising)"""
+        check(lib().tf_save(self.ctx, os.fsencode(path), _stream_ptr(stream)), "tf_save")
+
+    def load(self, path, stream=None):
+        """replace the volume by the one saved at `path` (same parameters; synchronising)"""
+        check(lib().tf_load(self.ctx, os.fsencode(path), _stream_ptr(stream)), "tf_load")
 
     def profile_enable(self, on=True):
         check(lib().tf_profile_enable(self.ctx, 1 if on else 0), "tf_profile_enable")

@@ -42,10 +42,11 @@ Net make_net()
         L.kp = ((9 * L.cinp + 31) / 32) * 32;
         if (l < kLayers - 1) {
             L.g_off = go;
-            // upsampled layers: the forward reads parity-folded 2x2 weights
-            go += L.up ? 4 * L.cout * 4 * L.cinp : L.cout * L.kp;
+            // upsampled layers: the forward reads parity-folded 2x2 weights,
+            // split into bf16 high and low halves
+            go += L.up ? 2 * 4 * L.cout * 4 * L.cinp : L.cout * L.kp;
             L.t_off = l > 0 ? to : -1;
-            if (l > 0) to += L.cinp * (L.up ? 16 : 9) * L.cout;   // up layers: folded, [ci][par][a][b][co]
+            if (l > 0) to += L.cinp * (L.up ? 2 * 16 : 9) * L.cout;   // up layers: [half][ci][par][a][b][co]
         } else {
             L.g_off = L.t_off = -1;
         }

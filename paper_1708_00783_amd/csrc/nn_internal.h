@@ -11,8 +11,9 @@
 // rounded up to 32) for the forward pass, T[cin][9 cout] with k = tap * cout
 // + co for the backward-data pass.  A layer that reads the 2x upsampled
 // source instead packs its taps folded by output parity (the sum of the taps
-// that land on each 2x2 source offset): G[4 parities][cout][4 CINP] and
-// T[cin][16 cout].
+// that land on each 2x2 source offset), each folded weight split into a bf16
+// high half and the bf16 remainder: G[2 halves][4 parities][cout][4 CINP] and
+// T[2 halves][cin][16 cout].
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -46,8 +47,8 @@ struct LayerDesc {
     int w_off, b_off;                   // fp32 parameter offsets
     int kp;                             // forward GEMM K (padded)
     int g_off, t_off;                   // bf16 packed-weight offsets (elements); an up layer's are
-                                        // parity-folded: [4 parities][cout][4 offsets x cinp] and
-                                        // [cinp][4 parities x 4 offsets x cout]
+                                        // parity-folded and split: [2 halves][4 parities][cout][4 offsets
+                                        // x cinp] and [2 halves][cinp][4 parities x 4 offsets x cout]
     int scale;                          // output resolution divisor (1, 2, 4, 8)
 };
 

@@ -6,10 +6,12 @@
 //                       the operand gather applies the stride
 //   k_conv_fwd_up       decoder (nearest 2x upsampling, then 3x3): per output
 //                       parity a 2x2 convolution of the source on folded
-//                       weights, K = (source offset, ci)
+//                       weights split into bf16 high and low halves,
+//                       K = (source offset, half, ci)
 //   k_conv_bwd_data_s2  stride-2 layers: M = input pixels, N = cin, K = the
 //                       taps that reach the input pixel's parity x co
-//   k_conv_bwd_data_up  decoder: the adjoint of the folded forward, K = 16 co
+//   k_conv_bwd_data_up  decoder: the adjoint of the folded forward, K = (16
+//                       parity x offset, half, co)
 //   k_conv_wgrad        M = cout, N = cin of one tap, K = pixels of one chunk:
 //                       both operands are staged transposed in LDS; per-chunk
 //                       partial sums are reduced in a fixed order
@@ -195,12 +197,18 @@ __device__ __forceinline__ void pack_t(const float *w, int cin, int cout, int i,
 // Nearest 2x upsampling followed by a 3x3 convolution, folded by output
 // parity: output pixel (2m + py, 2n + px) reads only the 2x2 source pixels
 // (m + py - 1 + a, n + px - 1 + b), a, b in {0, 1}.  Tap ky lands on source
-// row offset a = ((py + ky - 1) >> 1) + 1 - py (likewise kx -> b), so
-// gu[py * 2 + px][co][(a * 2 + b) * cinp + ci] is the fp32 sum of the
-// bf16-rounded weights of the taps that land there (ascending ky, kx),
-// rounded to bf16.  Zero padding agrees: a source row is outside the image
-// exactly when every tap landing on it is.
-__device__ __forceinline__ uint16_t folded_weight(const float *w, int cin, int par, int co, int q, int ci)
+// row offset a = ((py + ky - 1) >> 1) + 1 - py (likewise kx -> b): per axis
+// one offset receives one tap and the other two, so per parity the four
+// offsets receive 1, 2, 2 and 4 of the 9 taps.  The folded weight of an
+// offset is s = the fp32 sum of the bf16 taps landing there (ascending ky,
+// kx); it is carried as two bf16 numbers, hi = bf16(s) and lo = bf16(s - hi),
+// so that a product with a bf16 activation sums the taps' products: hi + lo
+// equals s exactly where at most two taps land (the rounding error of a
+// two-term sum is representable in the same precision) and within 2^-17 of
+// s at the four-tap offset.  The one-tap offset (a, b) = (py, px) has lo = 0.
+// Zero padding agrees: a source row is outside the image exactly when every
+// tap landing on it is.
+__device__ __forceinline__ uint16_t folded_weight(const float *w, int cin, int par, int co, int q, int ci, int lo)
 {
     const int py = par >> 1, px = par & 1, a = q >> 1, b = q & 1;
     float s = 0.0f;
@@ -212,23 +220,28 @@ __device__ __forceinline__ uint16_t folded_weight(const float *w, int cin, int p
                 s += bf2f(f2bf(w[(co * 9 + ky * 3 + kx) * cin + ci]));
             }
         }
-    return f2bf(s);
+    const uint16_t hi = f2bf(s);
+    return lo ? f2bf(s - bf2f(hi)) : hi;
 }
 
-// forward operand gu[par][co][q * cinp + ci], q = a * 2 + b
+// forward operand gu[lo][par][co][q * cinp + ci], q = a * 2 + b
 __device__ __forceinline__ void pack_up(const float *w, int cin, int cinp, int cout, int i, uint16_t *gu)
 {
     const int k4 = 4 * cinp;
-    const int par = i / (cout * k4), rem = i - par * cout * k4;
+    const int half = 4 * cout * k4;
+    const int lo = i / half, j = i - lo * half;
+    const int par = j / (cout * k4), rem = j - par * cout * k4;
     const int co = rem / k4, k = rem - co * k4, q = k / cinp, ci = k - (k / cinp) * cinp;
-    gu[i] = folded_weight(w, cin, par, co, q, ci);
+    gu[i] = folded_weight(w, cin, par, co, q, ci, lo);
 }
 
-// backward-data operand of the same folded weights: tu[ci][(par * 4 + q) * cout + co]
-__device__ __forceinline__ void pack_tu(const float *w, int cin, int cout, int i, uint16_t *tu)
+// backward-data operand of the same folded weights: tu[lo][ci][(par * 4 + q) * cout + co]
+__device__ __forceinline__ void pack_tu(const float *w, int cin, int cinp, int cout, int i, uint16_t *tu)
 {
-    const int ci = i / (16 * cout), rem = i - ci * 16 * cout, pq = rem / cout, co = rem - (rem / cout) * cout;
-    tu[i] = folded_weight(w, cin, pq >> 2, co, pq & 3, ci);
+    const int half = cinp * 16 * cout;
+    const int lo = i / half, j = i - lo * half;
+    const int ci = j / (16 * cout), rem = j - ci * 16 * cout, pq = rem / cout, co = rem - (rem / cout) * cout;
+    tu[i] = folded_weight(w, cin, pq >> 2, co, pq & 3, ci, lo);
 }
 
 // every conv layer's packed weights in one launch: thread i belongs to the
@@ -249,23 +262,25 @@ __global__ __launch_bounds__(256) void k_pack(PackJobs J)
     }
     if (p.t && li < p.n_t) {
         if (p.up)
-            pack_tu(p.w, p.cin, p.cout, li, p.t);
+            pack_tu(p.w, p.cin, p.cinp, p.cout, li, p.t);
         else
             pack_t(p.w, p.cin, p.cout, li, p.t);
     }
 }
 
 // forward of an upsampled layer on the parity-folded weights: a wave takes
-// 16 T source columns of one source row and one output parity (K = 4 cinp
-// instead of 9 cinp) and COUT / NS output channels; the 4 parities of a
-// column run are neighbouring waves and read the same source pixels
+// 16 T source columns of one source row and one output parity and COUT / NS
+// output channels; the 4 parities of a column run are neighbouring waves and
+// read the same source pixels.  Each source operand fragment meets the high
+// and the low half of the folded weights (the one-tap offset has no low
+// half): 7 cinp multiply-adds per output instead of 9 cinp
 template <int CINP, int COUT, bool SKIP, int T, int NS>
 __global__ __launch_bounds__(256) void k_conv_fwd_up(const uint16_t *in, int Hs, int Ws, const uint16_t *gu,
                                                      const float *bias, const uint16_t *skip, uint16_t *out, int N)
 {
     static_assert(NS == 1 || NS == 2 || NS == 4, "channel split must divide the 4 waves of a workgroup");
     constexpr int K4 = 4 * CINP;
-    static_assert(K4 % 32 == 0, "K must be whole MFMA steps");
+    static_assert(CINP % 32 == 0, "a K step stays inside one source offset");
     constexpr int NT = COUT / 16 / NS;
     const int lane = (int)threadIdx.x & 63, r = lane & 15, gq = lane >> 4;
     const int runs = (Ws + 16 * T - 1) / (16 * T);
@@ -287,10 +302,12 @@ __global__ __launch_bounds__(256) void k_conv_fwd_up(const uint16_t *in, int Hs,
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const uint16_t *gp = gu + (size_t)par * COUT * K4;
+    const uint16_t *gl = gp + (size_t)4 * COUT * K4;   // low halves
 #pragma unroll 2
     for (int k0 = 0; k0 < K4; k0 += 32) {
         const int k = k0 + gq * 8;
         const int q = k / CINP, ci = k - (k / CINP) * CINP;
+        const bool split = q != par;   // wave-uniform: one source offset per K step
         const int sy = m + py - 1 + (q >> 1);
         bf16x8 av[T];
 #pragma unroll
@@ -304,9 +321,15 @@ __global__ __launch_bounds__(256) void k_conv_fwd_up(const uint16_t *in, int Hs,
         }
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            const bf16x8 b = as_bf(ld16(gp + (size_t)(cbase + j * 16 + r) * K4 + k));
+            const size_t wo = (size_t)(cbase + j * 16 + r) * K4 + k;
+            const bf16x8 b = as_bf(ld16(gp + wo));
 #pragma unroll
             for (int t = 0; t < T; ++t) acc[t][j] = mfma(av[t], b, acc[t][j]);
+            if (split) {
+                const bf16x8 bl = as_bf(ld16(gl + wo));
+#pragma unroll
+                for (int t = 0; t < T; ++t) acc[t][j] = mfma(av[t], bl, acc[t][j]);
+            }
         }
     }
     const size_t orow = ((size_t)nimg * Ho + 2 * m + py) * Wo;
@@ -397,9 +420,10 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, in
 // backward data of an upsampled layer: the adjoint of the parity-folded
 // forward.  Source pixel (m, n) collects, for each output parity (py, px)
 // and source offset (a, b), the output pixel (2 m' + py, 2 n' + px) with
-// m' = m + 1 - py - a, n' = n + 1 - px - b: K = 16 COUT instead of 4 x 9 COUT,
-// on the same folded bf16 weights as the forward.  Then the source's relu
-// mask.  A wave takes 32 source pixels and CIN / NS channels.
+// m' = m + 1 - py - a, n' = n + 1 - px - b, on the same split folded
+// weights as the forward (high and low halves; 28 COUT multiply-adds per
+// source channel instead of 36 COUT).  Then the source's relu mask.  A wave
+// takes 32 source pixels and CIN / NS channels.
 template <int CIN, int COUT, int NS>
 __global__ __launch_bounds__(256) void k_conv_bwd_data_up(const uint16_t *gpre, const uint16_t *tu,
                                                           const uint16_t *act, uint16_t *gout, int N, int Hs, int Ws)
@@ -431,8 +455,10 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data_up(const uint16_t *gpre, 
     for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t *tl = tu + (size_t)CIN * K16;   // low halves
     for (int pq = 0; pq < 16; ++pq) {
         const int py = pq >> 3, px = (pq >> 2) & 1, a = (pq >> 1) & 1, b = pq & 1;
+        const bool split = (pq & 3) != (pq >> 2);   // offset (a, b) != (py, px): two or four taps
 #pragma unroll 2
         for (int co0 = 0; co0 < COUT; co0 += 32) {
             const int co = co0 + gq * 8;
@@ -447,9 +473,15 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data_up(const uint16_t *gpre, 
             }
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
-                const bf16x8 bv = as_bf(ld16(tu + (size_t)(cbase + j * 16 + r) * K16 + pq * COUT + co));
+                const size_t wo = (size_t)(cbase + j * 16 + r) * K16 + pq * COUT + co;
+                const bf16x8 bv = as_bf(ld16(tu + wo));
                 acc[0][j] = mfma(av[0], bv, acc[0][j]);
                 acc[1][j] = mfma(av[1], bv, acc[1][j]);
+                if (split) {
+                    const bf16x8 bl = as_bf(ld16(tl + wo));
+                    acc[0][j] = mfma(av[0], bl, acc[0][j]);
+                    acc[1][j] = mfma(av[1], bl, acc[1][j]);
+                }
             }
         }
     }
@@ -1123,8 +1155,8 @@ hipError_t launch_pack(const Net &net, const float *params, uint16_t *g, uint16_
         p.cout = L.cout;
         p.kp = L.kp;
         p.up = L.up;
-        p.n_g = L.up ? 16 * L.cout * L.cinp : L.cout * L.kp;
-        p.n_t = p.t ? L.cinp * (L.up ? 16 : 9) * L.cout : 0;
+        p.n_g = L.up ? 2 * 16 * L.cout * L.cinp : L.cout * L.kp;   // up layers: high and low halves
+        p.n_t = p.t ? L.cinp * (L.up ? 2 * 16 : 9) * L.cout : 0;
         J.start[l] = at;
         at += p.n_g > p.n_t ? p.n_g : p.n_t;
     }

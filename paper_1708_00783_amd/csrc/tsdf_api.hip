@@ -93,6 +93,8 @@ Layout make_layout(const tf_params *p)
         L.host_has = take(n_vis);
         L.xfer_idx = take((size_t)p->swap_transfer_blocks * 4);
         L.xfer_vox = take((size_t)p->swap_transfer_blocks * kBlockBytes);
+        L.xfer_host = take((size_t)p->swap_transfer_blocks * kBlockBytes);
+        L.xfer_pend = take((size_t)p->swap_transfer_blocks * 4);
         L.swap_chunks = take(((n_entries + kSwapChunk - 1) / kSwapChunk) * 4);
     }
     L.voxels = take((size_t)p->n_blocks * kBlockBytes);
@@ -158,30 +160,6 @@ struct Timed {
         }
     }
 };
-
-// secondary integration on the host (the same per-voxel rule as k_swap_merge):
-// copy a (the store) becomes the weighted average of a and b
-void merge_block_host(uint8_t *a, const uint8_t *b, int max_w)
-{
-    int16_t *sa = (int16_t *)a;
-    const int16_t *sb = (const int16_t *)b;
-    for (int j = 0; j < kBlockVox; ++j) {
-        int wa = a[1024 + j], wb = b[1024 + j];
-        if (wb == 0) continue;
-        if (wa == 0) {
-            sa[j] = sb[j];
-            a[1024 + j] = b[1024 + j];
-            continue;
-        }
-        const float fa = (float)sa[j] * (1.0f / 32767.0f);
-        const float fb = (float)sb[j] * (1.0f / 32767.0f);
-        const float avg = ((float)wa * fa + (float)wb * fb) / (float)(wa + wb);
-        int w = wa + wb;
-        if (w > max_w) w = max_w;
-        sa[j] = (int16_t)(avg * 32767.0f);
-        a[1024 + j] = (uint8_t)w;
-    }
-}
 
 // swap-in after the visible list (Sec. 5): the device lists the visible
 // entries whose host store holds data; the host takes the lowest entry
@@ -284,6 +262,8 @@ int tf_create(const tf_params *p, void *d_workspace, size_t bytes, void *h_store
     v.host_has = p->swap_transfer_blocks ? b + L.host_has : nullptr;
     v.xfer_idx = p->swap_transfer_blocks ? (int32_t *)(b + L.xfer_idx) : nullptr;
     v.xfer_vox = p->swap_transfer_blocks ? b + L.xfer_vox : nullptr;
+    v.xfer_host = p->swap_transfer_blocks ? b + L.xfer_host : nullptr;
+    v.xfer_pend = p->swap_transfer_blocks ? (int32_t *)(b + L.xfer_pend) : nullptr;
     v.swap_chunks = p->swap_transfer_blocks ? (uint32_t *)(b + L.swap_chunks) : nullptr;
     v.alist = nullptr;
     v.n_buckets = p->n_buckets;
@@ -517,15 +497,39 @@ int tf_swap_out(tf_ctx *ctx, tf_stream stream)
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return TF_E_HIP;
         uint8_t *store = (uint8_t *)ctx->h_store;
+        // blocks whose host copy never came back in are fused with it (the
+        // secondary integration, on the device, below); the others are copied
+        std::vector<int32_t> &pend = ctx->cand;
+        pend.clear();
         for (uint32_t k = 0; k < m; ++k) {
             const int32_t idx = hidx[k];
-            uint8_t *dst = store + (size_t)idx * kBlockBytes;
-            // host data that never made it back in is fused, not overwritten
             if (ctx->host_has[idx])
-                merge_block_host(dst, hvox + (size_t)k * kBlockBytes, ctx->p.max_w);
+                pend.push_back((int32_t)k);
             else
-                memcpy(dst, hvox + (size_t)k * kBlockBytes, kBlockBytes);
+                memcpy(store + (size_t)idx * kBlockBytes, hvox + (size_t)k * kBlockBytes, kBlockBytes);
             ctx->host_has[idx] = 1;
+        }
+        const uint32_t np = (uint32_t)pend.size();
+        if (np) {
+            // the pinned buffer's blocks are consumed: stage the store copies
+            // there (slot j), upload them with their transfer-buffer slots, fuse,
+            // and bring the results back
+            std::vector<int32_t> entry(np);
+            for (uint32_t j = 0; j < np; ++j) {
+                entry[j] = hidx[pend[j]];
+                memcpy(hvox + (size_t)j * kBlockBytes, store + (size_t)entry[j] * kBlockBytes, kBlockBytes);
+                hidx[j] = pend[j];
+            }
+            e = hipMemcpyAsync(v.xfer_pend, hidx, (size_t)np * 4, hipMemcpyHostToDevice, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(v.xfer_host, hvox, (size_t)np * kBlockBytes, hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = launch_swap_merge_out(v, np, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(hvox, v.xfer_host, (size_t)np * kBlockBytes, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return TF_E_HIP;
+            for (uint32_t j = 0; j < np; ++j)
+                memcpy(store + (size_t)entry[j] * kBlockBytes, hvox + (size_t)j * kBlockBytes, kBlockBytes);
         }
     }
     e = launch_swap_release(v, m, s);
@@ -647,6 +651,16 @@ int tf_export_voxels(tf_ctx *ctx, const int32_t *d_entries, uint32_t n, int16_t 
     return hip_status(launch_export_voxels(ctx->v, d_entries, n, d_sdf, d_w, (hipStream_t)stream));
 }
 
+int tf_camera_depth(const float *d_points, int32_t width, int32_t height, const float pose_w2c[16], float *d_depth,
+                    tf_stream stream)
+{
+    if (!d_points || !d_depth || !pose_ok(pose_w2c) || width < 1 || height < 1 || width > 16384 || height > 16384)
+        return TF_E_INVAL;
+    if (((uintptr_t)d_points) & 15u) return TF_E_INVAL;
+    return hip_status(launch_camera_depth((const float4 *)d_points, width * height, pose_w2c, d_depth,
+                                          (hipStream_t)stream));
+}
+
 const char *tf_status_string(int status)
 {
     switch (status) {
@@ -655,6 +669,7 @@ const char *tf_status_string(int status)
     case TF_E_HIP: return "HIP runtime error";
     case TF_E_ORDER: return "call order violated";
     case TF_E_SPACE: return "workspace too small";
+    case TF_E_IO: return "file error or not a volume of these parameters";
     default: return "unknown status";
     }
 }

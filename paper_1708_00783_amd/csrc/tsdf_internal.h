@@ -102,6 +102,8 @@ struct Vol {
     uint8_t *host_has;              // swapping: 1 if the host store holds data for the entry
     int32_t *xfer_idx;              // swapping: transfer-buffer entry indices
     uint8_t *xfer_vox;              // swapping: transfer-buffer blocks
+    uint8_t *xfer_host;             // swapping: host-store copies fused into swap-out blocks
+    int32_t *xfer_pend;             // swapping: transfer-buffer slot of each such copy
     uint32_t *swap_chunks;          // swapping: per-chunk candidate counts, then offsets
     int4 *alist;                    // submap volumes: allocated blocks {x | y << 16, z, ptr, entry}
     uint32_t n_buckets, n_excess, n_entries, n_blocks;
@@ -123,7 +125,8 @@ struct Cam {
 // workspace carving
 struct Layout {
     size_t entries, vis, free_blocks, free_excess, voxels, vlist, reqset, reqs, ret, depth,
-        recs, bins, bin_count, ctrl, acc_cols, acc_hits, occ, brick, host_has, xfer_idx, xfer_vox, swap_chunks, total;
+        recs, bins, bin_count, ctrl, acc_cols, acc_hits, occ, brick, host_has, xfer_idx, xfer_vox, xfer_host,
+        xfer_pend, swap_chunks, total;
     uint32_t reqset_size, max_req, max_tiles;
 };
 
@@ -146,6 +149,8 @@ hipError_t launch_swap_merge(const Vol &v, uint32_t n, hipStream_t s);
 hipError_t launch_swap_select(const Vol &v, hipStream_t s);
 hipError_t launch_swap_gather(const Vol &v, uint32_t n, hipStream_t s);
 hipError_t launch_swap_release(const Vol &v, uint32_t n, hipStream_t s);
+hipError_t launch_swap_merge_out(const Vol &v, uint32_t n, hipStream_t s);
+hipError_t launch_camera_depth(const float4 *pts, int n, const float *M, float *depth, hipStream_t s);
 hipError_t launch_export_voxels(const Vol &v, const int32_t *ids, uint32_t n, int16_t *sdf,
                                 uint8_t *w, hipStream_t s);
 

@@ -683,6 +683,31 @@ __global__ __launch_bounds__(256) void k_swap_merge(Vol v, uint32_t n)
     }
 }
 
+// Swap-out of blocks whose host copy never came back in (Sec. 5, secondary
+// integration): the store copies of those entries, uploaded to xfer_host,
+// are fused with the device copies the gather put into the transfer buffer
+// (slot xfer_pend[k]); the result replaces the store copy.  One wave per block.
+__global__ __launch_bounds__(256) void k_swap_merge_out(Vol v, uint32_t n)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t gwave = (blockIdx.x * 256u + threadIdx.x) / kWave;
+    const uint32_t nwaves = gridDim.x * (256u / kWave);
+    for (uint32_t k = gwave; k < n; k += nwaves) {
+        uint8_t *a = v.xfer_host + (size_t)k * kBlockBytes;
+        const uint8_t *b = v.xfer_vox + (size_t)v.xfer_pend[k] * kBlockBytes;
+        int16_t *as = reinterpret_cast<int16_t *>(a);
+        const int16_t *bs = reinterpret_cast<const int16_t *>(b);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int j = (int)lane * 8 + q;
+            int sa = as[j], wa = a[1024 + j];
+            merge_voxel(sa, wa, bs[j], b[1024 + j], v.max_w);
+            as[j] = (int16_t)sa;
+            a[1024 + j] = (uint8_t)wa;
+        }
+    }
+}
+
 // marks the visible entries (val = 1) or clears the marks (val = 0)
 __global__ __launch_bounds__(256) void k_mark_visible(Vol v, uint8_t val)
 {
@@ -825,6 +850,21 @@ __global__ __launch_bounds__(256) void k_export_voxels(Vol v, const int32_t *ids
 }
 
 // ============================================================================
+// camera depth of raycast hits (training targets of the prefilter)
+// ============================================================================
+struct Row3 {
+    float m8, m9, m10, m11;
+};
+
+__global__ __launch_bounds__(256) void k_camera_depth(const float4 *pts, int n, Row3 r, float *depth)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    const float4 q = pts[p];
+    depth[p] = q.w == 1.0f ? ((r.m8 * q.x + r.m9 * q.y) + r.m10 * q.z) + r.m11 : 0.0f;
+}
+
+// ============================================================================
 // launchers
 // ============================================================================
 static int cu_grid(size_t work, int per_block, int cap)
@@ -918,6 +958,13 @@ hipError_t launch_range_write(const Vol &v, const Cam &c, float *zmin, float *zm
     return hipGetLastError();
 }
 
+hipError_t launch_camera_depth(const float4 *pts, int n, const float *M, float *depth, hipStream_t s)
+{
+    const Row3 r = {M[8], M[9], M[10], M[11]};
+    hipLaunchKernelGGL(k_camera_depth, dim3((n + 255) / 256), dim3(256), 0, s, pts, n, r, depth);
+    return hipGetLastError();
+}
+
 hipError_t launch_export_voxels(const Vol &v, const int32_t *ids, uint32_t n, int16_t *sdf, uint8_t *w, hipStream_t s)
 {
     hipLaunchKernelGGL(k_export_voxels, dim3(cu_grid((size_t)n * 64, 256, 4096)), dim3(256), 0, s, v, ids, n, sdf, w);
@@ -953,6 +1000,12 @@ hipError_t launch_swap_select(const Vol &v, hipStream_t s)
 hipError_t launch_swap_gather(const Vol &v, uint32_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_swap_gather, dim3(cu_grid((size_t)n * 64, 256, 2048)), dim3(256), 0, s, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_swap_merge_out(const Vol &v, uint32_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_swap_merge_out, dim3(cu_grid((size_t)n * 64, 256, 2048)), dim3(256), 0, s, v, n);
     return hipGetLastError();
 }
 

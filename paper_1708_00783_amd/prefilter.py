@@ -18,7 +18,7 @@ import time
 
 import numpy as np
 
-from . import NN_LAYERS, Denoiser, Volume
+from . import NN_LAYERS, Denoiser, Volume, tf_camera_depth
 
 FRAME_W, FRAME_H = 640, 480
 
@@ -56,12 +56,14 @@ def room_poses(seed_index: int, n: int) -> np.ndarray:
     return np.stack(configs.c2_poses(max(300, n), seed_index)[:n]).astype(np.float32)
 
 
-def camera_depth(points, pose):
-    """camera z of world hit points (H, W, 4 device tensor; w = 1 on a hit), 0 on a miss"""
+def camera_depth(points, pose, out=None):
+    """camera z of world hit points (H, W, 4 device tensor; w = 1 on a hit), 0
+    on a miss, by the library's tf_camera_depth"""
     import torch
-    M = torch.as_tensor(np.asarray(pose, np.float32)[2], device=points.device)
-    z = points[..., 0] * M[0] + points[..., 1] * M[1] + points[..., 2] * M[2] + M[3]
-    return torch.where(points[..., 3] == 1.0, z, torch.zeros_like(z))
+    if out is None:
+        out = torch.empty(points.shape[:2], dtype=torch.float32, device=points.device)
+    tf_camera_depth(points, pose, out)
+    return out
 
 
 def fuse_frame(vol: Volume, depth, intr, pose, net: Denoiser | None = None, den_out=None):
@@ -90,7 +92,7 @@ def make_pairs(seed_index: int, n_frames: int, workers: int = 1, vp=None):
     nrm = torch.empty_like(pts)
     for k in range(n_frames):
         vol.raycast(poses[k], K, pts, nrm)
-        targets[k] = camera_depth(pts, poses[k])
+        camera_depth(pts, poses[k], out=targets[k])
     vol.close()
     return d, targets
 

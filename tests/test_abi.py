@@ -81,3 +81,17 @@ def test_multi_workspace_size_and_validation():
     assert L.tf_multi_set_config(None, ctypes.byref(cfg)) == T.TF_E_INVAL
     assert L.tf_multi_integrate(None, None, 0, None, None, None, 0, None) == T.TF_E_INVAL
     assert L.tf_multi_raycast(None, None, 0, None) == T.TF_E_INVAL
+
+
+def test_persistence_and_camera_depth_validation():
+    """argument errors of tf_save / tf_load / tf_camera_depth, caught on the host"""
+    import paper_1708_00783_amd as T
+    L = T.lib()
+    assert L.tf_save(None, b"/tmp/x", None) == T.TF_E_INVAL
+    assert L.tf_load(None, b"/tmp/x", None) == T.TF_E_INVAL
+    M = (ctypes.c_float * 16)(*[1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1])
+    assert L.tf_camera_depth(None, 4, 4, M, ctypes.c_void_p(256), None) == T.TF_E_INVAL
+    assert L.tf_camera_depth(ctypes.c_void_p(256), 0, 4, M, ctypes.c_void_p(256), None) == T.TF_E_INVAL
+    assert L.tf_camera_depth(ctypes.c_void_p(264), 4, 4, M, ctypes.c_void_p(256), None) == T.TF_E_INVAL
+    assert L.tf_camera_depth(ctypes.c_void_p(256), 4, 4, None, ctypes.c_void_p(256), None) == T.TF_E_INVAL
+    assert L.tf_status_string(T.TF_E_IO) == b"file error or not a volume of these parameters"

@@ -42,11 +42,17 @@ def _state(vol_o=None, vol_g=None):
     return res
 
 
-def test_swapping_parity_walk():
+# 2^21 buckets: the ordered swap-out selection scans 513 chunks of 4096
+# entries, so its single-workgroup scan carries offsets across two passes of
+# 256 chunks (the entries of the walk's blocks spread over all of them)
+@pytest.mark.parametrize("n_buckets", [None, 1 << 21])
+def test_swapping_parity_walk(n_buckets):
     from oracle import oracle as O
     import paper_1708_00783_amd as T
     frames, K, VP = _walk()
-    budget = VolumeParams(VP.voxel_size, VP.mu, VP.max_w, VP.n_buckets, VP.n_excess, 5000)
+    nb = n_buckets or VP.n_buckets
+    print(f"case swap walk, {nb} buckets", flush=True)
+    budget = VolumeParams(VP.voxel_size, VP.mu, VP.max_w, nb, VP.n_excess, 5000)
     o = O.Volume.from_params(budget)
     o.enable_swap(4096)
     g = T.Volume(budget, K.width, K.height, swap_transfer_blocks=4096)
@@ -118,3 +124,59 @@ def test_transfer_overflow_merge_parity():
     for key in a:
         assert np.array_equal(a[key][1], b[key][1]), key
         assert np.abs(a[key][0].astype(int) - b[key][0].astype(int)).max() <= 1, key
+
+
+def test_swap_out_merges_pending_host_copies():
+    """Blocks swapped out, then touched again: they get fresh device blocks
+    at once while their host copies come back at most 40 per frame.  Swapping
+    everything out again two frames later catches most of them with the host
+    copy still pending: the secondary integration (Sec. 5) then fuses the
+    device copy into the store copy on the device.  Final voxels by position
+    (device or host copy): weights bit-exact, SDF within 1 LSB of the oracle."""
+    from oracle import oracle as O
+    import paper_1708_00783_amd as T
+    from synth import configs, look_at
+    vp = configs.C1_VOLUME
+    K = configs.C1_INTR
+    pose = np.eye(4, dtype=np.float32)
+    plane = lambda z: np.full((K.height, K.width), z, np.float32)
+    sky = look_at([0.0, 0.0, 0.0], [0.0, 0.0, -5.0], up=(0.0, 1.0, 0.0)).astype(np.float32)
+    o = O.Volume.from_params(vp)
+    o.enable_swap(40)
+    g = T.Volume(vp, K.width, K.height, swap_transfer_blocks=40)
+    seq = [(plane(1.0), pose, True)] * 3 + [(plane(0.0), sky, False)] + [(plane(1.02), pose, True)] * 2 + \
+          [(plane(0.0), sky, False)] + [(plane(0.0), pose, False)] * 3
+    pending_at_swap = 0
+    for k, (d, P, integ) in enumerate(seq):
+        o.alloc_and_visible(d, K.as_array(), P)
+        dd = to_device(d)
+        g.alloc_and_visible(dd, K, P)
+        assert g.stats()["n_swapped_in"] == o.n_swapped_in, k
+        if integ:
+            o.integrate(d, K.as_array(), P)
+            g.integrate(dd, P)
+        if k in (3, 6):
+            if k == 6:
+                _, _, ptr = g.entries()
+                dev = np.flatnonzero(ptr >= 0).astype(np.int32)
+                pending_at_swap = int(g.host_voxels(dev)[2].sum())
+            while o.swap_out():
+                pass
+            for _ in range(500):
+                g.swap_out()
+                if g.stats()["n_swapped_out"] == 0:
+                    break
+            _, _, ptr = g.entries()
+            assert (ptr >= 0).sum() == 0, k
+    assert pending_at_swap > 100, pending_at_swap
+    a = _state(vol_o=o)
+    b = _state(vol_g=g)
+    assert a.keys() == b.keys()
+    n_lsb = 0
+    for key in a:
+        assert np.array_equal(a[key][1], b[key][1]), key
+        dsdf = np.abs(a[key][0].astype(int) - b[key][0].astype(int))
+        assert dsdf.max() <= 1, key
+        n_lsb += int((dsdf > 0).sum())
+    print(f"pending host copies merged at swap-out: {pending_at_swap}; blocks {len(a)}; "
+          f"1-LSB SDF differences {n_lsb}", flush=True)

@@ -56,3 +56,21 @@ def folded_backward_data(g, f):
                     # output m' feeds source m' + py - 1 + a (padded index + 1)
                     dx[:, py + a:py + a + Hs, px + b:px + b + Ws] += gp @ f[py, px, :, a, b, :].astype(np.float64)
     return dx[:, 1:-1, 1:-1]
+
+
+def split_fold(w, to_bf16):
+    """the decoder kernels' weight operands: the fold of the bf16-rounded
+    taps summed in float32 (ascending ky, kx), then split into bf16 halves
+    hi = bf16(s), lo = bf16(s - hi).  Returns (s, hi, lo), float32 arrays of
+    fold's shape; `to_bf16` rounds float32 to bf16 values (nearest even)."""
+    wb = to_bf16(np.asarray(w, np.float32))
+    s = fold(wb, np.float32)
+    hi = to_bf16(s)
+    lo = to_bf16((s - hi).astype(np.float32))
+    return s, hi, lo
+
+
+def taps_per_offset():
+    """(2, 2, 2, 2) counts of the 3x3 taps landing on source offset (a, b)
+    for output parity (py, px)"""
+    return fold(np.ones((1, 9, 1))).reshape(2, 2, 2, 2)
