@@ -51,7 +51,8 @@ def _setup(seed=0, shape=(N, H, W)):
     depth = np.stack([1.2 + 1.5 * n + 0.3 * np.sin(xx / (7.0 + n)) + 0.2 * np.cos(yy / 5.0) for n in range(nb)])
     depth = (depth + rng.normal(0, 0.004, depth.shape)).astype(np.float32)
     depth[0, 5:9, 10:20] = 0.0
-    depth[1, :, :3] = 0.0
+    if nb > 1:
+        depth[1, :, :3] = 0.0
     target = (depth + rng.normal(0, 0.02, depth.shape)).astype(np.float32)
     target[0, 20:24] = 0.0
     net = T.Denoiser(nb, h, w, training=True)

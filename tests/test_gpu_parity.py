@@ -217,7 +217,7 @@ def test_tile_bins_overflow_fall_back_to_all_records():
     assert n_alloc > 4 * 512
     gp, gn, op, on = pair.raycast(Kt, p[3])          # another view: all blocks
     nhit, flips = compare_raycast(gp, gn, op, on, "overflowing bins, all blocks")
-    assert nhit > 100
+    assert nhit > 20          # the fused patch covers a small part of the wide view
     gz0, gz1 = pair.g.range_image(p[2], Kt)
     oz0, oz1 = pair.o.range_image(Kt.width, Kt.height, Kt.as_array(), p[2], blocks="all")
     assert np.array_equal(gz0.cpu().numpy(), oz0) and np.array_equal(gz1.cpu().numpy(), oz1)
