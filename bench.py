@@ -5,14 +5,20 @@ One step = one depth frame through the whole path: tf_alloc_and_visible
 from the frame's pose.  Workload: the full-frame configuration -- 640x480
 uint16 depth of a seeded 4x4x3 m room with 20 primitives and Kinect-like
 noise, voxel 5 mm, mu 2 cm, 2^20 buckets + 2^17 excess slots, 2^18 blocks,
-along a 300-frame seeded trajectory (frame index wraps modulo 300).
+along a 300-frame seeded trajectory.
 
-Inputs are generated and uploaded to HBM before timing.  W warm-up frames,
-then K timed frames bracketed by device synchronisation.  Per-kernel device
-time comes from HIP events the library records on its launch stream during
-the timed frames; algorithmic bytes from the library's device-side work
-counters.  The CPU baseline times the oracle on a bounded prefix of the same
-trajectory on the host cores.
+Inputs are generated and uploaded to HBM before timing.  The whole trajectory
+is fused in order: an untimed prefix, W warm-up frames, then the K timed
+frames (the trajectory's last K, so the map has its configured size),
+bracketed by device synchronisation.  Per-kernel device time comes from HIP
+events the library records on its launch stream during the timed frames;
+algorithmic bytes from the library's device-side work counters.  The CPU
+baseline times the oracle on a bounded prefix of the same trajectory on the
+host cores, with all granted threads and with one.
+
+The second half of the metric (denoised vs plain at equal surface error)
+follows in `extra.c5`: the prefilter is trained on pairs the method makes
+from seeded rooms and both paths fuse held-out rooms (`--no-c5` skips it).
 
 Prints one JSON line.
 """
@@ -41,10 +47,11 @@ KERNEL_SOURCES = ("paper_1708_00783_amd/csrc/tsdf_device.h", "paper_1708_00783_a
                   "paper_1708_00783_amd/csrc/tsdf_internal.h")
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, timed=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 summaries
-    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), only if they were taken with
-    the current kernel sources; else None"""
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated, averaged over the dispatches of
+    the timed frames), only if they were taken with the current kernel sources
+    and over the same timed frame range `timed` = (first, last); else None"""
     import glob
     import hashlib
     import re
@@ -53,11 +60,12 @@ def measured_traffic(kernel):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     sha = h.hexdigest()[:16]
+    want = f"{timed[0]}-{timed[1]}" if timed else None
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(f):
-            m = re.match(r"traffic (\S+) ([0-9a-f]{16}) (\d+)", line.strip())
+            m = re.match(r"traffic (\S+) ([0-9a-f]{16}) (\d+)(?: frames=(\d+-\d+))?$", line.strip())
             # the trace names a template instance (k_raycast<true>); match the kernel
-            if m and m.group(1).split("<")[0] == kernel and m.group(2) == sha:
+            if m and m.group(1).split("<")[0] == kernel and m.group(2) == sha and m.group(4) == want:
                 return int(m.group(3))
     return None
 
@@ -118,11 +126,19 @@ def cpu_cores():
         return os.cpu_count() or 1
 
 
-def cpu_baseline(frames, poses, K, budget_s=20.0, max_frames=150):
-    """Oracle frames/s on a prefix of the trajectory (bounded wall time)."""
+def cpu_threads():
+    """threads for the oracle: the cores this process may run on, capped by
+    OMP_NUM_THREADS when the host sets it (a shared GPU host grants a share)"""
+    n = cpu_cores()
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return n
+
+
+def _oracle_fps(frames, poses, K, threads, budget_s, max_frames):
     from oracle import oracle as O
     from synth import configs
-    threads = min(cpu_cores(), 16)
     O.set_threads(threads)
     vol = O.Volume.from_params(configs.C2_VOLUME)
     intr = K.as_array()
@@ -137,9 +153,32 @@ def cpu_baseline(frames, poses, K, budget_s=20.0, max_frames=150):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "frames/s", "cores": O.get_threads(), "kind": "oracle",
+    return n / dt, n, dt, O.get_threads()
+
+
+def cpu_baseline(frames, poses, K, budget_s=12.0, max_frames=150):
+    """Oracle frames/s on a prefix of the trajectory (bounded wall time), with
+    all granted host threads and with one thread."""
+    fps, n, dt, used = _oracle_fps(frames, poses, K, cpu_threads(), budget_s, max_frames)
+    fps1, n1, dt1, _ = _oracle_fps(frames, poses, K, 1, budget_s, max_frames)
+    return {"value": fps, "unit": "frames/s", "cores": used, "kind": "oracle",
             "sample": f"first {n} frames of the same trajectory (alloc+integrate+raycast each), "
-                      f"{dt:.1f} s on the host"}
+                      f"{dt:.1f} s on the host",
+            "one_thread": {"value": fps1, "cores": 1,
+                           "sample": f"first {n1} frames of the same trajectory, {dt1:.1f} s"},
+            "host_cores_visible": cpu_cores(),
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS"),
+            "cpu_model": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 C4_BIN_CAP = 1 << 27      # (block, tile) entries of one raycast call over its 8 views (4 GiB)
@@ -368,12 +407,17 @@ C5_COVERAGE = 0.95
 
 
 def run_c5(args):
+    print(json.dumps(c5_result(args)), flush=True)
+
+
+def c5_result(args):
     """Train the prefilter on pairs the method makes itself (fused-model
     raycasts as targets), then fuse held-out rooms with raw and with denoised
     depth: e* = raw surface RMS with all frames fused; N_d = the smallest
     frame count (every k-th frame of the whole trajectory) at which the
     denoised RMS <= e*; report the time each path takes."""
     from synth import configs
+    t_all = time.perf_counter()
     tr_seeds = list(range(5000, 5000 + args.c5_rooms))
     ev_seeds = list(range(6000, 6000 + args.c5_eval_rooms))
     nf, ne = args.c5_frames, args.c5_eval_frames
@@ -479,8 +523,29 @@ def run_c5(args):
                     "also needs >= 95% of the raw path's evaluation hits at N = 300",
         "train": {"loss_curve": [(a, round(b, 6)) for a, b, _ in losses], "seconds": round(t_train, 2),
                   "pairs_seconds": round(t_pairs, 2), "render_seconds": round(t_render, 2)},
+        "seconds": round(time.perf_counter() - t_all, 1),
     }
-    print(json.dumps(out), flush=True)
+    return out
+
+
+# the equal-error half of the headline, run after the frame-rate half: a
+# protocol sized to finish in about two minutes on a 16-core host share
+C5_IN_C2 = {"c5_rooms": 50, "c5_frames": 40, "c5_steps": 2000, "c5_eval_rooms": 4, "c5_eval_frames": 300}
+
+
+def c5_summary(args):
+    a = argparse.Namespace(**vars(args))
+    for k, v in C5_IN_C2.items():
+        setattr(a, k, v)
+    a.c5_save = None
+    r = c5_result(a)
+    keep = ("value", "unit", "config", "e_star_mm", "n_d", "t_plain_s", "t_denoised_s", "frames_per_s_plain",
+            "frames_per_s_denoised", "rms_mm", "median_over_rooms", "eval_hits", "protocol", "seconds")
+    out = {k: r[k] for k in keep}
+    out["metric"] = "denoised vs plain at equal surface RMS error: T_plain(300 frames) / T_denoised(N_d frames)"
+    out["train_seconds"] = r["train"]["seconds"]
+    out["final_loss"] = r["train"]["loss_curve"][-1][1] if r["train"]["loss_curve"] else None
+    return out
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0
@@ -555,6 +620,7 @@ def main():
     ap.add_argument("--steps", type=int, default=270)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c5", action="store_true", help="c2: skip the equal-error (prefilter) half")
     ap.add_argument("--workers", type=int, default=min(16, cpu_cores()))
     ap.add_argument("--frames-cache", default=None,
                     help="npy file holding the generated depth frames (written if absent)")
@@ -597,11 +663,29 @@ def main():
         return run_c5(args)
     if args.workload == "prefilter":
         return run_prefilter(args)
+    line = run_c2(args)
+    if not args.no_c5:
+        print("[bench] equal-error half: training and evaluating the prefilter", file=sys.stderr, flush=True)
+        line["extra"]["c5"] = c5_summary(args)
+    print(json.dumps(line), flush=True)
+
+
+def c2_schedule(warmup, steps, n_traj=N_TRAJ):
+    """trajectory frame index of every fused frame: an untimed prefix so that
+    the timed frames are the trajectory's last `steps` (the map at its
+    configured size), then `warmup`, then the timed frames; with more than
+    n_traj frames in all, indices wrap (the pose jumps back to the start)"""
+    prefill = max(0, n_traj - warmup - steps)
+    order = [i % n_traj for i in range(prefill + warmup + steps)]
+    return prefill, order
+
+
+def run_c2(args):
     from synth import configs
     K = configs.KINECT_INTR
-    n_frames = min(N_TRAJ, args.warmup + args.steps)
-    print(f"[bench] generating {n_frames} frames", file=sys.stderr, flush=True)
-    frames = make_frames(n_frames, args.workers, args.frames_cache)
+    prefill, order = c2_schedule(args.warmup, args.steps)
+    print(f"[bench] generating {N_TRAJ} frames", file=sys.stderr, flush=True)
+    frames = make_frames(N_TRAJ, args.workers, args.frames_cache)
     poses = np.stack(configs.c2_poses(N_TRAJ)).astype(np.float32)
 
     import torch
@@ -614,10 +698,10 @@ def main():
     nrm = torch.empty_like(pts)
 
     def step(i):
-        f = i % n_frames
-        vol.frame(d_frames[f], K, poses[i % N_TRAJ], pts, nrm, stream)
+        f = order[i]
+        vol.frame(d_frames[f], K, poses[f], pts, nrm, stream)
 
-    for i in range(args.warmup):
+    for i in range(prefill + args.warmup):
         step(i)
     torch.cuda.synchronize()
     s0 = vol.stats()
@@ -628,10 +712,12 @@ def main():
     vol.profile_enable(True)
     vol.profile_select(("integrate", "raycast"), PROFILE_EVERY)
     vol.profile_read(reset=True)
-    print(f"[bench] warm-up done ({args.warmup} frames), timing {args.steps}", file=sys.stderr, flush=True)
+    t_first, t_last = order[prefill + args.warmup], order[-1]
+    print(f"[bench] prefix {prefill} + warm-up {args.warmup} frames fused, timing {args.steps} "
+          f"(trajectory frames {t_first}..{t_last})", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.warmup, args.warmup + args.steps):
+    for i in range(prefill + args.warmup, len(order)):
         step(i)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -657,8 +743,10 @@ def main():
     total_ms = {k: v["ms"] for k, v in prof.items()}
     dominant = max(("integrate", "raycast"), key=lambda k: total_ms[k])
     rk = kern[dominant]
+    timed = (t_first, t_last)
     roofline = {"bound": "hbm", "achieved": round(rk["gbs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(rk["gbs"] / HBM_PEAK_GBS, 5), "traffic": measured_traffic("k_" + dominant),
+                "frac": round(rk["gbs"] / HBM_PEAK_GBS, 5),
+                "traffic": measured_traffic("k_" + dominant, timed),
                 "kernel": dominant,
                 "algorithmic_bytes_per_launch": int(rk["bytes"]),
                 "avg_launch_ms": round(rk["avg_ms"], 5)}
@@ -668,7 +756,7 @@ def main():
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         cpu = cpu_baseline(frames, poses, K)
 
-    out = {
+    return {
         "metric": METRIC, "value": round(fps, 3), "unit": "frames/s", "n_gpus": 1,
         "steps": steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -676,7 +764,9 @@ def main():
         "config": {"workload": "full frame: 640x480 uint16 depth, 4x4x3 m room with 20 primitives, "
                                "Kinect-like noise, voxel 5 mm, mu 2 cm, 2^20 buckets + 2^17 excess, "
                                "2^18 blocks; alloc+integrate+raycast per frame",
-                   "frames": N_TRAJ, "width": K.width, "height": K.height},
+                   "trajectory_frames": N_TRAJ, "frames_fused": len(order), "prefill_frames": prefill,
+                   "warmup_frames": args.warmup, "timed_frames": [t_first, t_last],
+                   "width": K.width, "height": K.height},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": {
@@ -693,7 +783,6 @@ def main():
             "allocated_blocks": s1["n_allocated"],
         },
     }
-    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

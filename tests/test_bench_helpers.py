@@ -30,3 +30,31 @@ def test_traffic_lookup_matches_template_instances_and_source_hash(tmp_path, mon
     assert bench.measured_traffic("k_integrate") is None      # taken with other sources
     assert bench.measured_traffic("k_alloc_rays") is None     # not in any summary
 
+
+
+def test_traffic_lookup_needs_the_same_timed_frames(tmp_path, monkeypatch):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    sha = _sha()
+    (prof / "x.md").write_text(f"traffic k_raycast {sha} 555 frames=280-299\n"
+                               f"traffic k_integrate {sha} 777 frames=30-299\n")
+    real_root = bench.ROOT
+    for f in bench.KERNEL_SOURCES:
+        dst = tmp_path / f
+        dst.parent.mkdir(parents=True, exist_ok=True)
+        dst.write_bytes(open(os.path.join(real_root, f), "rb").read())
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("k_raycast", (280, 299)) == 555
+    assert bench.measured_traffic("k_raycast", (30, 299)) is None
+    assert bench.measured_traffic("k_integrate", (30, 299)) == 777
+    assert bench.measured_traffic("k_raycast") is None        # a range-keyed figure needs a range
+
+
+def test_schedule_fuses_the_whole_trajectory_and_times_its_end():
+    pre, order = bench.c2_schedule(5, 20)
+    assert pre == 275 and order == list(range(300))
+    assert order[pre + 5] == 280 and order[-1] == 299
+    pre, order = bench.c2_schedule(30, 270)
+    assert pre == 0 and order[30] == 30 and order[-1] == 299
+    pre, order = bench.c2_schedule(100, 300)       # more frames than the trajectory: wraps
+    assert pre == 0 and len(order) == 400 and order[300] == 0 and order[-1] == 99
