@@ -205,6 +205,35 @@ def analytic_sdf(scene: Scene, pts: np.ndarray) -> np.ndarray:
     return s
 
 
+def render_points_normals(scene: Scene, pose_w2c: np.ndarray, intr: Intrinsics, h: float = 1e-5):
+    """Exact surface point and normal maps of a view, float32 (H, W, 4) each,
+    world frame, w = 1 where the noiseless depth is valid: the point is the
+    rendered depth's ray point, the normal the normalised gradient of the
+    analytic signed distance there (central differences, step h).  A synthetic
+    stand-in for a perfect model's raycast."""
+    M = np.asarray(pose_w2c, np.float64)
+    R, t = M[:3, :3], M[:3, 3]
+    z = render_depth(scene, M, intr)
+    cam = pixel_rays(intr) * z[..., None]
+    world = (cam.reshape(-1, 3) - t) @ R          # R^T (X - t), row-wise
+    ok = z.reshape(-1) > 0
+    g = np.zeros_like(world)
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        g[:, a] = (analytic_sdf(scene, world + e) - analytic_sdf(scene, world - e)) / (2 * h)
+    nrm = np.linalg.norm(g, axis=1)
+    ok &= nrm > 0
+    n = g / np.where(nrm > 0, nrm, 1.0)[:, None]
+    V = np.zeros((world.shape[0], 4), np.float32)
+    N = np.zeros((world.shape[0], 4), np.float32)
+    V[ok, :3] = world[ok]
+    V[ok, 3] = 1.0
+    N[ok, :3] = n[ok]
+    N[ok, 3] = 1.0
+    return V.reshape(intr.height, intr.width, 4), N.reshape(intr.height, intr.width, 4)
+
+
 # ----------------------------------------------------------------------------
 # sensor noise
 # ----------------------------------------------------------------------------
