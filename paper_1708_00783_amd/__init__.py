@@ -39,6 +39,8 @@ EXPORTS = (
     # include/tsdf_nn.h
     "tf_nn_param_count", "tf_nn_workspace_bytes", "tf_nn_create", "tf_nn_destroy", "tf_nn_set_params",
     "tf_nn_get_params", "tf_nn_forward", "tf_nn_backward", "tf_nn_adam_step", "tf_nn_tensor",
+    # include/tsdf_track.h
+    "tf_track_workspace_bytes", "tf_track",
 )
 
 
@@ -97,6 +99,16 @@ class tf_multi_stats(ctypes.Structure):
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class tf_track_params(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("iterations", ctypes.c_int32 * 4),
+                ("dist_thresh", ctypes.c_float * 4), ("min_update", ctypes.c_float)]
+
+
+class tf_track_result(ctypes.Structure):
+    _fields_ = [("pose_w2c", ctypes.c_float * 16), ("iterations", ctypes.c_int32 * 4), ("pairs", ctypes.c_int32 * 4),
+                ("status", ctypes.c_int32), ("pad", ctypes.c_int32), ("sums", (ctypes.c_double * 28) * 4)]
 
 
 class TsdfError(RuntimeError):
@@ -175,6 +187,9 @@ def lib():
             "tf_nn_adam_step": (ctypes.c_int, [_VP, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                                ctypes.c_float, _VP]),
             "tf_nn_tensor": (ctypes.c_int, [_VP, ctypes.c_int, P(_VP), P(ctypes.c_int32)]),
+            "tf_track_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+            "tf_track": (ctypes.c_int, [_VP, ctypes.c_int, P(tf_intrinsics), _VP, _VP, P(tf_intrinsics), _F16, _F16,
+                                        P(tf_track_params), _VP, ctypes.c_size_t, _VP, _VP]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -674,3 +689,59 @@ def bf16_bits_to_float(t):
     """int16 bf16 bit patterns (torch) -> float32 numpy"""
     a = t.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
     return a.view(np.float32)
+
+
+# ---- depth tracker -------------------------------------------------------------------
+
+def make_track_params(iterations=(4, 5, 10), dist_thresh=(0.1, 0.2, 0.3), min_update=0.0) -> tf_track_params:
+    """per-level iterations and distance thresholds, index 0 = finest"""
+    assert len(iterations) == len(dist_thresh) and 1 <= len(iterations) <= 4
+    p = tf_track_params()
+    p.n_levels = len(iterations)
+    for l, (n, d) in enumerate(zip(iterations, dist_thresh)):
+        p.iterations[l] = int(n)
+        p.dist_thresh[l] = float(d)
+    p.min_update = float(min_update)
+    return p
+
+
+def parse_track_result(raw) -> dict:
+    """tf_track_result bytes (numpy uint8) -> dict"""
+    r = tf_track_result.from_buffer_copy(np.ascontiguousarray(raw, np.uint8).tobytes())
+    return {"pose_w2c": np.array(r.pose_w2c, np.float32).reshape(4, 4),
+            "iterations": list(r.iterations), "pairs": list(r.pairs), "status": int(r.status),
+            "sums": np.array([list(x) for x in r.sums], np.float64)}
+
+
+class Tracker:
+    """The depth tracker for depth images of width x height on the current
+    HIP device: owns its workspace and a device result buffer."""
+
+    def __init__(self, width, height, n_levels=3):
+        import torch
+        nbytes = int(lib().tf_track_workspace_bytes(width, height, n_levels))
+        if nbytes == 0:
+            raise TsdfError("invalid tracker size")
+        self.W, self.H, self.L = width, height, n_levels
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.result = torch.empty(ctypes.sizeof(tf_track_result), dtype=torch.uint8, device="cuda")
+
+    def track_async(self, depth, intr, ref_points, ref_normals, ref_intr, ref_pose, init_pose, params,
+                    stream=None):
+        """enqueue one tracking call; the result lands in self.result"""
+        fmt = TF_DEPTH_U16_MM if depth.dtype.itemsize == 2 else TF_DEPTH_F32_M
+        K, Kr = make_intrinsics(intr), make_intrinsics(ref_intr)
+        _, Mr = _pose_arg(ref_pose)
+        _, Mi = _pose_arg(init_pose)
+        check(lib().tf_track(ctypes.c_void_p(depth.data_ptr()), fmt, ctypes.byref(K),
+                             ctypes.c_void_p(ref_points.data_ptr()), ctypes.c_void_p(ref_normals.data_ptr()),
+                             ctypes.byref(Kr), Mr, Mi, ctypes.byref(params),
+                             ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                             ctypes.c_void_p(self.result.data_ptr()), _stream_ptr(stream)), "tf_track")
+
+    def track(self, depth, intr, ref_points, ref_normals, ref_intr, ref_pose, init_pose, params=None,
+              stream=None) -> dict:
+        """one tracking call, then the result (synchronises)"""
+        params = params or make_track_params()
+        self.track_async(depth, intr, ref_points, ref_normals, ref_intr, ref_pose, init_pose, params, stream)
+        return parse_track_result(self.result.cpu().numpy())

@@ -7,19 +7,11 @@ and a known synthetic trajectory recovered frame by frame."""
 import numpy as np
 
 from oracle import track as TR
+from pose_helpers import pose_error
 from synth import configs, scenes
 from synth.scenes import Intrinsics, Scene, look_at, render_depth
 
 K_HALF = Intrinsics(262.5, 262.5, 159.75, 119.75, 320, 240)
-
-
-def pose_error(A, B):
-    """(translation error in m, rotation angle in degrees) of two world->camera poses"""
-    Ra, ta = TR.invert_pose(A)
-    Rb, tb = TR.invert_pose(B)
-    dR = Ra @ Rb.T
-    w = np.array([dR[2, 1] - dR[1, 2], dR[0, 2] - dR[2, 0], dR[1, 0] - dR[0, 1]]) / 2
-    return float(np.linalg.norm(ta - tb)), float(np.degrees(np.arcsin(min(1.0, np.linalg.norm(w)))))
 
 
 def test_pyramid_levels_by_brute_force():
