@@ -87,6 +87,26 @@ int tf_track(const void *d_depth, int depth_format, const tf_intrinsics *intr, c
              const float init_pose_w2c[16], const tf_track_params *params, void *d_workspace,
              size_t workspace_bytes, tf_track_result *d_result, tf_stream stream);
 
+/* Largest workspace tf_track_noalloc can serve (8 MiB: e.g. 1280x1024 depth
+ * with four levels). */
+#define TF_TRACK_NOALLOC_MAX_BYTES (8u << 20)
+
+/* tf_track for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same computation and result, bit for bit, with the workspace taken from a
+ * fixed device array of TF_TRACK_NOALLOC_MAX_BYTES that the library holds on
+ * every GPU it runs on until the process ends (looked up on the first call on
+ * a device).  Allocates nothing.  Every call on one GPU shares that array:
+ * calls that overlap on one GPU (different streams, or threads without
+ * ordering) race and must not be issued; calls in one stream order are safe
+ * (each call initialises what it reads).  TF_E_SPACE when
+ * tf_track_workspace_bytes(width, height, n_levels) exceeds the array; other
+ * errors as tf_track. */
+int tf_track_noalloc(const void *d_depth, int depth_format, const tf_intrinsics *intr, const float *d_ref_points,
+                     const float *d_ref_normals, const tf_intrinsics *ref_intr, const float ref_pose_w2c[16],
+                     const float init_pose_w2c[16], const tf_track_params *params, tf_track_result *d_result,
+                     tf_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

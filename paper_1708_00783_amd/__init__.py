@@ -40,7 +40,7 @@ EXPORTS = (
     "tf_nn_param_count", "tf_nn_workspace_bytes", "tf_nn_create", "tf_nn_destroy", "tf_nn_set_params",
     "tf_nn_get_params", "tf_nn_forward", "tf_nn_backward", "tf_nn_adam_step", "tf_nn_tensor",
     # include/tsdf_track.h
-    "tf_track_workspace_bytes", "tf_track",
+    "tf_track_workspace_bytes", "tf_track", "tf_track_noalloc",
 )
 
 
@@ -190,6 +190,8 @@ def lib():
             "tf_track_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
             "tf_track": (ctypes.c_int, [_VP, ctypes.c_int, P(tf_intrinsics), _VP, _VP, P(tf_intrinsics), _F16, _F16,
                                         P(tf_track_params), _VP, ctypes.c_size_t, _VP, _VP]),
+            "tf_track_noalloc": (ctypes.c_int, [_VP, ctypes.c_int, P(tf_intrinsics), _VP, _VP, P(tf_intrinsics),
+                                                _F16, _F16, P(tf_track_params), _VP, _VP]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -745,3 +747,20 @@ class Tracker:
         params = params or make_track_params()
         self.track_async(depth, intr, ref_points, ref_normals, ref_intr, ref_pose, init_pose, params, stream)
         return parse_track_result(self.result.cpu().numpy())
+
+
+TF_TRACK_NOALLOC_MAX_BYTES = 8 << 20
+
+
+def tf_track_noalloc(depth, intr, ref_points, ref_normals, ref_intr, ref_pose, init_pose, params, result,
+                     stream=None):
+    """tf_track on the library's fixed device workspace (no allocation);
+    `result`: device buffer of sizeof(tf_track_result) bytes"""
+    fmt = TF_DEPTH_U16_MM if depth.dtype.itemsize == 2 else TF_DEPTH_F32_M
+    K, Kr = make_intrinsics(intr), make_intrinsics(ref_intr)
+    _, Mr = _pose_arg(ref_pose)
+    _, Mi = _pose_arg(init_pose)
+    check(lib().tf_track_noalloc(ctypes.c_void_p(depth.data_ptr()), fmt, ctypes.byref(K),
+                                 ctypes.c_void_p(ref_points.data_ptr()), ctypes.c_void_p(ref_normals.data_ptr()),
+                                 ctypes.byref(Kr), Mr, Mi, ctypes.byref(params), ctypes.c_void_p(result.data_ptr()),
+                                 _stream_ptr(stream)), "tf_track_noalloc")

@@ -12,6 +12,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "tsdf_track.h"
 
 namespace {
@@ -443,7 +445,50 @@ int tsdf_track_impl(const void *d_depth, int depth_format, const tf_intrinsics *
     return hipGetLastError() == hipSuccess ? TF_OK : TF_E_HIP;
 }
 
+// The workspace of tf_track_noalloc: a fixed device array, one copy per GPU,
+// held until the process ends.  Host code never passes `scratch` itself to a
+// kernel (in host code the name is not a device address); it passes the
+// address hipGetSymbolAddress returns for the current device.
+namespace {
+constexpr size_t kScratchBytes = (size_t)TF_TRACK_NOALLOC_MAX_BYTES;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices];
+
+// the current device's copy of `scratch`, looked up once per device
+int scratch_address(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return TF_E_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return TF_E_HIP;
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return TF_OK;
+}
+}  // namespace
+
 extern "C" {
+
+int tf_track_noalloc(const void *d_depth, int depth_format, const tf_intrinsics *intr, const float *d_ref_points,
+                     const float *d_ref_normals, const tf_intrinsics *ref_intr, const float ref_pose_w2c[16],
+                     const float init_pose_w2c[16], const tf_track_params *params, tf_track_result *d_result,
+                     tf_stream stream)
+{
+    if (!intr || !params) return TF_E_INVAL;
+    const size_t need = tf_track_workspace_bytes(intr->width, intr->height, params->n_levels);
+    if (need == 0) return TF_E_INVAL;
+    if (need > kScratchBytes) return TF_E_SPACE;
+    void *ws = nullptr;
+    const int st = scratch_address(&ws);
+    if (st != TF_OK) return st;
+    return tsdf_track_impl(d_depth, depth_format, intr, d_ref_points, d_ref_normals, ref_intr, ref_pose_w2c,
+                           init_pose_w2c, params, ws, kScratchBytes, d_result, stream);
+}
 
 size_t tf_track_workspace_bytes(int32_t width, int32_t height, int32_t n_levels)
 {
