@@ -404,6 +404,7 @@ def render_rooms(seeds, n, workers, tag):
 
 
 C5_COVERAGE = 0.95
+C5_BILATERAL = (2, 2.5, 0.025)     # radius (px), sigma_space (px), sigma_range (m)
 
 
 def run_c5(args):
@@ -463,10 +464,12 @@ def c5_result(args):
     inf = T.Denoiser(1, K.height, K.width)
     inf.set_params(params)
     # held-out rooms, equal-coverage protocol (every k-th frame of the whole trajectory)
-    res = {"raw": [], "denoised": []}
+    # the paper's own prefilter, the bilateral filter, as the comparator
+    bil = T.Bilateral(K.height, K.width, *C5_BILATERAL)
+    res = {"raw": [], "denoised": [], "bilateral": []}
     for i, s in enumerate(ev_seeds):
         d = torch.from_numpy(eval_frames[i]).cuda()
-        for name, nn in (("raw", None), ("denoised", inf)):
+        for name, nn in (("raw", None), ("denoised", inf), ("bilateral", bil)):
             res[name].append(PF.evaluate_room(s, d, nn))
         print(f"[bench] c5: room {s}: raw {res['raw'][-1][ne][0] * 1e3:.3f} mm, denoised "
               f"{res['denoised'][-1][ne][0] * 1e3:.3f} mm with all {ne} frames", file=sys.stderr, flush=True)
@@ -489,6 +492,10 @@ def c5_result(args):
     reach = [j for j, v in enumerate(den) if v <= e_star and hden[j] >= C5_COVERAGE * h_star]
     reach_md = [j for j, v in enumerate(den_md) if v <= raw_md[-1] and hden[j] >= C5_COVERAGE * h_star]
     nd = ns[reach[0]] if reach else None
+    bl = np.array([np.mean([r[n][0] for r in res["bilateral"]]) for n in ns])
+    tbl = np.array([np.mean([r[n][1] for r in res["bilateral"]]) for n in ns])
+    hbl = np.array([np.mean([r[n][2] for r in res["bilateral"]]) for n in ns])
+    reach_bl = [j for j, v in enumerate(bl) if v <= e_star and hbl[j] >= C5_COVERAGE * h_star]
     t_plain = float(traw[-1])
     t_den = float(tden[reach[0]]) if reach else None
     cps = ns
@@ -509,6 +516,12 @@ def c5_result(args):
         "frames_per_s_denoised": round(float(ns[-1] / tden[-1]), 2),
         "rms_mm": {"frames_fused": cps, "raw": [round(v * 1e3, 4) for v in raw],
                    "denoised": [round(v * 1e3, 4) for v in den]},
+        "bilateral": {"params": {"radius": C5_BILATERAL[0], "sigma_space_px": C5_BILATERAL[1],
+                                 "sigma_range_m": C5_BILATERAL[2]},
+                      "n_d": ns[reach_bl[0]] if reach_bl else None,
+                      "ratio": round(float(traw[-1]) / float(tbl[reach_bl[0]]), 4) if reach_bl else None,
+                      "rms_mm": [round(v * 1e3, 4) for v in bl],
+                      "frames_per_s": round(float(ns[-1] / tbl[-1]), 2)},
         "median_over_rooms": {"e_star_mm": round(float(raw_md[-1]) * 1e3, 4),
                               "n_d": ns[reach_md[0]] if reach_md else None,
                               "ratio": round(t_plain / float(tden[reach_md[0]]), 4) if reach_md else None,
@@ -540,12 +553,89 @@ def c5_summary(args):
     a.c5_save = None
     r = c5_result(a)
     keep = ("value", "unit", "config", "e_star_mm", "n_d", "t_plain_s", "t_denoised_s", "frames_per_s_plain",
-            "frames_per_s_denoised", "rms_mm", "median_over_rooms", "eval_hits", "protocol", "seconds")
+            "frames_per_s_denoised", "rms_mm", "bilateral", "median_over_rooms", "eval_hits", "protocol", "seconds")
     out = {k: r[k] for k in keep}
     out["metric"] = "denoised vs plain at equal surface RMS error: T_plain(300 frames) / T_denoised(N_d frames)"
     out["train_seconds"] = r["train"]["seconds"]
     out["final_loss"] = r["train"]["loss_curve"][-1][1] if r["train"]["loss_curve"] else None
     return out
+
+
+def run_track(args):
+    """The tracking loop of Sec. 4.1.1 on the full-frame room trajectory: each
+    frame is tracked against the raycast of the model at the previous estimate
+    (tf_track, 3 levels, 4/5/10 iterations), then fused and raycast at the new
+    estimate.  One step = track + allocate + integrate + raycast."""
+    import torch
+    import paper_1708_00783_amd as T
+    from synth import configs
+    K = configs.KINECT_INTR
+    n = min(N_TRAJ, args.warmup + args.steps + 1)
+    frames = make_frames(n, args.workers, args.frames_cache)
+    truth = np.stack(configs.c2_poses(N_TRAJ)).astype(np.float32)
+    torch.cuda.set_device(0)
+    d = torch.from_numpy(frames).cuda()
+    vol = T.Volume(configs.C2_VOLUME, K.width, K.height)
+    trk = T.Tracker(K.width, K.height, 3)
+    prm = T.make_track_params((4, 5, 10), (0.1, 0.2, 0.3))
+    pts = torch.empty((K.height, K.width, 4), dtype=torch.float32, device="cuda")
+    nrm = torch.empty_like(pts)
+    est = [truth[0]]
+    vol.frame(d[0], K, truth[0], pts, nrm)
+    ev = []
+
+    def step(k, timed):
+        if timed:
+            e = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            e[0].record()
+        trk.track_async(d[k], K, pts, nrm, K, est[-1], est[-1], prm)
+        if timed:
+            e[1].record()
+            ev.append(e)
+        # the estimate is read back for the host-side pose arguments of fusion
+        r = T.parse_track_result(trk.result.cpu().numpy())
+        est.append(r["pose_w2c"])
+        vol.frame(d[k], K, est[-1], pts, nrm)
+        return r
+
+    for k in range(1, 1 + args.warmup):
+        step(k, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pairs = []
+    for k in range(1 + args.warmup, n):
+        r = step(k, True)
+        pairs.append(r["pairs"][:3])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    steps = n - 1 - args.warmup
+    ms_track = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    Ra, Rb = est[-1][:3, :3].T, truth[n - 1][:3, :3].T
+    ta, tb = -(Ra @ est[-1][:3, 3]), -(Rb @ truth[n - 1][:3, 3])
+    drift_mm = float(np.linalg.norm(ta - tb) * 1e3)
+    # algorithmic bytes of one tracking call: per sums launch the level's depth
+    # (4 B per pixel) and the V and N gathers of every pair (32 B)
+    WH = [K.width * K.height >> (2 * l) for l in range(3)]
+    p_mean = np.mean(np.array(pairs, np.float64), axis=0)
+    its = (4, 5, 10)
+    call_bytes = sum(its[l] * (4 * WH[l] + 32 * p_mean[l]) for l in range(3)) + 6 * WH[0]
+    gbs = call_bytes / (ms_track * 1e-3) / 1e9
+    out = {
+        "metric": "tracked frames/s (point-to-plane tracking + alloc + integrate + raycast, 640x480 @5mm)",
+        "value": round(steps / dt, 3), "unit": "frames/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt / steps, 4), "higher_is_better": True, "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "full-frame room trajectory, each frame tracked against the raycast at the previous "
+                               "estimate (3 levels, 4/5/10 iterations, 0.1/0.2/0.3 m gates) and fused at the estimate",
+                   "frames": n},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "tf_track (whole call)",
+                     "algorithmic_bytes_per_call": int(call_bytes), "avg_call_ms": round(ms_track, 5)},
+        "extra": {"tf_track_ms": round(ms_track, 5), "avg_pairs_per_level": [int(v) for v in p_mean],
+                  "drift_mm_at_end": round(drift_mm, 3),
+                  "host_readback": "the estimate is copied to the host after each call (fusion takes host poses)"},
+    }
+    print(json.dumps(out), flush=True)
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0
@@ -625,7 +715,7 @@ def main():
     ap.add_argument("--frames-cache", default=None,
                     help="npy file holding the generated depth frames (written if absent)")
     ap.add_argument("--c4-tile", default="", help="c4: fixed raycast tile shape WxH instead of autotuning")
-    ap.add_argument("--workload", choices=("c2", "c3", "c4", "c5", "prefilter"), default="c2",
+    ap.add_argument("--workload", choices=("c2", "c3", "c4", "c5", "prefilter", "track"), default="c2",
                     help="c2: one volume, the headline metric; c3: the large walk with host swapping; "
                          "c4: 64 batched submaps, 8 views; "
                          "c5: train the depth prefilter, then denoised vs plain at equal surface error")
@@ -663,6 +753,8 @@ def main():
         return run_c5(args)
     if args.workload == "prefilter":
         return run_prefilter(args)
+    if args.workload == "track":
+        return run_track(args)
     line = run_c2(args)
     if not args.no_c5:
         print("[bench] equal-error half: training and evaluating the prefilter", file=sys.stderr, flush=True)

@@ -41,6 +41,8 @@ EXPORTS = (
     "tf_nn_get_params", "tf_nn_forward", "tf_nn_backward", "tf_nn_adam_step", "tf_nn_tensor",
     # include/tsdf_track.h
     "tf_track_workspace_bytes", "tf_track", "tf_track_noalloc",
+    # include/tsdf_filter.h
+    "tf_bilateral",
 )
 
 
@@ -109,6 +111,10 @@ class tf_track_params(ctypes.Structure):
 class tf_track_result(ctypes.Structure):
     _fields_ = [("pose_w2c", ctypes.c_float * 16), ("iterations", ctypes.c_int32 * 4), ("pairs", ctypes.c_int32 * 4),
                 ("status", ctypes.c_int32), ("pad", ctypes.c_int32), ("sums", (ctypes.c_double * 28) * 4)]
+
+
+class tf_bilateral_params(ctypes.Structure):
+    _fields_ = [("radius", ctypes.c_int32), ("sigma_space", ctypes.c_float), ("sigma_range", ctypes.c_float)]
 
 
 class TsdfError(RuntimeError):
@@ -190,6 +196,8 @@ def lib():
             "tf_track_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
             "tf_track": (ctypes.c_int, [_VP, ctypes.c_int, P(tf_intrinsics), _VP, _VP, P(tf_intrinsics), _F16, _F16,
                                         P(tf_track_params), _VP, ctypes.c_size_t, _VP, _VP]),
+            "tf_bilateral": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int32, ctypes.c_int32,
+                                            P(tf_bilateral_params), _VP, _VP]),
             "tf_track_noalloc": (ctypes.c_int, [_VP, ctypes.c_int, P(tf_intrinsics), _VP, _VP, P(tf_intrinsics),
                                                 _F16, _F16, P(tf_track_params), _VP, _VP]),
         }
@@ -764,3 +772,31 @@ def tf_track_noalloc(depth, intr, ref_points, ref_normals, ref_intr, ref_pose, i
                                  ctypes.c_void_p(ref_points.data_ptr()), ctypes.c_void_p(ref_normals.data_ptr()),
                                  ctypes.byref(Kr), Mr, Mi, ctypes.byref(params), ctypes.c_void_p(result.data_ptr()),
                                  _stream_ptr(stream)), "tf_track_noalloc")
+
+
+# ---- bilateral depth filter ------------------------------------------------------------
+
+def tf_bilateral(depth, out, radius=2, sigma_space=2.5, sigma_range=0.025, stream=None):
+    """bilateral filter of depth (H, W) uint16 mm or float32 m into out (H, W) float32 m"""
+    fmt = TF_DEPTH_U16_MM if depth.dtype.itemsize == 2 else TF_DEPTH_F32_M
+    H, W = int(depth.shape[-2]), int(depth.shape[-1])
+    p = tf_bilateral_params(int(radius), float(sigma_space), float(sigma_range))
+    check(lib().tf_bilateral(ctypes.c_void_p(depth.data_ptr()), fmt, W, H, ctypes.byref(p),
+                             ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), "tf_bilateral")
+    return out
+
+
+class Bilateral:
+    """The bilateral filter as a depth prefilter with the Denoiser's forward()
+    interface: (1, H, W) depth in, (1, H, W) float32 metres out."""
+
+    def __init__(self, height, width, radius=2, sigma_space=2.5, sigma_range=0.025):
+        self.H, self.W = height, width
+        self.args = (radius, sigma_space, sigma_range)
+
+    def forward(self, depth, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((1, self.H, self.W), dtype=torch.float32, device="cuda")
+        tf_bilateral(depth.reshape(self.H, self.W), out.reshape(self.H, self.W), *self.args, stream=stream)
+        return out
