@@ -43,6 +43,8 @@ EXPORTS = (
     "tf_track_workspace_bytes", "tf_track", "tf_track_noalloc",
     # include/tsdf_filter.h
     "tf_bilateral",
+    # include/tsdf_mesh.h
+    "tf_mesh_workspace_bytes", "tf_mesh",
 )
 
 
@@ -196,6 +198,8 @@ def lib():
             "tf_track_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
             "tf_track": (ctypes.c_int, [_VP, ctypes.c_int, P(tf_intrinsics), _VP, _VP, P(tf_intrinsics), _F16, _F16,
                                         P(tf_track_params), _VP, ctypes.c_size_t, _VP, _VP]),
+            "tf_mesh_workspace_bytes": (ctypes.c_size_t, [P(tf_params)]),
+            "tf_mesh": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_uint64, _VP, _VP, ctypes.c_size_t, _VP]),
             "tf_bilateral": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int32, ctypes.c_int32,
                                             P(tf_bilateral_params), _VP, _VP]),
             "tf_track_noalloc": (ctypes.c_int, [_VP, ctypes.c_int, P(tf_intrinsics), _VP, _VP, P(tf_intrinsics),
@@ -450,6 +454,23 @@ class Volume:
         pos, _, ptr = self.entries()
         p = pos[ptr >= 0].astype(np.int32)
         return p[np.lexsort((p[:, 2], p[:, 1], p[:, 0]))] if len(p) else p.reshape(0, 3)
+
+    def mesh(self, stream=None):
+        """marching-cubes mesh: (vertices (m, 3, 3) float32 world metres, edge
+        keys (m, 3) int64) on the host"""
+        import torch
+        nbytes = int(lib().tf_mesh_workspace_bytes(ctypes.byref(self.params)))
+        ws = torch.empty(max(8, nbytes), dtype=torch.uint8, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        check(lib().tf_mesh(self.ctx, None, None, 0, ctypes.c_void_p(cnt.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                            nbytes, _stream_ptr(stream)), "tf_mesh")
+        n = int(cnt.item())
+        verts = torch.empty((max(1, n), 3, 3), dtype=torch.float32, device="cuda")
+        keys = torch.empty((max(1, n), 3), dtype=torch.int64, device="cuda")
+        check(lib().tf_mesh(self.ctx, ctypes.c_void_p(verts.data_ptr()), ctypes.c_void_p(keys.data_ptr()), n,
+                            ctypes.c_void_p(cnt.data_ptr()), ctypes.c_void_p(ws.data_ptr()), nbytes,
+                            _stream_ptr(stream)), "tf_mesh")
+        return verts[:n].cpu().numpy(), keys[:n].cpu().numpy()
 
     def voxels_by_position(self):
         pos, _, ptr = self.entries()
