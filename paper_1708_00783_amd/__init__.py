@@ -45,6 +45,9 @@ EXPORTS = (
     "tf_bilateral",
     # include/tsdf_mesh.h
     "tf_mesh_workspace_bytes", "tf_mesh",
+    # include/tsdf_surfel.h
+    "tf_surfel_workspace_bytes", "tf_surfel_create", "tf_surfel_destroy", "tf_surfel_reset", "tf_surfel_fuse",
+    "tf_surfel_stats", "tf_surfel_export", "tf_surfel_export_frame",
 )
 
 
@@ -117,6 +120,11 @@ class tf_track_result(ctypes.Structure):
 
 class tf_bilateral_params(ctypes.Structure):
     _fields_ = [("radius", ctypes.c_int32), ("sigma_space", ctypes.c_float), ("sigma_range", ctypes.c_float)]
+
+
+class tf_surfel_params(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_uint32), ("max_width", ctypes.c_int32), ("max_height", ctypes.c_int32),
+                ("sigma", ctypes.c_float), ("max_depth_diff", ctypes.c_float), ("min_normal_dot", ctypes.c_float)]
 
 
 class TsdfError(RuntimeError):
@@ -198,6 +206,14 @@ def lib():
             "tf_track_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
             "tf_track": (ctypes.c_int, [_VP, ctypes.c_int, P(tf_intrinsics), _VP, _VP, P(tf_intrinsics), _F16, _F16,
                                         P(tf_track_params), _VP, ctypes.c_size_t, _VP, _VP]),
+            "tf_surfel_workspace_bytes": (ctypes.c_size_t, [P(tf_surfel_params)]),
+            "tf_surfel_create": (ctypes.c_int, [P(tf_surfel_params), _VP, ctypes.c_size_t, _VP, P(_VP)]),
+            "tf_surfel_destroy": (ctypes.c_int, [_VP]),
+            "tf_surfel_reset": (ctypes.c_int, [_VP, _VP]),
+            "tf_surfel_fuse": (ctypes.c_int, [_VP, _VP, ctypes.c_int, P(tf_intrinsics), _F16, _VP]),
+            "tf_surfel_stats": (ctypes.c_int, [_VP, P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32), _VP]),
+            "tf_surfel_export": (ctypes.c_int, [_VP, ctypes.c_uint32, _VP, _VP, _VP, _VP]),
+            "tf_surfel_export_frame": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
             "tf_mesh_workspace_bytes": (ctypes.c_size_t, [P(tf_params)]),
             "tf_mesh": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_uint64, _VP, _VP, ctypes.c_size_t, _VP]),
             "tf_bilateral": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int32, ctypes.c_int32,
@@ -821,3 +837,76 @@ class Bilateral:
             out = torch.empty((1, self.H, self.W), dtype=torch.float32, device="cuda")
         tf_bilateral(depth.reshape(self.H, self.W), out.reshape(self.H, self.W), *self.args, stream=stream)
         return out
+
+
+# ---- surfel fusion -------------------------------------------------------------------
+
+TF_FLAG_SURFEL_OVERFLOW = 0x20
+
+
+class SurfelMap:
+    """A surfel map on the current HIP device (Sec. 7.3), owning its workspace."""
+
+    def __init__(self, capacity, max_width, max_height, sigma=0.6, max_depth_diff=0.05, min_normal_dot=0.5,
+                 stream=None):
+        import torch
+        self.params = tf_surfel_params(int(capacity), int(max_width), int(max_height), float(sigma),
+                                       float(max_depth_diff), float(min_normal_dot))
+        nbytes = int(lib().tf_surfel_workspace_bytes(ctypes.byref(self.params)))
+        if nbytes == 0:
+            raise TsdfError("invalid surfel map parameters")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        h = _VP()
+        check(lib().tf_surfel_create(ctypes.byref(self.params), ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                     _stream_ptr(stream), ctypes.byref(h)), "tf_surfel_create")
+        self.h = h
+        self.last_shape = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tf_surfel_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self, stream=None):
+        check(lib().tf_surfel_reset(self.h, _stream_ptr(stream)), "tf_surfel_reset")
+
+    def fuse(self, depth, intr, pose, stream=None):
+        fmt = TF_DEPTH_U16_MM if depth.dtype.itemsize == 2 else TF_DEPTH_F32_M
+        K = make_intrinsics(intr)
+        _, Mp = _pose_arg(pose)
+        check(lib().tf_surfel_fuse(self.h, ctypes.c_void_p(depth.data_ptr()), fmt, ctypes.byref(K), Mp,
+                                   _stream_ptr(stream)), "tf_surfel_fuse")
+        self.last_shape = (K.height, K.width)
+
+    def stats(self, stream=None) -> dict:
+        n, f, fr = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        check(lib().tf_surfel_stats(self.h, ctypes.byref(n), ctypes.byref(f), ctypes.byref(fr), _stream_ptr(stream)),
+              "tf_surfel_stats")
+        return {"count": int(n.value), "flags": int(f.value), "frames": int(fr.value)}
+
+    def export(self, stream=None):
+        """(pos (n, 4), nrm (n, 4), time (n,)) on the host"""
+        import torch
+        n = self.stats(stream)["count"]
+        pos = torch.empty((max(1, n), 4), dtype=torch.float32, device="cuda")
+        nrm = torch.empty_like(pos)
+        tm = torch.empty(max(1, n), dtype=torch.int32, device="cuda")
+        check(lib().tf_surfel_export(self.h, n, ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(nrm.data_ptr()),
+                                     ctypes.c_void_p(tm.data_ptr()), _stream_ptr(stream)), "tf_surfel_export")
+        return pos[:n].cpu().numpy(), nrm[:n].cpu().numpy(), tm[:n].cpu().numpy()
+
+    def export_frame(self, stream=None):
+        """(index map, correspondences) of the last fused frame, (H, W) int32 each"""
+        import torch
+        H, W = self.last_shape
+        im = torch.empty((H, W), dtype=torch.int32, device="cuda")
+        co = torch.empty((H, W), dtype=torch.int32, device="cuda")
+        check(lib().tf_surfel_export_frame(self.h, ctypes.c_void_p(im.data_ptr()), ctypes.c_void_p(co.data_ptr()),
+                                           _stream_ptr(stream)), "tf_surfel_export_frame")
+        return im.cpu().numpy(), co.cpu().numpy()

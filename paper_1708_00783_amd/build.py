@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libtsdf.so")
-SOURCES = ["tsdf_api.hip", "tsdf_io.hip", "tsdf_kernels.hip", "tsdf_multi.hip", "tsdf_multi_api.hip", "nn_kernels.hip", "nn_api.hip", "tsdf_track.hip", "tsdf_filter.hip", "tsdf_mesh.hip"]
+SOURCES = ["tsdf_api.hip", "tsdf_io.hip", "tsdf_kernels.hip", "tsdf_multi.hip", "tsdf_multi_api.hip", "nn_kernels.hip", "nn_api.hip", "tsdf_track.hip", "tsdf_filter.hip", "tsdf_mesh.hip", "tsdf_surfel.hip"]
 OBJDIR = os.path.join(PKG, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
