@@ -620,6 +620,16 @@ def run_track(args):
     its = (4, 5, 10)
     call_bytes = sum(its[l] * (4 * WH[l] + 32 * p_mean[l]) for l in range(3)) + 6 * WH[0]
     gbs = call_bytes / (ms_track * 1e-3) / 1e9
+    # the oracle's tracking call on a bounded sample of the same inputs
+    from oracle import track as OT
+    V, N = pts.cpu().numpy(), nrm.cpu().numpy()
+    dm = frames[n - 1].astype(np.float32) / np.float32(1000.0)
+    t0 = time.perf_counter()
+    m = 0
+    while m < 5 and time.perf_counter() - t0 < 15.0:
+        OT.track(dm, K.as_array(), V, N, K.as_array(), est[-2], est[-2], [4, 5, 10], [0.1, 0.2, 0.3])
+        m += 1
+    cpu = m / (time.perf_counter() - t0)
     out = {
         "metric": "tracked frames/s (point-to-plane tracking + alloc + integrate + raycast, 640x480 @5mm)",
         "value": round(steps / dt, 3), "unit": "frames/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
@@ -631,9 +641,130 @@ def run_track(args):
         "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "tf_track (whole call)",
                      "algorithmic_bytes_per_call": int(call_bytes), "avg_call_ms": round(ms_track, 5)},
+        "cpu_baseline": {"value": round(cpu, 3), "unit": "tracking calls/s", "cores": 1, "kind": "oracle",
+                         "sample": f"{m} calls of the numpy oracle on the last frame's inputs"},
         "extra": {"tf_track_ms": round(ms_track, 5), "avg_pairs_per_level": [int(v) for v in p_mean],
                   "drift_mm_at_end": round(drift_mm, 3),
                   "host_readback": "the estimate is copied to the host after each call (fusion takes host poses)"},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def run_filter(args):
+    """The bilateral depth filter (radius 2, sigma 2.5 px / 25 mm) on 640x480
+    uint16 frames; the oracle filters a bounded sample on the host."""
+    import torch
+    import paper_1708_00783_amd as T
+    from oracle.bilateral import bilateral
+    frames = make_frames(8, args.workers, args.frames_cache)
+    torch.cuda.set_device(0)
+    d = torch.from_numpy(frames).cuda()
+    out = torch.empty(frames.shape[1:], dtype=torch.float32, device="cuda")
+    for k in range(args.warmup):
+        T.tf_bilateral(d[k % 8], out, *C5_BILATERAL)
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record()
+    for k in range(args.steps):
+        T.tf_bilateral(d[k % 8], out, *C5_BILATERAL)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    H, W = frames.shape[1:]
+    nbytes = (2 + 4) * W * H
+    t0 = time.perf_counter()
+    n = 0
+    while n < 8 and time.perf_counter() - t0 < 10.0:
+        bilateral(frames[n].astype(np.float32) / np.float32(1000.0), *C5_BILATERAL)
+        n += 1
+    cpu = n / (time.perf_counter() - t0)
+    out_line = {
+        "metric": "bilateral-filtered frames/s (640x480 uint16 in, float32 out)", "value": round(1e3 / ms, 2),
+        "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "bilateral filter of full-frame room depth frames", "radius": C5_BILATERAL[0],
+                   "sigma_space_px": C5_BILATERAL[1], "sigma_range_m": C5_BILATERAL[2]},
+        "roofline": {"bound": "hbm", "achieved": round(nbytes / (ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5), "traffic": None,
+                     "kernel": "k_bilateral", "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": round(ms, 5)},
+        "cpu_baseline": {"value": round(cpu, 3), "unit": "frames/s", "cores": 1, "kind": "oracle",
+                         "sample": f"{n} frames, float64 numpy oracle (vectorised over pixels)"},
+    }
+    print(json.dumps(out_line), flush=True)
+
+
+def run_mesh(args):
+    """Marching-cubes meshing of the full-frame room after fusing its
+    300-frame trajectory; the oracle meshes a bounded sample of the blocks."""
+    import ctypes
+    import torch
+    import paper_1708_00783_amd as T
+    from oracle import mesh as OM
+    from synth import configs
+    K = configs.KINECT_INTR
+    frames = make_frames(N_TRAJ, args.workers, args.frames_cache)
+    poses = np.stack(configs.c2_poses(N_TRAJ)).astype(np.float32)
+    torch.cuda.set_device(0)
+    d = torch.from_numpy(frames).cuda()
+    vol = T.Volume(configs.C2_VOLUME, K.width, K.height)
+    for k in range(N_TRAJ):
+        vol.frame(d[k], K, poses[k])
+    torch.cuda.synchronize()
+    nb = vol.stats()["n_allocated"]
+    nbytes_ws = int(T.lib().tf_mesh_workspace_bytes(ctypes.byref(vol.params)))
+    ws = torch.empty(nbytes_ws, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    T.check(T.lib().tf_mesh(vol.ctx, None, None, 0, ctypes.c_void_p(cnt.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                            nbytes_ws, T._stream_ptr(None)), "tf_mesh")
+    ntri = int(cnt.item())
+    verts = torch.empty((ntri, 3, 3), dtype=torch.float32, device="cuda")
+    keys = torch.empty((ntri, 3), dtype=torch.int64, device="cuda")
+
+    def call():
+        T.check(T.lib().tf_mesh(vol.ctx, ctypes.c_void_p(verts.data_ptr()), ctypes.c_void_p(keys.data_ptr()), ntri,
+                                ctypes.c_void_p(cnt.data_ptr()), ctypes.c_void_p(ws.data_ptr()), nbytes_ws,
+                                T._stream_ptr(None)), "tf_mesh")
+    for _ in range(args.warmup):
+        call()
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record()
+    for _ in range(args.steps):
+        call()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    n_entries = configs.C2_VOLUME.n_buckets + configs.C2_VOLUME.n_excess
+    # two walks over the entries, each reading every allocated block and its
+    # halo (217 voxels of 3 bytes), plus the triangles written (9 floats + 3 keys)
+    nbytes = 2 * (16 * n_entries + nb * (1536 + 217 * 3)) + ntri * (36 + 24)
+    # oracle: a bounded sample of blocks (it needs the neighbours of each)
+    pos, sdf, w = vol.voxels_by_position()
+    t0 = time.perf_counter()
+    m = 0
+    step = 256
+    while m < len(pos) and time.perf_counter() - t0 < 15.0:
+        OM.mesh(pos[m:m + step], sdf[m:m + step], w[m:m + step], configs.C2_VOLUME.voxel_size)
+        m += step
+    cpu = m / (time.perf_counter() - t0)
+    out = {
+        "metric": "blocks meshed per second (marching cubes over every allocated block)",
+        "value": round(nb / (ms * 1e-3), 1), "unit": "blocks/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "mesh of the full-frame room after its 300-frame trajectory (voxel 5 mm)",
+                   "allocated_blocks": nb, "triangles": ntri},
+        "roofline": {"bound": "hbm", "achieved": round(nbytes / (ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5), "traffic": None,
+                     "kernel": "tf_mesh (count, scan, emit)", "algorithmic_bytes_per_call": int(nbytes),
+                     "avg_call_ms": round(ms, 5)},
+        "cpu_baseline": {"value": round(cpu, 1), "unit": "blocks/s", "cores": 1, "kind": "oracle",
+                         "sample": f"{m} of {len(pos)} blocks in groups of {step} (neighbours outside a group "
+                                   "count as absent)"},
     }
     print(json.dumps(out), flush=True)
 
@@ -715,7 +846,7 @@ def main():
     ap.add_argument("--frames-cache", default=None,
                     help="npy file holding the generated depth frames (written if absent)")
     ap.add_argument("--c4-tile", default="", help="c4: fixed raycast tile shape WxH instead of autotuning")
-    ap.add_argument("--workload", choices=("c2", "c3", "c4", "c5", "prefilter", "track"), default="c2",
+    ap.add_argument("--workload", choices=("c2", "c3", "c4", "c5", "prefilter", "track", "filter", "mesh"), default="c2",
                     help="c2: one volume, the headline metric; c3: the large walk with host swapping; "
                          "c4: 64 batched submaps, 8 views; "
                          "c5: train the depth prefilter, then denoised vs plain at equal surface error")
@@ -755,6 +886,10 @@ def main():
         return run_prefilter(args)
     if args.workload == "track":
         return run_track(args)
+    if args.workload == "filter":
+        return run_filter(args)
+    if args.workload == "mesh":
+        return run_mesh(args)
     line = run_c2(args)
     if not args.no_c5:
         print("[bench] equal-error half: training and evaluating the prefilter", file=sys.stderr, flush=True)

@@ -1,15 +1,17 @@
 // tsdf_mesh.hip -- marching-cubes meshing of the volume (Sec. 4, meshing
 // engine) on gfx950.
 //
-// Three launches.  k_mesh<false> walks the hash entries in chunks of 256, one
-// wave per chunk: the allocated entries of 64 at a time are found with one
-// ballot, and for each such block the wave stages the block and its +x/+y/+z
+// Three launches.  k_mesh<false> walks the hash entries in chunks of 64, one
+// wave per chunk: the allocated entries are found with one ballot, and for
+// each such block the wave stages the block and its +x/+y/+z
 // halo (9^3 voxels, looked up in up to 7 neighbour blocks) in LDS; lane
 // (x, y) classifies the 8 cells of its z column and the chunk's triangle count
 // is written.  k_mesh_scan turns the counts into offsets (one workgroup, fixed
-// order).  k_mesh<true> repeats the walk and writes each lane's triangles at
-// chunk offset + earlier blocks + a wave prefix over the lanes, so the output
-// order is fixed and two calls give the same arrays.
+// order).  k_mesh<true> repeats the walk; a block's triangles occupy a
+// contiguous range (chunk offset + earlier blocks), each lane's at a wave
+// prefix over the lanes: they are built in LDS and written out with
+// consecutive lanes on consecutive words.  The output order is fixed and two
+// calls give the same arrays.
 //
 // The case table is derived at compile time from the cube's faces (constexpr),
 // not tabulated: the rule of each face pairs its active edges into segments,
@@ -133,7 +135,8 @@ constexpr McTable make_mc_table()
 
 __constant__ McTable kMc = make_mc_table();
 
-constexpr int kChunk = 256;           // hash entries per wave
+constexpr int kChunk = 64;            // hash entries per wave (one ballot)
+constexpr int kCap = 256;             // triangles staged in LDS per write-out round
 constexpr int kSide = 9;              // staged block + halo
 constexpr int kVox = kSide * kSide * kSide;
 constexpr int kUnobserved = 1 << 20;  // outside the short range: a corner with weight 0
@@ -153,7 +156,7 @@ __device__ __forceinline__ int stage_voxel(const uint8_t *blk, int idx)
 }
 
 // stage block (bx, by, bz) with device pointer ptr into g (index z * 81 + y * 9 + x)
-__device__ void stage_block(const Vol &v, int bx, int by, int bz, int ptr, int *g)
+__device__ __forceinline__ void stage_block(const Vol &v, int bx, int by, int bz, int ptr, int *g)
 {
     const int lane = (int)__lane_id();
     // neighbour n = 1..7 at (n & 1, n >> 1 & 1, n >> 2 & 1); lane n - 1 looks it up
@@ -207,84 +210,106 @@ __device__ __forceinline__ int cell_case(const int *g, int x, int y, int z, int 
     return ok ? m : 0;
 }
 
+// the triangle's three vertices and edge keys
+__device__ __forceinline__ void make_triangle(const int (&s)[8], int m, int t, int gx0, int gy0, int gz0, float voxel,
+                                              float *v, long long *k)
+{
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int e = kMc.tri[m][3 * t + j];
+        const int c0 = kMc.e0[e], c1 = kMc.e1[e], ax = kMc.axis[e];
+        int s0 = s[0], s1 = s[0];
+#pragma unroll
+        for (int c = 1; c < 8; ++c) {
+            s0 = c == c0 ? s[c] : s0;
+            s1 = c == c1 ? s[c] : s1;
+        }
+        const float f0 = (float)s0 * (1.0f / 32767.0f);
+        const float f1 = (float)s1 * (1.0f / 32767.0f);
+        const float tt = f0 / (f0 - f1);
+        const int gx = gx0 + (c0 & 1), gy = gy0 + ((c0 >> 1) & 1), gz = gz0 + ((c0 >> 2) & 1);
+        float px = (float)gx, py = (float)gy, pz = (float)gz;
+        if (ax == 0) px = px + tt;
+        else if (ax == 1) py = py + tt;
+        else pz = pz + tt;
+        v[3 * j + 0] = px * voxel;
+        v[3 * j + 1] = py * voxel;
+        v[3 * j + 2] = pz * voxel;
+        k[j] = (long long)(((unsigned long long)(gx + (1 << 19)) << 42) | ((unsigned long long)(gy + (1 << 19)) << 22) |
+                           ((unsigned long long)(gz + (1 << 19)) << 2) | (unsigned long long)ax);
+    }
+}
+
 template <bool EMIT>
 __global__ __launch_bounds__(64) void k_mesh(Vol v, MeshOut o, float voxel)
 {
     __shared__ int g[kVox];
+    __shared__ float sv[EMIT ? kCap * 9 : 1];
+    __shared__ long long sk[EMIT ? kCap * 3 : 1];
     const int lane = (int)threadIdx.x;
     const uint32_t chunk = blockIdx.x;
-    const uint32_t e_begin = chunk * kChunk;
     const int cx = lane & 7, cy = lane >> 3;          // the lane's cell column
     unsigned long long base = EMIT ? o.chunk_off[chunk] : 0ull;
     unsigned long long count = 0;
-    for (uint32_t r = 0; r < kChunk; r += 64) {
-        const uint32_t e = e_begin + r + (uint32_t)lane;
-        int4 w = make_int4(0, 0, 0, -2);
-        if (e < v.n_entries) w = load_entry(v.entries, e);
-        unsigned long long live = __ballot(w.w >= 0);
-        while (live) {
-            const int src = __ffsll((long long)live) - 1;
-            live &= live - 1;
-            const int kxy = __shfl(w.x, src, 64), kz = __shfl(w.y, src, 64), ptr = __shfl(w.w, src, 64);
-            const int bx = (int16_t)(kxy & 0xffff), by = (int16_t)((uint32_t)kxy >> 16), bz = (int16_t)(kz & 0xffff);
-            __syncthreads();                             // the previous block's reads are done
-            stage_block(v, bx, by, bz, ptr, g);
-            __syncthreads();
-            int n = 0;
+    const uint32_t e = chunk * kChunk + (uint32_t)lane;
+    int4 w = make_int4(0, 0, 0, -2);
+    if (e < v.n_entries) w = load_entry(v.entries, e);
+    unsigned long long live = __ballot(w.w >= 0);
+    while (live) {
+        const int src = __ffsll((long long)live) - 1;
+        live &= live - 1;
+        const int kxy = __shfl(w.x, src, 64), kz = __shfl(w.y, src, 64), ptr = __shfl(w.w, src, 64);
+        const int bx = (int16_t)(kxy & 0xffff), by = (int16_t)((uint32_t)kxy >> 16), bz = (int16_t)(kz & 0xffff);
+        __syncthreads();                             // the previous block's reads are done
+        stage_block(v, bx, by, bz, ptr, g);
+        __syncthreads();
+        int n = 0;
 #pragma unroll
-            for (int z = 0; z < 8; ++z) {
-                int s[8];
-                n += kMc.ntri[cell_case(g, cx, cy, z, s)];
-            }
-            if (!EMIT) {
-                count += (unsigned long long)n;   // summed over lanes below
-                continue;
-            }
-            // exclusive prefix of n over the lanes
-            int pre = n;
+        for (int z = 0; z < 8; ++z) {
+            int s[8];
+            n += kMc.ntri[cell_case(g, cx, cy, z, s)];
+        }
+        if (!EMIT) {
+            count += (unsigned long long)n;   // summed over lanes below
+            continue;
+        }
+        // exclusive prefix of n over the lanes: the lane's first triangle in the block
+        int pre = n;
 #pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const int t = __shfl_up(pre, d, 64);
-                if (lane >= d) pre += t;
-            }
-            const int tot = __shfl(pre, 63, 64);
-            unsigned long long idx = base + (unsigned long long)(pre - n);
-            base += (unsigned long long)tot;
-            const int gx0 = bx * 8 + cx, gy0 = by * 8 + cy, gz0 = bz * 8;
-            for (int z = 0; z < 8; ++z) {
-                int s[8];
-                const int m = cell_case(g, cx, cy, z, s);
-                const int nt = kMc.ntri[m];
-                if (!nt) continue;
-                for (int t = 0; t < nt; ++t, ++idx) {
-                    if (idx >= o.max_tri) continue;
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const int e = kMc.tri[m][3 * t + k];
-                        const int c0 = kMc.e0[e], c1 = kMc.e1[e], ax = kMc.axis[e];
-                        const float f0 = (float)s[c0] * (1.0f / 32767.0f);
-                        const float f1 = (float)s[c1] * (1.0f / 32767.0f);
-                        const float tt = f0 / (f0 - f1);
-                        const int gx = gx0 + (c0 & 1), gy = gy0 + ((c0 >> 1) & 1), gz = gz0 + z + ((c0 >> 2) & 1);
-                        float px = (float)gx, py = (float)gy, pz = (float)gz;
-                        if (ax == 0) px = px + tt;
-                        else if (ax == 1) py = py + tt;
-                        else pz = pz + tt;
-                        if (o.verts) {
-                            float *p = o.verts + idx * 9 + 3 * k;
-                            p[0] = px * voxel;
-                            p[1] = py * voxel;
-                            p[2] = pz * voxel;
-                        }
-                        if (o.keys)
-                            o.keys[idx * 3 + k] = (long long)(((unsigned long long)(gx + (1 << 19)) << 42) |
-                                                             ((unsigned long long)(gy + (1 << 19)) << 22) |
-                                                             ((unsigned long long)(gz + (1 << 19)) << 2) |
-                                                             (unsigned long long)ax);
-                    }
+        for (int d = 1; d < 64; d <<= 1) {
+            const int t = __shfl_up(pre, d, 64);
+            if (lane >= d) pre += t;
+        }
+        const int tot = __shfl(pre, 63, 64);
+        const int first = pre - n;
+        const int gx0 = bx * 8 + cx, gy0 = by * 8 + cy, gz0 = bz * 8;
+        // the block's triangles are contiguous in the output: build them in LDS,
+        // kCap at a time, and write each round with consecutive lanes on
+        // consecutive words
+        for (int r0 = 0; r0 < tot; r0 += kCap) {
+            if (first < r0 + kCap && first + n > r0) {
+                int li = first;
+                for (int z = 0; z < 8; ++z) {
+                    int s[8];
+                    const int m = cell_case(g, cx, cy, z, s);
+                    const int nt = kMc.ntri[m];
+                    for (int t = 0; t < nt; ++t, ++li)
+                        if (li >= r0 && li < r0 + kCap)
+                            make_triangle(s, m, t, gx0, gy0, gz0 + z, voxel, sv + (li - r0) * 9, sk + (li - r0) * 3);
                 }
             }
+            __syncthreads();
+            const int cnt = tot - r0 < kCap ? tot - r0 : kCap;
+            const unsigned long long t0 = base + (unsigned long long)r0;
+            unsigned long long lim = o.max_tri > t0 ? o.max_tri - t0 : 0ull;
+            const int keep = lim < (unsigned long long)cnt ? (int)lim : cnt;
+            if (o.verts)
+                for (int i = lane; i < keep * 9; i += 64) o.verts[t0 * 9 + (unsigned long long)i] = sv[i];
+            if (o.keys)
+                for (int i = lane; i < keep * 3; i += 64) o.keys[t0 * 3 + (unsigned long long)i] = sk[i];
+            __syncthreads();
         }
+        base += (unsigned long long)tot;
     }
     if (!EMIT) {
         // fixed-order wave sum of the lanes' counts

@@ -1,13 +1,15 @@
 // tsdf_track.hip -- the depth tracker (Sec. 4.1.1, ITMDepthTracker) on gfx950.
 //
-// Per iteration one launch of k_trk_step: every thread scores the live depth
+// Per iteration two launches: in k_trk_sums every thread scores the live depth
 // pixels of a fixed grid-stride slice against the reference point and normal
 // maps (float32 pair terms, float64 sums), the wave and then the workgroup
-// reduce them in a fixed order, and the workgroup that finishes last (ticket)
-// reduces the per-workgroup partials in a fixed order, solves the 6x6 normal
+// reduce them in a fixed order into one partial per workgroup; k_trk_solve (one
+// workgroup) reduces the partials in a fixed order, solves the 6x6 normal
 // equations by Cholesky in float64 and updates the pose on the device.  The
-// pyramid levels are built by 2x2 valid-mean kernels first.  Nothing waits for
-// the host, so a call can be captured in a HIP graph.
+// kernel boundary orders the partials before their reduction, so no workgroup
+// needs a device-scope fence.  The pyramid levels are built by 2x2 valid-mean
+// kernels first.  Nothing waits for the host, so a call can be captured in a
+// HIP graph.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -32,7 +34,7 @@ struct alignas(256) TrkState {
     int32_t iterations[TF_TRACK_MAX_LEVELS];
     int32_t pairs[TF_TRACK_MAX_LEVELS];
     int32_t status;
-    uint32_t ticket;                 // workgroups of the current sums launch that have finished
+    uint32_t pad;
     double sums[TF_TRACK_MAX_LEVELS][28];
 };
 static_assert(sizeof(TrkState) <= kStateBytes, "tracker state");
@@ -73,7 +75,7 @@ __global__ __launch_bounds__(128) void k_trk_init(TrkState *st, TrkInit ini)
     }
     if (i == 0) {
         st->status = 0;
-        st->ticket = 0;
+        st->pad = 0;
     }
     for (int k = i; k < TF_TRACK_MAX_LEVELS * 28; k += blockDim.x) (&st->sums[0][0])[k] = 0.0;
 }
@@ -200,9 +202,9 @@ __device__ void solve_and_update(TrkState *st, const double *tot, int level, dou
     if (sqrt(nx) < min_update) st->done[level] = 1;
 }
 
-// One iteration at one level: pair terms and sums; the last workgroup solves.
-__global__ __launch_bounds__(kThreads) void k_trk_step(TrkLevel L, TrkRef r, float tau2, TrkState *st,
-                                                       double *part, int level, double min_update)
+// One iteration at one level, part 1: pair terms and per-workgroup sums.
+__global__ __launch_bounds__(kThreads) void k_trk_sums(TrkLevel L, TrkRef r, float tau2, const TrkState *st,
+                                                       double *part, int level)
 {
     if (st->done[level]) return;     // the same for every workgroup of the launch
     const float R0 = st->Rf[0], R1 = st->Rf[1], R2 = st->Rf[2];
@@ -252,9 +254,6 @@ __global__ __launch_bounds__(kThreads) void k_trk_step(TrkLevel L, TrkRef r, flo
         acc[28] += 1.0;
     }
     __shared__ double wsum[kThreads / 64][kTerms];
-    __shared__ double red[kSlices][kTerms];
-    __shared__ double tot[kTerms];
-    __shared__ int last;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < kTerms; ++k) {
@@ -265,17 +264,32 @@ __global__ __launch_bounds__(kThreads) void k_trk_step(TrkLevel L, TrkRef r, flo
     if (threadIdx.x < kTerms) {
         const int k = threadIdx.x;
         part[(size_t)blockIdx.x * kPartStride + k] = ((wsum[0][k] + wsum[1][k]) + wsum[2][k]) + wsum[3][k];
-        __threadfence();             // release this workgroup's partial
     }
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(&st->ticket, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();                 // acquire every workgroup's partial
+}
+
+// Part 2 (one workgroup): the partials of `groups` workgroups in a fixed
+// order, then the solve and the pose update.
+__global__ __launch_bounds__(kThreads) void k_trk_solve(TrkState *st, const double *part, int groups, int level,
+                                                        double min_update)
+{
+    if (st->done[level]) return;
+    __shared__ double red[kSlices][kTerms];
+    __shared__ double tot[kTerms];
     if (threadIdx.x < kSlices * kTerms) {
         const int k = threadIdx.x / kSlices, s = threadIdx.x % kSlices;
         double v = 0.0;
-        for (int g = s; g < (int)gridDim.x; g += kSlices) v += part[(size_t)g * kPartStride + k];
+        // 8 loads in flight per step, added in the same (ascending) order
+        for (int g0 = s; g0 < groups; g0 += 8 * kSlices) {
+            double x[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int g = g0 + j * kSlices;
+                x[j] = g < groups ? part[(size_t)g * kPartStride + k] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (g0 + j * kSlices < groups) v += x[j];
+        }
         red[s][k] = v;
     }
     __syncthreads();
@@ -285,10 +299,7 @@ __global__ __launch_bounds__(kThreads) void k_trk_step(TrkLevel L, TrkRef r, flo
         tot[threadIdx.x] = v;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        solve_and_update(st, tot, level, min_update);
-        st->ticket = 0;
-    }
+    if (threadIdx.x == 0) solve_and_update(st, tot, level, min_update);
 }
 
 __global__ __launch_bounds__(128) void k_trk_finish(const TrkState *st, tf_track_result *out)
@@ -437,9 +448,12 @@ int tsdf_track_impl(const void *d_depth, int depth_format, const tf_intrinsics *
         const size_t npix = (size_t)L.W * L.H;
         int groups = (int)((npix + kThreads - 1) / kThreads);
         if (groups > kMaxGroups) groups = kMaxGroups;
-        for (int it = 0; it < tp->iterations[l]; ++it)
-            hipLaunchKernelGGL(k_trk_step, dim3(groups), dim3(kThreads), 0, s, L, ref, tau2, st, part, l,
+        for (int it = 0; it < tp->iterations[l]; ++it) {
+            hipLaunchKernelGGL(k_trk_sums, dim3(groups), dim3(kThreads), 0, s, L, ref, tau2, (const TrkState *)st,
+                               part, l);
+            hipLaunchKernelGGL(k_trk_solve, dim3(1), dim3(kThreads), 0, s, st, (const double *)part, groups, l,
                                (double)tp->min_update);
+        }
     }
     hipLaunchKernelGGL(k_trk_finish, dim3(1), dim3(128), 0, s, (const TrkState *)st, d_result);
     return hipGetLastError() == hipSuccess ? TF_OK : TF_E_HIP;
