@@ -769,6 +769,68 @@ def run_mesh(args):
     print(json.dumps(out), flush=True)
 
 
+def run_surfel(args):
+    """Surfel fusion (Sec. 7.3) along the full-frame room trajectory: W
+    warm-up frames, then K timed frames (each: input points, index map of
+    every surfel, association, update, new surfels); the oracle fuses a
+    bounded sample on the host."""
+    import torch
+    import paper_1708_00783_amd as T
+    from oracle import surfel as OS
+    from synth import configs
+    K = configs.KINECT_INTR
+    n = min(N_TRAJ, args.warmup + args.steps)
+    frames = make_frames(n, args.workers, args.frames_cache)
+    poses = np.stack(configs.c2_poses(N_TRAJ)).astype(np.float32)
+    torch.cuda.set_device(0)
+    d = torch.from_numpy(frames).cuda()
+    g = T.SurfelMap(1 << 24, K.width, K.height)
+    for k in range(args.warmup):
+        g.fuse(d[k], K, poses[k])
+    torch.cuda.synchronize()
+    n0 = g.stats()["count"]
+    e0, e1 = _events()
+    e0.record()
+    for k in range(args.warmup, n):
+        g.fuse(d[k], K, poses[k])
+    e1.record()
+    torch.cuda.synchronize()
+    steps = n - args.warmup
+    ms = e0.elapsed_time(e1) / steps
+    st = g.stats()
+    n1 = st["count"]
+    WH = K.width * K.height
+    mean_surfels = 0.5 * (n0 + n1)
+    # per frame: each pixel's depth (2 B) read, its point and normal written and
+    # read back (2 x 32 B), z-buffer word written, set and read (3 x 8 B),
+    # correspondence written and read (2 x 4 B); each surfel's position read
+    # twice (2 x 16 B) and its normal once (16 B); new surfels written (36 B)
+    nbytes = WH * (2 + 64 + 24 + 8) + mean_surfels * 48 + (n1 - n0) / steps * 36
+    # oracle: the first frames from an empty map
+    t0 = time.perf_counter()
+    o = OS.SurfelMap(1 << 24)
+    m = 0
+    while m < 3 and time.perf_counter() - t0 < 15.0:
+        OS.fuse(o, frames[m].astype(np.float32) / np.float32(1000.0), K.as_array(), poses[m])
+        m += 1
+    cpu = m / (time.perf_counter() - t0)
+    out = {
+        "metric": "surfel-fused frames/s (640x480, index map of every surfel per frame)", "value": round(1e3 / ms, 2),
+        "unit": "frames/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup, "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "full-frame room trajectory fused into a surfel map", "frames": n,
+                   "surfels_at_start": n0, "surfels_at_end": n1},
+        "roofline": {"bound": "hbm", "achieved": round(nbytes / (ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5), "traffic": None,
+                     "kernel": "tf_surfel_fuse (whole frame)", "algorithmic_bytes_per_frame": int(nbytes),
+                     "avg_frame_ms": round(ms, 5)},
+        "cpu_baseline": {"value": round(cpu, 3), "unit": "frames/s", "cores": 1, "kind": "oracle",
+                         "sample": f"the first {m} frames from an empty map (numpy oracle)"},
+        "extra": {"flags": st["flags"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
@@ -846,7 +908,7 @@ def main():
     ap.add_argument("--frames-cache", default=None,
                     help="npy file holding the generated depth frames (written if absent)")
     ap.add_argument("--c4-tile", default="", help="c4: fixed raycast tile shape WxH instead of autotuning")
-    ap.add_argument("--workload", choices=("c2", "c3", "c4", "c5", "prefilter", "track", "filter", "mesh"), default="c2",
+    ap.add_argument("--workload", choices=("c2", "c3", "c4", "c5", "prefilter", "track", "filter", "mesh", "surfel"), default="c2",
                     help="c2: one volume, the headline metric; c3: the large walk with host swapping; "
                          "c4: 64 batched submaps, 8 views; "
                          "c5: train the depth prefilter, then denoised vs plain at equal surface error")
@@ -890,6 +952,8 @@ def main():
         return run_filter(args)
     if args.workload == "mesh":
         return run_mesh(args)
+    if args.workload == "surfel":
+        return run_surfel(args)
     line = run_c2(args)
     if not args.no_c5:
         print("[bench] equal-error half: training and evaluating the prefilter", file=sys.stderr, flush=True)

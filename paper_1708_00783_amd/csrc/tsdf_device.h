@@ -16,17 +16,6 @@ namespace {
 
 constexpr int kWave = 64;
 
-// tuning knobs of the raycast (compile-time)
-#ifndef TSDF_RAY_XCD_BANDS
-#define TSDF_RAY_XCD_BANDS 1    // give each XCD a contiguous band of tiles
-#endif
-#ifndef TSDF_RAY_BITMAP
-#define TSDF_RAY_BITMAP 1       // consult the bucket-occupancy bitmap before an entry
-#endif
-#ifndef TSDF_RAY_SKIP
-#define TSDF_RAY_SKIP 4         // march positions tested together against the occupancy bricks
-#endif
-
 __device__ __forceinline__ uint32_t hash_index(int x, int y, int z, uint32_t mask)
 {
     // Sec. 3.2 hashIndex

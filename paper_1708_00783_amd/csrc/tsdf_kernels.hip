@@ -324,9 +324,7 @@ __device__ __forceinline__ int lookup_block(const Vol &v, const TileTable *tt, i
         sl = (sl + 1u) & (uint32_t)(kTileTable - 1);
     }
     if (local) return -1;
-#if TSDF_RAY_BITMAP
     if (!(gload(v.brick + brick_word(bx, by, bz)) & brick_bit(bx, by, bz))) return -1;
-#endif
     int ptr = -1;
     const int e = find_entry_from(v.entries, v.n_buckets, v.n_excess, hash_index(bx, by, bz, v.n_buckets - 1u), bx,
                                   by, bz, 0, &ptr);
@@ -470,14 +468,10 @@ __global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, f
     __shared__ TileTable tbl;
     const int ntx = (c.W + kTile - 1) / kTile, nty = (c.H + kTile - 1) / kTile;
     const int ntiles = ntx * nty;
-#if TSDF_RAY_XCD_BANDS
     // workgroups go round-robin to the 8 XCDs: XCD k gets the k-th band of
     // tiles, so its L2 holds the blocks of one band of the image
     const int per = (ntiles + 7) / 8;
     const int tile = (int)(blockIdx.x % 8u) * per + (int)(blockIdx.x / 8u);
-#else
-    const int tile = (int)blockIdx.x;
-#endif
     const bool real = tile < ntiles;
     const int q = (int)threadIdx.x >> 6, i = (int)threadIdx.x & 63;
     const int lx = (q & 1) * 8 + (i & 7), ly = (q >> 1) * 8 + (i >> 3);
@@ -513,14 +507,13 @@ __global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, f
         BlockCache cc = {0x7fffffff, 0, 0, -1, local};
         int steps = 0;
         while (t < t_end && steps < kMaxRaySteps) {
-#if TSDF_RAY_BITMAP
             if (state == SEARCH_BLOCK_COARSE || state == SEARCH_BLOCK_FINE) {
                 // Empty-space skip: the march stays in this state with a fixed
                 // step while it finds no block.  Test the occupancy bricks of the next
                 // kSkip positions together; a clear bit proves the block absent,
                 // so those iterations are exactly the ones the loop would run.
                 const float stp = state == SEARCH_BLOCK_COARSE ? 8.0f : mu_v;
-                constexpr int kSkip = TSDF_RAY_SKIP;
+                constexpr int kSkip = 4;
                 float tk[kSkip];
                 uint32_t hk[kSkip], wk[kSkip];
                 float tt = t;
@@ -546,7 +539,6 @@ __global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, f
                 if (!stop) t = tt;
                 if (!(t < t_end && steps < kMaxRaySteps)) break;
             }
-#endif
             ++steps;
             const float P0 = ox + t * dx, P1 = oy + t * dy, P2 = oz + t * dz;
             const bool alloc = allocated_at(v, &tbl, P0, P1, P2, cc);
@@ -939,11 +931,7 @@ hipError_t launch_range_bin(const Vol &v, const Cam &c, bool all_blocks, hipStre
 hipError_t launch_raycast(const Vol &v, const Cam &c, bool all_blocks, float4 *pts, float4 *nrm, hipStream_t s)
 {
     const int ntiles = ((c.W + kTile - 1) / kTile) * ((c.H + kTile - 1) / kTile);
-#if TSDF_RAY_XCD_BANDS
-    const int grid = ((ntiles + 7) / 8) * 8;
-#else
-    const int grid = ntiles;
-#endif
+    const int grid = ((ntiles + 7) / 8) * 8;     // whole rounds of the 8 XCDs (see the tile mapping)
     if ((size_t)v.n_blocks * kBlockBytes <= 0xffffffffu)
         hipLaunchKernelGGL(k_raycast<true>, dim3(grid), dim3(256), 0, s, v, c, all_blocks ? 1 : 0, pts, nrm);
     else
