@@ -891,30 +891,40 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float *partial, cons
 // ============================================================================
 // head: delta = conv(d1, 32 -> 1); out = d + 5 cm delta on valid pixels
 // ============================================================================
-__global__ __launch_bounds__(256) void k_head_fwd(const uint16_t *d1, const float *w, const float *b,
-                                                  const float *dm, float *out, int N, int H, int W)
+// One workgroup per 16x16 output tile of one image: the tile's d1 with a
+// one-pixel halo (zeros outside the image) is staged in LDS once, and the 288
+// weights, the same for every lane, are read through the scalar cache.  The
+// sum runs tap by tap, channel by channel, from the bias.
+__global__ __launch_bounds__(256) void k_head_fwd(const uint16_t *d1, const float *__restrict__ w,
+                                                  const float *__restrict__ b, const float *dm, float *out, int N,
+                                                  int H, int W)
 {
-    __shared__ float ws[288];
-    for (int k = threadIdx.x; k < 288; k += 256) ws[k] = w[k];
+    __shared__ u32x4 tile[18 * 18 * 4];
+    const int tx = (int)blockIdx.x * 16, ty = (int)blockIdx.y * 16, n = (int)blockIdx.z;
+    for (int k = threadIdx.x; k < 18 * 18 * 4; k += 256) {
+        const int pix = k >> 2, q = k & 3;
+        const int iy = ty - 1 + pix / 18, ix = tx - 1 + pix % 18;
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (iy >= 0 && iy < H && ix >= 0 && ix < W) v = ld16(d1 + (((size_t)n * H + iy) * W + ix) * 32 + 8 * q);
+        tile[k] = v;
+    }
     __syncthreads();
-    const long P = (long)N * H * W;
-    const long p = (long)blockIdx.x * 256 + threadIdx.x;
-    if (p >= P) return;
-    const int n = (int)(p / ((long)H * W));
-    const int rem = (int)(p - (long)n * H * W);
-    const int y = rem / W, x = rem - (rem / W) * W;
+    const int lx = (int)threadIdx.x & 15, ly = (int)threadIdx.x >> 4;
+    const int x = tx + lx, y = ty + ly;
+    if (x >= W || y >= H) return;
     float s = b[0];
     for (int tap = 0; tap < 9; ++tap) {
         const int iy = y + tap / 3 - 1, ix = x + tap % 3 - 1;
         if (iy < 0 || iy >= H || ix < 0 || ix >= W) continue;
-        const uint16_t *src = d1 + (((size_t)n * H + iy) * W + ix) * 32;
+        const u32x4 *src = tile + ((ly + tap / 3) * 18 + lx + tap % 3) * 4;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const u32x4 v = ld16(src + 8 * q);
+            const u32x4 v = src[q];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) s += ws[tap * 32 + 8 * q + e] * bf2f((uint16_t)(v[e >> 1] >> (16 * (e & 1))));
+            for (int e = 0; e < 8; ++e) s += w[tap * 32 + 8 * q + e] * bf2f((uint16_t)(v[e >> 1] >> (16 * (e & 1))));
         }
     }
+    const size_t p = ((size_t)n * H + y) * W + x;
     const float d = dm[p];
     out[p] = d > 0.0f ? d + kCorrScale * s : 0.0f;
 }
@@ -1197,7 +1207,7 @@ hipError_t launch_conv_fwd(int layer, const uint16_t *in, int Hs, int Ws, const 
 hipError_t launch_head_fwd(const uint16_t *d1, const float *w, const float *b, const float *dm, float *out, int N,
                            int H, int W, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_head_fwd, grid1((long)N * H * W, 256), dim3(256), 0, s, d1, w, b, dm, out, N, H, W);
+    hipLaunchKernelGGL(k_head_fwd, dim3((W + 15) / 16, (H + 15) / 16, N), dim3(256), 0, s, d1, w, b, dm, out, N, H, W);
     return hipGetLastError();
 }
 
