@@ -3,6 +3,7 @@
 // graph capture and replay, and the launch-shape autotuner.
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -470,17 +471,47 @@ int tf_multi_autotune(tf_multi *m, const void *d_depth, int fmt, const tf_intrin
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return TF_E_HIP;
     int st = TF_OK;
+    // one candidate: an untimed warm-up, then `reps` runs each timed on its
+    // own; the median of those times (robust to a stray slow run)
     auto timed = [&](const tf_multi_config &c, bool integ, float &ms) -> int {
         m->cfg = c;
-        for (int r = -1; r < reps; ++r) {   // one untimed warm-up
-            if (r == 0 && hipEventRecord(e0, s) != hipSuccess) return TF_E_HIP;
+        std::vector<float> t;
+        for (int r = -1; r < reps; ++r) {
+            if (r >= 0 && hipEventRecord(e0, s) != hipSuccess) return TF_E_HIP;
             const int rs = integ ? run(m, d_depth, fmt, K, pose, sel, n_sel, nullptr, 0, false, true, s)
                                  : run(m, nullptr, 0, nullptr, nullptr, nullptr, 0, views, n_views, false, false, s);
             if (rs != TF_OK) return rs;
+            if (r >= 0) {
+                float x = 0.0f;
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&x, e0, e1) != hipSuccess)
+                    return TF_E_HIP;
+                t.push_back(x);
+            }
         }
-        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return TF_E_HIP;
-        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return TF_E_HIP;
-        ms /= (float)reps;
+        std::sort(t.begin(), t.end());
+        ms = t[t.size() / 2];
+        return TF_OK;
+    };
+    // Each stage's candidates are timed in two interleaved passes (so that a
+    // drift of the clock or of the cache state between candidates averages
+    // out), each keeping its better median; a later candidate replaces the
+    // best only when it is faster by more than 2%, so near-ties keep the
+    // earlier (default-first) order and repeated runs pick the same shape.
+    auto pick = [&](const std::vector<tf_multi_config> &cand, bool integ, tf_multi_config &bc, float &bt) -> int {
+        std::vector<float> best(cand.size(), 3.4e38f);
+        for (int pass = 0; pass < 2; ++pass)
+            for (size_t i = 0; i < cand.size(); ++i) {
+                float ms = 0.0f;
+                const int r = timed(cand[i], integ, ms);
+                if (r != TF_OK) return r;
+                if (ms < best[i]) best[i] = ms;
+            }
+        size_t bi = 0;
+        for (size_t i = 1; i < cand.size(); ++i)
+            if (best[i] < 0.98f * best[bi]) bi = i;
+        bc = cand[bi];
+        bt = best[bi];
         return TF_OK;
     };
     // the frame's allocation (dry integration passes re-run it: idempotent
@@ -489,39 +520,29 @@ int tf_multi_autotune(tf_multi *m, const void *d_depth, int fmt, const tf_intrin
     float ms_int = 0.0f, ms_ray = 0.0f;
     static const int nts[4] = {64, 128, 256, 512};
     static const int grps[4] = {64, 128, 256, 512};
-    float bi = 3.4e38f;
-    tf_multi_config bcfg = cur;
-    for (int a = 0; a < 4 && st == TF_OK; ++a)
-        for (int g = 0; g < 4 && st == TF_OK; ++g) {
+    std::vector<tf_multi_config> ci;
+    for (int a = 0; a < 4; ++a)
+        for (int g = 0; g < 4; ++g) {
             tf_multi_config c = cur;
             c.integrate_threads = nts[a];
             c.integrate_groups = grps[g];
-            float ms = 0.0f;
-            st = timed(c, true, ms);
-            if (st == TF_OK && ms < bi) {
-                bi = ms;
-                bcfg = c;
-            }
+            ci.push_back(c);
         }
+    tf_multi_config bcfg = cur;
+    st = pick(ci, true, bcfg, ms_int);
     cur = bcfg;
-    ms_int = bi;
     static const int tws[4][2] = {{16, 16}, {32, 8}, {16, 8}, {8, 8}};
     static const int bgs[3] = {64, 256, 1024};
-    float br = 3.4e38f;
-    for (int a = 0; a < 4 && st == TF_OK; ++a)
-        for (int g = 0; g < 3 && st == TF_OK; ++g) {
+    std::vector<tf_multi_config> cr;
+    for (int a = 0; a < 4; ++a)
+        for (int g = 0; g < 3; ++g) {
             tf_multi_config c = cur;
             c.tile_w = tws[a][0];
             c.tile_h = tws[a][1];
             c.bin_groups = bgs[g];
-            float ms = 0.0f;
-            st = timed(c, false, ms);
-            if (st == TF_OK && ms < br) {
-                br = ms;
-                bcfg = c;
-            }
+            cr.push_back(c);
         }
-    ms_ray = br;
+    if (st == TF_OK) st = pick(cr, false, bcfg, ms_ray);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != TF_OK) {
