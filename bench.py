@@ -484,24 +484,21 @@ def c5_result(args):
     # paths should not decide the comparison)
     raw_md = np.array([np.median([r[n][0] for r in res["raw"]]) for n in ns])
     den_md = np.array([np.median([r[n][0] for r in res["denoised"]]) for n in ns])
-    e_star = float(raw[-1])
     # equal error at equal coverage: the RMS is over evaluation hits only, so a
     # model fused from few frames must also cover the room (>= 95% of the raw
     # path's hits with every frame) before its error counts
-    h_star = float(hraw[-1])
-    reach = [j for j, v in enumerate(den) if v <= e_star and hden[j] >= C5_COVERAGE * h_star]
-    reach_md = [j for j, v in enumerate(den_md) if v <= raw_md[-1] and hden[j] >= C5_COVERAGE * h_star]
-    nd = ns[reach[0]] if reach else None
+    e_star, nd, ratio = PF.equal_error(ns, raw, den, hraw, hden, traw, tden, C5_COVERAGE)
+    _, nd_md, ratio_md = PF.equal_error(ns, raw_md, den_md, hraw, hden, traw, tden, C5_COVERAGE)
     bl = np.array([np.mean([r[n][0] for r in res["bilateral"]]) for n in ns])
     tbl = np.array([np.mean([r[n][1] for r in res["bilateral"]]) for n in ns])
     hbl = np.array([np.mean([r[n][2] for r in res["bilateral"]]) for n in ns])
-    reach_bl = [j for j, v in enumerate(bl) if v <= e_star and hbl[j] >= C5_COVERAGE * h_star]
+    _, nd_bl, ratio_bl = PF.equal_error(ns, raw, bl, hraw, hbl, traw, tbl, C5_COVERAGE)
     t_plain = float(traw[-1])
-    t_den = float(tden[reach[0]]) if reach else None
+    t_den = float(tden[list(ns).index(nd)]) if nd is not None else None
     cps = ns
     out = {
         "metric": "denoised vs plain at equal surface RMS error (time to reach the plain path's error)",
-        "value": round(t_plain / t_den, 4) if t_den else None, "unit": "x (T_plain(300) / T_denoised(N_d))",
+        "value": round(ratio, 4) if ratio is not None else None, "unit": "x (T_plain(300) / T_denoised(N_d))",
         "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "bf16 prefilter, f32 fusion",
         "data": "synthetic",
         "config": {"workload": "learned prefilter: 4-level 3x3 conv encoder-decoder (32/64/64/128), bf16 on "
@@ -518,13 +515,11 @@ def c5_result(args):
                    "denoised": [round(v * 1e3, 4) for v in den]},
         "bilateral": {"params": {"radius": C5_BILATERAL[0], "sigma_space_px": C5_BILATERAL[1],
                                  "sigma_range_m": C5_BILATERAL[2]},
-                      "n_d": ns[reach_bl[0]] if reach_bl else None,
-                      "ratio": round(float(traw[-1]) / float(tbl[reach_bl[0]]), 4) if reach_bl else None,
+                      "n_d": nd_bl, "ratio": round(ratio_bl, 4) if ratio_bl is not None else None,
                       "rms_mm": [round(v * 1e3, 4) for v in bl],
                       "frames_per_s": round(float(ns[-1] / tbl[-1]), 2)},
         "median_over_rooms": {"e_star_mm": round(float(raw_md[-1]) * 1e3, 4),
-                              "n_d": ns[reach_md[0]] if reach_md else None,
-                              "ratio": round(t_plain / float(tden[reach_md[0]]), 4) if reach_md else None,
+                              "n_d": nd_md, "ratio": round(ratio_md, 4) if ratio_md is not None else None,
                               "raw_mm": [round(v * 1e3, 4) for v in raw_md],
                               "denoised_mm": [round(v * 1e3, 4) for v in den_md]},
         "per_room_mm_at_300": {"raw": [round(r[ns[-1]][0] * 1e3, 4) for r in res["raw"]],

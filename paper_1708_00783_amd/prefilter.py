@@ -133,16 +133,36 @@ def surface_rms(vol: Volume, scene, poses, intr, stride: int = 4):
     from synth import analytic_sdf
     pts = torch.empty((intr.height, intr.width, 4), dtype=torch.float32, device="cuda")
     nrm = torch.empty_like(pts)
-    s2, n = 0.0, 0
+    errs, n = [], 0
     for P in poses:
         vol.raycast(P, intr, pts, nrm)
         p = pts[::stride, ::stride].reshape(-1, 4).cpu().numpy()
         p = p[p[:, 3] == 1.0][:, :3].astype(np.float64)
         if len(p):
-            e = analytic_sdf(scene, p)
-            s2 += float(np.sum(e * e))
+            errs.append(analytic_sdf(scene, p))
             n += len(p)
-    return (np.sqrt(s2 / n) if n else float("nan")), n
+    return rms_of(np.concatenate(errs) if errs else []), n
+
+
+def rms_of(errors) -> float:
+    """surface RMS of signed distances (the evaluation's statistic): sqrt(mean e^2)"""
+    e = np.asarray(errors, np.float64).reshape(-1)
+    return float(np.sqrt(np.mean(e * e))) if e.size else float("nan")
+
+
+def equal_error(ns, rms_plain, rms_path, hits_plain, hits_path, t_plain, t_path, coverage=0.95):
+    """The equal-error comparison: e* = the plain path's RMS with the most
+    frames (the last of `ns`, ascending frame counts); N_d = the smallest N
+    at which the other path's RMS <= e* while its evaluation hits reach
+    `coverage` of the plain path's with every frame (the RMS is over hits
+    only, so a sparse model must also cover the room); ratio = T_plain(all) /
+    T_path(N_d).  Returns (e*, N_d, ratio), N_d and ratio None if never."""
+    e_star = float(rms_plain[-1])
+    h_star = float(hits_plain[-1])
+    for j, n in enumerate(ns):
+        if rms_path[j] <= e_star and hits_path[j] >= coverage * h_star:
+            return e_star, n, float(t_plain[-1]) / float(t_path[j])
+    return e_star, None, None
 
 
 EVAL_STRIDES = (60, 30, 20, 15, 10, 6, 5, 4, 3, 2, 1)   # every k-th frame: N = 300 / k frames
