@@ -7,13 +7,15 @@
 // valid mean in 5 cm units) padded to 8.  Conv
 // weights are kept as fp32 master copies in the parameter vector (per layer
 // W[cout][3][3][cin] then b[cout], layers in forward order) and packed to
-// bf16 GEMM operands: G[cout][KP] with k = tap * CINP + ci (KP = 9 CINP
-// rounded up to 32) for the forward pass, T[cin][9 cout] with k = tap * cout
-// + co for the backward-data pass.  A layer that reads the 2x upsampled
-// source instead packs its taps folded by output parity (the sum of the taps
-// that land on each 2x2 source offset), each folded weight split into a bf16
-// high half and the bf16 remainder: G[2 halves][4 parities][cout][4 CINP] and
-// T[2 halves][cin][16 cout].
+// bf16 GEMM operands: G, the cout x KP matrix with k = tap * CINP + ci (KP =
+// 9 CINP rounded up to 32) for the forward pass, stored in MFMA fragment
+// order (the 64 lanes' 16-byte B fragments of one K step and 16-channel tile
+// contiguous), and T[cin][9 cout] with k = tap * cout + co for the
+// backward-data pass.  A layer that reads the 2x upsampled source instead
+// packs its taps folded by output parity (the sum of the taps that land on
+// each 2x2 source offset), each folded weight split into a bf16 high half and
+// the bf16 remainder: G[2 halves][4 parities][cout x 4 CINP, fragment order]
+// and T[2 halves][cin][16 cout].
 #pragma once
 
 #include <hip/hip_runtime.h>

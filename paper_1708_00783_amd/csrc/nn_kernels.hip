@@ -134,7 +134,16 @@ __device__ __forceinline__ void epilogue_tile(EpiTile<NT> &st, const f32x4 (&a)[
     __syncthreads();
 }
 
-__device__ __forceinline__ uint32_t bf2(float a, float b) { return (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16); }
+// two floats to packed bf16 (low half = a) by v_cvt_pk_bf16_f32: round to
+// nearest even, the same bits as f2bf for every finite value
+__device__ __forceinline__ uint32_t bf2(float a, float b)
+{
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    bf16x2 v;
+    v[0] = (__bf16)a;
+    v[1] = (__bf16)b;
+    return __builtin_bit_cast(uint32_t, v);
+}
 
 // forward: o[e] = bf16(relu(x[e] + bias[e] (+ skip[e]))), e = 0..7
 template <bool SKIP>
@@ -182,9 +191,23 @@ __device__ __forceinline__ void bwd_store8(uint16_t *o, f32x4 lo, f32x4 hi, cons
 // ============================================================================
 // fp32 master weights -> bf16 GEMM operands of every conv layer
 // ============================================================================
-__device__ __forceinline__ void pack_g(const float *w, int cin, int cinp, int kp, int i, uint16_t *g)
+// Forward operands are stored in MFMA fragment order: element
+// ((step * cout / 16 + tile) * 64 + lane) * 8 + e holds the B value of lane
+// lane = gq * 16 + r at K step `step`, i.e. output channel tile * 16 + r and
+// k = step * 32 + gq * 8 + e.  The 64 lanes' 16-byte fragments of one (step,
+// tile) are contiguous, so a fragment load reads whole cache lines.
+__device__ __forceinline__ void frag_coords(int j, int cout, int &co, int &k)
 {
-    const int co = i / kp, k = i % kp, tap = k / cinp, ci = k % cinp;
+    const int e = j & 7, lane = (j >> 3) & 63, st = (j >> 9) / (cout / 16), tile = (j >> 9) - st * (cout / 16);
+    co = tile * 16 + (lane & 15);
+    k = st * 32 + (lane >> 4) * 8 + e;
+}
+
+__device__ __forceinline__ void pack_g(const float *w, int cin, int cinp, int cout, int i, uint16_t *g)
+{
+    int co, k;
+    frag_coords(i, cout, co, k);
+    const int tap = k / cinp, ci = k % cinp;
     g[i] = (tap < 9 && ci < cin) ? f2bf(w[(co * 9 + tap) * cin + ci]) : (uint16_t)0;
 }
 
@@ -224,14 +247,17 @@ __device__ __forceinline__ uint16_t folded_weight(const float *w, int cin, int p
     return lo ? f2bf(s - bf2f(hi)) : hi;
 }
 
-// forward operand gu[lo][par][co][q * cinp + ci], q = a * 2 + b
+// forward operand gu[lo][par][cout x 4 cinp matrix in fragment order], the
+// matrix's K index k = q * cinp + ci, q = a * 2 + b
 __device__ __forceinline__ void pack_up(const float *w, int cin, int cinp, int cout, int i, uint16_t *gu)
 {
     const int k4 = 4 * cinp;
     const int half = 4 * cout * k4;
     const int lo = i / half, j = i - lo * half;
     const int par = j / (cout * k4), rem = j - par * cout * k4;
-    const int co = rem / k4, k = rem - co * k4, q = k / cinp, ci = k - (k / cinp) * cinp;
+    int co, k;
+    frag_coords(rem, cout, co, k);
+    const int q = k / cinp, ci = k - (k / cinp) * cinp;
     gu[i] = folded_weight(w, cin, par, co, q, ci, lo);
 }
 
@@ -258,7 +284,7 @@ __global__ __launch_bounds__(256) void k_pack(PackJobs J)
         if (p.up)
             pack_up(p.w, p.cin, p.cinp, p.cout, li, p.g);
         else
-            pack_g(p.w, p.cin, p.cinp, p.kp, li, p.g);
+            pack_g(p.w, p.cin, p.cinp, p.cout, li, p.g);
     }
     if (p.t && li < p.n_t) {
         if (p.up)
@@ -321,7 +347,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_up(const uint16_t *in, int Hs,
         }
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            const size_t wo = (size_t)(cbase + j * 16 + r) * K4 + k;
+            const size_t wo = ((size_t)((k0 / 32) * (COUT / 16) + cbase / 16 + j) * 64 + lane) * 8;
             const bf16x8 b = as_bf(ld16(gp + wo));
 #pragma unroll
             for (int t = 0; t < T; ++t) acc[t][j] = mfma(av[t], b, acc[t][j]);
@@ -397,7 +423,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, in
         }
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            const bf16x8 b = as_bf(ld16(g + (size_t)(cbase + j * 16 + r) * KP + k));
+            const bf16x8 b = as_bf(ld16(g + ((size_t)((k0 / 32) * (COUT / 16) + cbase / 16 + j) * 64 + lane) * 8));
 #pragma unroll
             for (int t = 0; t < T; ++t) acc[t][j] = mfma(a[t], b, acc[t][j]);
         }
@@ -1185,19 +1211,20 @@ static dim3 up_grid(int N, int Hs, int Ws, int T, int NS)
 hipError_t launch_conv_fwd(int layer, const uint16_t *in, int Hs, int Ws, const uint16_t *g, const float *bias,
                            const uint16_t *skip, uint16_t *out, int N, int Ho, int Wo, hipStream_t s)
 {
-    // 64 output pixels per wave for 32 output channels, else 32; the deepest
-    // layers (fewest pixels) split their output channels over 4 or 2 waves
+    // output pixels per workgroup = 4 waves x 16 T pixels / NS channel
+    // shares; the deeper, smaller layers take fewer pixels per wave and split
+    // their output channels over 2 or 4 waves (measured at 640x480)
     const long P = (long)N * Ho * Wo;
-    const dim3 g4 = grid1(P, 256), g2 = grid1(P, 128), g2s4 = grid1(P, 32), b(256);
+    const dim3 g128 = grid1(P, 128), g32 = grid1(P, 32), g16 = grid1(P, 16), b(256);
     if (layer >= 4 && (Ho != 2 * Hs || Wo != 2 * Ws)) return hipErrorInvalidValue;
     switch (layer) {
-    case 0: hipLaunchKernelGGL((k_conv_fwd<8, 32, 1, false, 4, 1>), g4, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 1: hipLaunchKernelGGL((k_conv_fwd<32, 64, 2, false, 2, 1>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 2: hipLaunchKernelGGL((k_conv_fwd<64, 64, 2, false, 2, 1>), g2, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 3: hipLaunchKernelGGL((k_conv_fwd<64, 128, 2, false, 2, 4>), g2s4, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 0: hipLaunchKernelGGL((k_conv_fwd<8, 32, 1, false, 2, 1>), g128, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 1: hipLaunchKernelGGL((k_conv_fwd<32, 64, 2, false, 2, 1>), g128, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 2: hipLaunchKernelGGL((k_conv_fwd<64, 64, 2, false, 1, 2>), g32, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
+    case 3: hipLaunchKernelGGL((k_conv_fwd<64, 128, 2, false, 1, 4>), g16, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
     // upsampled layers: parity-folded weights, one wave per (source row, parity, column run)
-    case 4: hipLaunchKernelGGL((k_conv_fwd_up<128, 64, true, 2, 2>), up_grid(N, Hs, Ws, 2, 2), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
-    case 5: hipLaunchKernelGGL((k_conv_fwd_up<64, 64, true, 2, 1>), up_grid(N, Hs, Ws, 2, 1), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
+    case 4: hipLaunchKernelGGL((k_conv_fwd_up<128, 64, true, 1, 2>), up_grid(N, Hs, Ws, 1, 2), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
+    case 5: hipLaunchKernelGGL((k_conv_fwd_up<64, 64, true, 2, 2>), up_grid(N, Hs, Ws, 2, 2), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
     case 6: hipLaunchKernelGGL((k_conv_fwd_up<64, 32, true, 4, 1>), up_grid(N, Hs, Ws, 4, 1), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
     default: return hipErrorInvalidValue;
     }
