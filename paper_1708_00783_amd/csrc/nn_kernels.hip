@@ -372,36 +372,65 @@ __global__ __launch_bounds__(256) void k_conv_fwd_up(const uint16_t *in, int Hs,
 }
 
 // ============================================================================
-// forward 3x3 convolution: each wave computes 16 T output pixels x COUT / NS
-// output channels (T row tiles share every weight fragment it loads; the NS
-// waves of a pixel group sit in one workgroup and share its input loads in L1)
+// Workgroups of the staged forward kernels go round-robin to the 8 XCDs;
+// remapped so that XCD x takes the x-th contiguous band of tiles, the
+// neighbouring tiles that share input rows share that XCD's L2.  The grid is
+// rounded up to a multiple of 8; tiles past the end stage zeros and store
+// nothing.
 // ============================================================================
-template <int CINP, int COUT, int STRIDE, bool SKIP, int T, int NS>
+__device__ __forceinline__ long xcd_band_tile(long ntiles)
+{
+    const long per = (ntiles + 7) / 8;
+    return (long)(blockIdx.x % 8u) * per + blockIdx.x / 8u;
+}
+
+// stage rows iy0 .. iy0 + IR - 1, columns ix0 .. ix0 + IC - 1 of one image's
+// NHWC bf16 tensor (CINP channels) in LDS, RS bytes per pixel, zeros outside
+template <int CINP, int IR, int IC, int RS>
+__device__ __forceinline__ void stage_tile(unsigned char *tile, const uint16_t *in, int nimg, int Hs, int Ws,
+                                           int iy0, int ix0, bool live)
+{
+    constexpr int CH = CINP / 8;
+    for (int i = (int)threadIdx.x; i < IR * IC * CH; i += 256) {
+        const int ch = i % CH, pc = i / CH, c = pc % IC, rr = pc / IC;
+        const int sy = iy0 + rr, sx = ix0 + c;
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (live && sy >= 0 && sy < Hs && sx >= 0 && sx < Ws)
+            v = ld16(in + (((size_t)nimg * Hs + sy) * Ws + sx) * CINP + ch * 8);
+        *reinterpret_cast<u32x4 *>(tile + (rr * IC + c) * RS + ch * 16) = v;
+    }
+    __syncthreads();
+}
+
+// ============================================================================
+// forward 3x3 convolution (no skip input): a workgroup takes ROWS = 4 / NS
+// output rows x 16 T columns; it stages the input rows and columns those
+// reach (with the stride) in LDS with coalesced 16-byte loads, then each
+// wave computes 16 T pixels of one row x COUT / NS channels, A fragments
+// from LDS, B fragments (fragment order) from global memory
+// ============================================================================
+template <int CINP, int COUT, int STRIDE, int T, int NS>
 __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, int Ws, const uint16_t *g,
-                                                  const float *bias, const uint16_t *skip, uint16_t *out, int N,
-                                                  int Ho, int Wo)
+                                                  const float *bias, uint16_t *out, int N, int Ho, int Wo)
 {
     static_assert(NS == 1 || NS == 2 || NS == 4, "channel split must divide the 4 waves of a workgroup");
     constexpr int KP = ((9 * CINP + 31) / 32) * 32;
     constexpr int NT = COUT / 16 / NS;
-    const int lane = (int)threadIdx.x & 63;
-    const long P = (long)N * Ho * Wo;
-    const int wid = (int)blockIdx.x * 4 + ((int)threadIdx.x >> 6);
-    const int cbase = (wid % NS) * (COUT / NS);
-    const long p0 = (long)(wid / NS) * (16 * T);   // waves past P load nothing and store nothing
-    const int r = lane & 15, gq = lane >> 4;
-    int pn[T], py[T], px[T];
-    bool pv[T];
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-        long p = p0 + t * 16 + r;
-        pv[t] = p < P;
-        if (!pv[t]) p = 0;
-        pn[t] = (int)(p / ((long)Ho * Wo));
-        const int rem = (int)(p - (long)pn[t] * Ho * Wo);
-        py[t] = rem / Wo;
-        px[t] = rem - py[t] * Wo;
-    }
+    constexpr int ROWS = 4 / NS;
+    constexpr int IR = STRIDE * (ROWS - 1) + 3, IC = STRIDE * (16 * T - 1) + 3;
+    constexpr int RS = CINP * 2 + 16;   // +16 bytes: neighbouring pixels' fragments start on different banks
+    __shared__ __attribute__((aligned(16))) unsigned char tile[IR * IC * RS];
+    const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6, r = lane & 15, gq = lane >> 4;
+    const int tx = (Wo + 16 * T - 1) / (16 * T), ty = (Ho + ROWS - 1) / ROWS;
+    const long ntiles = (long)N * ty * tx;
+    const long wt = xcd_band_tile(ntiles);
+    const bool live = wt < ntiles;
+    const long gt = live ? wt : 0;
+    const int xt = (int)(gt % tx);
+    const long nyt = gt / tx;
+    const int nimg = (int)(nyt / ty), y0 = (int)(nyt - (long)nimg * ty) * ROWS, x0 = xt * 16 * T;
+    stage_tile<CINP, IR, IC, RS>(tile, in, nimg, Hs, Ws, STRIDE * y0 - 1, STRIDE * x0 - 1, live);
+    const int yy = w / NS, cbase = (w % NS) * (COUT / NS);
     f32x4 acc[T][NT];
 #pragma unroll
     for (int t = 0; t < T; ++t)
@@ -415,10 +444,10 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, in
         bf16x8 a[T];
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-            const int iy = STRIDE * py[t] + ky - 1, ix = STRIDE * px[t] + kx - 1;
             u32x4 v = {0u, 0u, 0u, 0u};
-            if (tap < 9 && pv[t] && iy >= 0 && iy < Hs && ix >= 0 && ix < Ws)
-                v = ld16(in + (((size_t)pn[t] * Hs + iy) * Ws + ix) * CINP + ci);
+            if (tap < 9)   // K padding past the 9 taps multiplies zeros
+                v = *reinterpret_cast<const u32x4 *>(tile + ((STRIDE * yy + ky) * IC + STRIDE * (t * 16 + r) + kx) * RS +
+                                                     ci * 2);
             a[t] = as_bf(v);
         }
 #pragma unroll
@@ -429,13 +458,85 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, in
         }
     }
     __shared__ EpiTile<NT> st[4];
+    const int oy = y0 + yy;
 #pragma unroll
     for (int t = 0; t < T; ++t)
-        epilogue_tile(st[threadIdx.x >> 6], acc[t], lane, [&](int pix, int c8, f32x4 lo, f32x4 hi) {
-            const long p = p0 + t * 16 + pix;
-            if (p >= P) return;
+        epilogue_tile(st[w], acc[t], lane, [&](int pix, int c8, f32x4 lo, f32x4 hi) {
+            const int ox = x0 + t * 16 + pix;
+            if (!live || oy >= Ho || ox >= Wo) return;
+            const size_t p = ((size_t)nimg * Ho + oy) * Wo + ox;
             const int co = cbase + c8;
-            fwd_store8<SKIP>(out + (size_t)p * COUT + co, lo, hi, bias + co, SKIP ? skip + (size_t)p * COUT + co : nullptr);
+            fwd_store8<false>(out + p * COUT + co, lo, hi, bias + co, nullptr);
+        });
+}
+
+// the same on a source tile staged in LDS: a workgroup = the 4 output
+// parities (one per wave) of one (image, source row m, run of 16 T source
+// columns); it stages source rows m - 1 .. m + 1 and columns c0 - 1 ..
+// c0 + 16 T, which every parity's 2x2 offsets read
+template <int CINP, int COUT, bool SKIP, int T>
+__global__ __launch_bounds__(256) void k_conv_fwd_up_st(const uint16_t *in, int Hs, int Ws, const uint16_t *gu,
+                                                        const float *bias, const uint16_t *skip, uint16_t *out, int N)
+{
+    constexpr int K4 = 4 * CINP;
+    constexpr int NT = COUT / 16;
+    constexpr int TC = 16 * T + 2;
+    constexpr int RS = CINP * 2 + 16;
+    static_assert(CINP % 32 == 0, "a K step stays inside one source offset");
+    __shared__ __attribute__((aligned(16))) unsigned char tile[3 * TC * RS];
+    const int lane = (int)threadIdx.x & 63, r = lane & 15, gq = lane >> 4;
+    const int runs = (Ws + 16 * T - 1) / (16 * T);
+    const long ntiles = (long)N * Hs * runs;
+    const long wt = xcd_band_tile(ntiles);
+    const bool live = wt < ntiles;
+    const long gt = live ? wt : 0;
+    const int run = (int)(gt % runs);
+    const long nm = gt / runs;
+    const int nimg = (int)(nm / Hs), m = (int)(nm - (long)nimg * Hs);
+    const int c0 = run * 16 * T;
+    stage_tile<CINP, 3, TC, RS>(tile, in, nimg, Hs, Ws, m - 1, c0 - 1, live);
+    const int par = (int)threadIdx.x >> 6;
+    const int py = par >> 1, px = par & 1;
+    const int Ho = 2 * Hs, Wo = 2 * Ws;
+    f32x4 acc[T][NT];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t *gp = gu + (size_t)par * COUT * K4;
+    const uint16_t *gl = gp + (size_t)4 * COUT * K4;   // low halves
+#pragma unroll 2
+    for (int k0 = 0; k0 < K4; k0 += 32) {
+        const int k = k0 + gq * 8;
+        const int q = k / CINP, ci = k - (k / CINP) * CINP;
+        const bool split = q != par;   // wave-uniform: one source offset per K step
+        const int row = py + (q >> 1);
+        bf16x8 av[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+            av[t] = as_bf(*reinterpret_cast<const u32x4 *>(tile + (row * TC + t * 16 + r + px + (q & 1)) * RS + ci * 2));
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const size_t wo = ((size_t)((k0 / 32) * (COUT / 16) + j) * 64 + lane) * 8;
+            const bf16x8 b = as_bf(ld16(gp + wo));
+#pragma unroll
+            for (int t = 0; t < T; ++t) acc[t][j] = mfma(av[t], b, acc[t][j]);
+            if (split) {
+                const bf16x8 bl = as_bf(ld16(gl + wo));
+#pragma unroll
+                for (int t = 0; t < T; ++t) acc[t][j] = mfma(av[t], bl, acc[t][j]);
+            }
+        }
+    }
+    const size_t orow = ((size_t)nimg * Ho + 2 * m + py) * Wo;
+    __shared__ EpiTile<NT> st[4];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+        epilogue_tile(st[par], acc[t], lane, [&](int pix, int c8, f32x4 lo, f32x4 hi) {
+            const int nn = c0 + t * 16 + pix;
+            if (!live || nn >= Ws) return;
+            const size_t p = orow + 2 * nn + px;
+            fwd_store8<SKIP>(out + p * COUT + c8, lo, hi, bias + c8, SKIP ? skip + p * COUT + c8 : nullptr);
         });
 }
 
@@ -1211,21 +1312,30 @@ static dim3 up_grid(int N, int Hs, int Ws, int T, int NS)
 hipError_t launch_conv_fwd(int layer, const uint16_t *in, int Hs, int Ws, const uint16_t *g, const float *bias,
                            const uint16_t *skip, uint16_t *out, int N, int Ho, int Wo, hipStream_t s)
 {
-    // output pixels per workgroup = 4 waves x 16 T pixels / NS channel
-    // shares; the deeper, smaller layers take fewer pixels per wave and split
-    // their output channels over 2 or 4 waves (measured at 640x480)
-    const long P = (long)N * Ho * Wo;
-    const dim3 g128 = grid1(P, 128), g32 = grid1(P, 32), g16 = grid1(P, 16), b(256);
+    // encoder tiles: 4 / NS output rows x 16 T columns per workgroup; the
+    // deeper, smaller layers split their output channels over 2 or 4 waves;
+    // d3 (the smallest decoder) runs one wave per (source row, parity,
+    // column run, channel half), d2 and d1 stage their source tiles
+    // (shapes measured at 640x480)
+    const dim3 b(256);
+    auto enc_grid = [&](int T, int NS) {
+        const long nt = (long)N * ((Ho + 4 / NS - 1) / (4 / NS)) * ((Wo + 16 * T - 1) / (16 * T));
+        return dim3((unsigned)((nt + 7) / 8 * 8));
+    };
+    auto up_st_grid = [&](int T) {
+        const long nt = (long)N * Hs * ((Ws + 16 * T - 1) / (16 * T));
+        return dim3((unsigned)((nt + 7) / 8 * 8));
+    };
+    if (layer < 4 && skip) return hipErrorInvalidValue;
     if (layer >= 4 && (Ho != 2 * Hs || Wo != 2 * Ws)) return hipErrorInvalidValue;
     switch (layer) {
-    case 0: hipLaunchKernelGGL((k_conv_fwd<8, 32, 1, false, 2, 1>), g128, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 1: hipLaunchKernelGGL((k_conv_fwd<32, 64, 2, false, 2, 1>), g128, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 2: hipLaunchKernelGGL((k_conv_fwd<64, 64, 2, false, 1, 2>), g32, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    case 3: hipLaunchKernelGGL((k_conv_fwd<64, 128, 2, false, 1, 4>), g16, b, 0, s, in, Hs, Ws, g, bias, skip, out, N, Ho, Wo); break;
-    // upsampled layers: parity-folded weights, one wave per (source row, parity, column run)
+    case 0: hipLaunchKernelGGL((k_conv_fwd<8, 32, 1, 2, 1>), enc_grid(2, 1), b, 0, s, in, Hs, Ws, g, bias, out, N, Ho, Wo); break;
+    case 1: hipLaunchKernelGGL((k_conv_fwd<32, 64, 2, 2, 2>), enc_grid(2, 2), b, 0, s, in, Hs, Ws, g, bias, out, N, Ho, Wo); break;
+    case 2: hipLaunchKernelGGL((k_conv_fwd<64, 64, 2, 1, 4>), enc_grid(1, 4), b, 0, s, in, Hs, Ws, g, bias, out, N, Ho, Wo); break;
+    case 3: hipLaunchKernelGGL((k_conv_fwd<64, 128, 2, 1, 4>), enc_grid(1, 4), b, 0, s, in, Hs, Ws, g, bias, out, N, Ho, Wo); break;
     case 4: hipLaunchKernelGGL((k_conv_fwd_up<128, 64, true, 1, 2>), up_grid(N, Hs, Ws, 1, 2), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
-    case 5: hipLaunchKernelGGL((k_conv_fwd_up<64, 64, true, 2, 2>), up_grid(N, Hs, Ws, 2, 2), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
-    case 6: hipLaunchKernelGGL((k_conv_fwd_up<64, 32, true, 4, 1>), up_grid(N, Hs, Ws, 4, 1), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
+    case 5: hipLaunchKernelGGL((k_conv_fwd_up_st<64, 64, true, 2>), up_st_grid(2), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
+    case 6: hipLaunchKernelGGL((k_conv_fwd_up_st<64, 32, true, 2>), up_st_grid(2), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
