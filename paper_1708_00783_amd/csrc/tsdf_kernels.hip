@@ -207,6 +207,8 @@ struct TileTable {
     unsigned long long key[kTileTable];   // 0 = empty slot
     int ptr[kTileTable];
     uint4 box[kBinCap];                   // x0, y0, x1, y1 (int16), zlo, zhi (float)
+    uint16_t wlist[4][kBinCap];           // per wave: the staged records whose box meets its pixels
+    int wcnt[4];
     int complete;                         // the table holds the whole bin
 };
 
@@ -222,14 +224,19 @@ __device__ __forceinline__ uint32_t table_slot(int bx, int by, int bz)
 
 // The tile's block table and the search range of pixel (px, py) from the
 // tile's bin (all records, in chunks of kBinCap and without a table, if the
-// bin overflowed).  The records are staged in LDS and every thread takes the
-// min / max over those whose box holds its pixel: the per-pixel loop itself,
-// with no atomics.  Every thread of the workgroup calls it; zmin = +inf and
-// zmax = -inf when no record covers the pixel.
-__device__ __forceinline__ void tile_range(const Vol &v, int tile, int px, int py, TileTable *tt, bool table,
-                                           float &zmin, float &zmax)
+// bin overflowed).  The records are staged in LDS, each also listed for the
+// waves whose pixels its box meets (wave w's pixels: the 8 x 8 quadrant w of
+// the tile when `quads`, else rows 4 w .. 4 w + 3); every thread then takes
+// the min / max over its wave's list whose box holds its pixel: the
+// per-pixel loop itself, with no atomics, over the records that can matter.
+// Every thread of the workgroup calls it; zmin = +inf and zmax = -inf when
+// no record covers the pixel.
+__device__ __forceinline__ void tile_range(const Vol &v, int tile, int tx0, int ty0, bool quads, int px, int py,
+                                           TileTable *tt, bool table, float &zmin, float &zmax)
 {
     for (int k = threadIdx.x; k < kTileTable; k += 256) tt->key[k] = 0ull;
+    if (threadIdx.x < 4) tt->wcnt[threadIdx.x] = 0;
+    const int wave = (int)threadIdx.x >> 6;
     const int cnt = v.bin_count[tile];
     const bool fallback = cnt > kBinCap;
     const int n = fallback ? (int)v.ctrl->n_rec : cnt;
@@ -255,10 +262,19 @@ __device__ __forceinline__ void tile_range(const Vol &v, int tile, int px, int p
             tt->box[j] = make_uint4((uint32_t)(uint16_t)r.x0 | ((uint32_t)(uint16_t)r.y0 << 16),
                                     (uint32_t)(uint16_t)r.x1 | ((uint32_t)(uint16_t)r.y1 << 16),
                                     __float_as_uint(r.zlo), __float_as_uint(r.zhi));
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const int wx0 = tx0 + (quads ? (w & 1) * 8 : 0), wy0 = ty0 + (quads ? (w >> 1) * 8 : 4 * w);
+                const int wx1 = wx0 + (quads ? 7 : 15), wy1 = wy0 + (quads ? 7 : 3);
+                if (r.x0 <= wx1 && r.x1 >= wx0 && r.y0 <= wy1 && r.y1 >= wy0)
+                    tt->wlist[w][atomicAdd(&tt->wcnt[w], 1)] = (uint16_t)j;
+            }
         }
         __syncthreads();
-        for (int j = 0; j < m; ++j) {
-            const uint4 b = tt->box[j];
+        // the order of a wave's list varies with the atomics; min and max do not
+        const int nw = __builtin_amdgcn_readfirstlane(tt->wcnt[wave]);
+        for (int i = 0; i < nw; ++i) {
+            const uint4 b = tt->box[tt->wlist[wave][i]];
             const int x0 = (int16_t)(b.x & 0xffffu), y0 = (int16_t)(b.x >> 16);
             const int x1 = (int16_t)(b.y & 0xffffu), y1 = (int16_t)(b.y >> 16);
             if (px >= x0 && px <= x1 && py >= y0 && py <= y1) {
@@ -267,6 +283,8 @@ __device__ __forceinline__ void tile_range(const Vol &v, int tile, int px, int p
                 hi = zh > hi ? zh : hi;
             }
         }
+        // this wave's list is consumed; the next chunk's staging starts after the barrier above
+        if ((threadIdx.x & 63) == 0) tt->wcnt[wave] = 0;
     }
     __syncthreads();   // the table is complete before any lookup
     zmin = lo;
@@ -429,6 +447,100 @@ __device__ __forceinline__ float trilinear_diff(const Vol &v, const TileTable *t
     return cell_lerp(A.present, sa, A.tx, A.ty, A.tz) - cell_lerp(B.present, sb, B.tx, B.ty, B.tz);
 }
 
+// The normal's central differences (Sec. 4.4): g_a = (F(P + e_a) -
+// F(P - e_a)) / 2 for the three axes.  The six trilinear cells are those of
+// floor(P) -+ e_a; together they read 32 distinct voxels of the 4 x 4 x 4
+// around floor(P), which spans at most two blocks per axis, so the block
+// pointers are looked up once and the 32 loads issued together.  Each cell
+// keeps the fractions of its own point P -+ e_a, as separate trilinear reads
+// would.  Returns false (nothing computed) when rounding of P -+ 1 moves a
+// cell off floor(P) -+ e_a.
+template <bool kOff32>
+__device__ __forceinline__ bool normal_gradient(const Vol &v, const TileTable *tt, float X, float Y, float Z,
+                                                BlockCache &cc, float &gx, float &gy, float &gz)
+{
+    const float Xp = X + 1.0f, Xm = X - 1.0f, Yp = Y + 1.0f, Ym = Y - 1.0f, Zp = Z + 1.0f, Zm = Z - 1.0f;
+    const float fX = floorf(X), fY = floorf(Y), fZ = floorf(Z);
+    const float fXp = floorf(Xp), fXm = floorf(Xm), fYp = floorf(Yp), fYm = floorf(Ym), fZp = floorf(Zp),
+                fZm = floorf(Zm);
+    if (fXp != fX + 1.0f || fXm != fX - 1.0f || fYp != fY + 1.0f || fYm != fY - 1.0f || fZp != fZ + 1.0f ||
+        fZm != fZ - 1.0f)
+        return false;
+    const int ix = (int)fX, iy = (int)fY, iz = (int)fZ;
+    const int Bx = ix >> 3, By = iy >> 3, Bz = iz >> 3;
+    // the second block the range i - 1 .. i + 2 reaches on each axis (0: none)
+    const int ax = (ix & 7) == 0 ? -1 : ((ix & 7) >= 6 ? 1 : 0);
+    const int ay = (iy & 7) == 0 ? -1 : ((iy & 7) >= 6 ? 1 : 0);
+    const int az = (iz & 7) == 0 ? -1 : ((iz & 7) >= 6 ? 1 : 0);
+    int pb[8];
+    pb[0] = cached_block(v, tt, Bx, By, Bz, cc);
+    const bool lc = cc.local;
+#pragma unroll
+    for (int c = 1; c < 8; ++c) {
+        const int sx = c & 1, sy = (c >> 1) & 1, sz = c >> 2;
+        pb[c] = ((sx && !ax) || (sy && !ay) || (sz && !az))
+                    ? -1
+                    : lookup_block(v, tt, Bx + (sx ? ax : 0), By + (sy ? ay : 0), Bz + (sz ? az : 0), lc);
+    }
+    // voxel (ix + dx, iy + dy, iz + dz): x-cells dx -1..2, dy 0..1, dz 0..1;
+    // then the y-cells' dy = -1, 2 and the z-cells' dz = -1, 2 (dx, dy 0..1)
+    constexpr int kN = 32;
+    int16_t sv[kN];
+    uint32_t present = 0u;
+#pragma unroll
+    for (int i = 0; i < kN; ++i) {
+        int dx, dy, dz;
+        if (i < 16) {
+            dx = (i & 3) - 1;
+            dy = (i >> 2) & 1;
+            dz = i >> 3;
+        } else if (i < 24) {
+            dx = i & 1;
+            dy = ((i >> 1) & 1) ? 2 : -1;
+            dz = (i >> 2) & 1;
+        } else {
+            dx = i & 1;
+            dy = (i >> 1) & 1;
+            dz = ((i >> 2) & 1) ? 2 : -1;
+        }
+        const int x = ix + dx, y = iy + dy, z = iz + dz;
+        // selects, not an indexed private array (which would live in scratch)
+        const bool bx = (x >> 3) != Bx, by = (y >> 3) != By, bz = (z >> 3) != Bz;
+        const int pc = bz ? (by ? (bx ? pb[7] : pb[6]) : (bx ? pb[5] : pb[4]))
+                          : (by ? (bx ? pb[3] : pb[2]) : (bx ? pb[1] : pb[0]));
+        present |= (pc >= 0 ? 1u : 0u) << i;
+        const uint32_t pu = pc >= 0 ? (uint32_t)pc : 0u;
+        const uint32_t j = (uint32_t)((z & 7) + 8 * (y & 7) + 64 * (x & 7));
+        if (kOff32)
+            sv[i] = gload(reinterpret_cast<const int16_t *>(v.voxels + (__umul24(pu, (uint32_t)kBlockBytes) + 2u * j)));
+        else
+            sv[i] = gload(reinterpret_cast<const int16_t *>(v.voxels + ((size_t)pu * kBlockBytes + 2u * j)));
+    }
+    // a cell from 8 of the loaded voxels, corner c at (c & 1, c >> 1 & 1, c >> 2)
+    auto cell = [&](const int (&idx)[8], float tx, float ty, float tz) {
+        int16_t s8[8];
+        uint32_t pr = 0u;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            s8[c] = sv[idx[c]];
+            pr |= ((present >> idx[c]) & 1u) << c;
+        }
+        return cell_lerp(pr, s8, tx, ty, tz);
+    };
+    const float tx = X - fX, ty = Y - fY, tz = Z - fZ;
+    // x-cells: index (dx + 1) + 4 dy + 8 dz
+    const int xp[8] = {2, 3, 6, 7, 10, 11, 14, 15}, xm[8] = {0, 1, 4, 5, 8, 9, 12, 13};
+    gx = (cell(xp, Xp - fXp, ty, tz) - cell(xm, Xm - fXm, ty, tz)) * 0.5f;
+    // y-cells: dy 0 / 1 from the x-cells (dx 0 / 1: indices 1, 2 + 4 dy + 8 dz),
+    // dy -1 / 2 at 16 + dx + 2 (dy == 2) + 4 dz
+    const int yp[8] = {5, 6, 18, 19, 13, 14, 22, 23}, ym[8] = {16, 17, 1, 2, 20, 21, 9, 10};
+    gy = (cell(yp, tx, Yp - fYp, tz) - cell(ym, tx, Ym - fYm, tz)) * 0.5f;
+    // z-cells: dz 0 / 1 from the x-cells, dz -1 / 2 at 24 + dx + 2 dy + 4 (dz == 2)
+    const int zp[8] = {9, 10, 13, 14, 28, 29, 30, 31}, zm[8] = {24, 25, 26, 27, 1, 2, 5, 6};
+    gz = (cell(zp, tx, ty, Zp - fZp) - cell(zm, tx, ty, Zm - fZm)) * 0.5f;
+    return true;
+}
+
 // "allocated" test of the march: the block of floor(P) has a device block
 __device__ __forceinline__ bool allocated_at(const Vol &v, const TileTable *tt, float P0, float P1, float P2,
                                              BlockCache &cc)
@@ -450,7 +562,7 @@ __global__ __launch_bounds__(256) void k_range_write(Vol v, Cam c, float *zmin_o
     const int px = tx0 + (int)(threadIdx.x % kTile);
     const int py = ty0 + (int)(threadIdx.x / kTile);
     float zmin, zmax;
-    tile_range(v, tile, px, py, &tbl, false, zmin, zmax);
+    tile_range(v, tile, tx0, ty0, false, px, py, &tbl, false, zmin, zmax);
     finish_tile(v, tile, false);
     if (px >= c.W || py >= c.H) return;
     zmin_out[(size_t)py * c.W + px] = zmin;
@@ -478,7 +590,7 @@ __global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, f
     const int tx0 = real ? (tile % ntx) * kTile : 0, ty0 = real ? (tile / ntx) * kTile : 0;
     const int px = tx0 + lx, py = ty0 + ly;
     float zmin = __builtin_inff(), zmax = -__builtin_inff();
-    if (real) tile_range(v, tile, px, py, &tbl, true, zmin, zmax);
+    if (real) tile_range(v, tile, tx0, ty0, true, px, py, &tbl, true, zmin, zmax);
     const bool inside = real && px < c.W && py < c.H;
     float4 out_p = make_float4(0.f, 0.f, 0.f, 0.f), out_n = make_float4(0.f, 0.f, 0.f, 0.f);
     if (inside && zmin <= zmax) {
@@ -582,11 +694,11 @@ __global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, f
             P1 = oy + t * dy;
             P2 = oz + t * dz;
             out_p = make_float4(P0 * vs, P1 * vs, P2 * vs, 1.0f);
-            // one axis per iteration: unrolled, the compiler keeps all six
-            // cells in flight, and the registers cost half the waves per SIMD
             float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+            // the rare rays whose shifted points round across a voxel take the
+            // cells one axis per iteration
 #pragma unroll 1
-            for (int ax = 0; ax < 3; ++ax) {
+            for (int ax = normal_gradient<kOff32>(v, &tbl, P0, P1, P2, cc, gx, gy, gz) ? 3 : 0; ax < 3; ++ax) {
                 const float d = trilinear_diff<kOff32>(v, &tbl, ax == 0 ? P0 + 1.0f : P0, ax == 1 ? P1 + 1.0f : P1,
                                                        ax == 2 ? P2 + 1.0f : P2, ax == 0 ? P0 - 1.0f : P0,
                                                        ax == 1 ? P1 - 1.0f : P1, ax == 2 ? P2 - 1.0f : P2, cc) *
