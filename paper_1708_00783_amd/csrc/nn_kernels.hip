@@ -3,11 +3,12 @@
 // The 3x3 convolutions are implicit GEMMs on the bf16 matrix cores
 // (v_mfma_f32_16x16x32_bf16, fp32 accumulation):
 //   k_conv_fwd          encoder: M = output pixels, N = cout, K = (tap, ci);
-//                       the operand gather applies the stride
+//                       the workgroup's input tile is staged in LDS, the
+//                       operand reads from it apply the stride
 //   k_conv_fwd_up       decoder (nearest 2x upsampling, then 3x3): per output
-//                       parity a 2x2 convolution of the source on folded
-//                       weights split into bf16 high and low halves,
-//                       K = (source offset, half, ci)
+//                       parity a 2x2 convolution of the source (a tile staged
+//                       in LDS) on folded weights split into bf16 high and
+//                       low halves, K = (source offset, half, ci)
 //   k_conv_bwd_data_s2  stride-2 layers: M = input pixels, N = cin, K = the
 //                       taps that reach the input pixel's parity x co
 //   k_conv_bwd_data_up  decoder: the adjoint of the folded forward, K = (16
@@ -294,83 +295,6 @@ __global__ __launch_bounds__(256) void k_pack(PackJobs J)
     }
 }
 
-// forward of an upsampled layer on the parity-folded weights: a wave takes
-// 16 T source columns of one source row and one output parity and COUT / NS
-// output channels; the 4 parities of a column run are neighbouring waves and
-// read the same source pixels.  Each source operand fragment meets the high
-// and the low half of the folded weights (the one-tap offset has no low
-// half): 7 cinp multiply-adds per output instead of 9 cinp
-template <int CINP, int COUT, bool SKIP, int T, int NS>
-__global__ __launch_bounds__(256) void k_conv_fwd_up(const uint16_t *in, int Hs, int Ws, const uint16_t *gu,
-                                                     const float *bias, const uint16_t *skip, uint16_t *out, int N)
-{
-    static_assert(NS == 1 || NS == 2 || NS == 4, "channel split must divide the 4 waves of a workgroup");
-    constexpr int K4 = 4 * CINP;
-    static_assert(CINP % 32 == 0, "a K step stays inside one source offset");
-    constexpr int NT = COUT / 16 / NS;
-    const int lane = (int)threadIdx.x & 63, r = lane & 15, gq = lane >> 4;
-    const int runs = (Ws + 16 * T - 1) / (16 * T);
-    const long wid = (long)blockIdx.x * 4 + ((int)threadIdx.x >> 6);
-    const bool live = wid / NS < (long)N * Hs * runs * 4;   // dead waves still join the epilogue barriers
-    const long grp = live ? wid / NS : 0;
-    const int cbase = (int)(wid % NS) * (COUT / NS);
-    const int par = (int)(grp & 3);
-    const long rowrun = grp >> 2;
-    const int run = (int)(rowrun % runs);
-    const long nm = rowrun / runs;   // image * Hs + source row
-    const int nimg = (int)(nm / Hs), m = (int)(nm - (long)nimg * Hs);
-    const int py = par >> 1, px = par & 1;
-    const int Ho = 2 * Hs, Wo = 2 * Ws;
-    const int c0 = run * 16 * T;
-    f32x4 acc[T][NT];
-#pragma unroll
-    for (int t = 0; t < T; ++t)
-#pragma unroll
-        for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const uint16_t *gp = gu + (size_t)par * COUT * K4;
-    const uint16_t *gl = gp + (size_t)4 * COUT * K4;   // low halves
-#pragma unroll 2
-    for (int k0 = 0; k0 < K4; k0 += 32) {
-        const int k = k0 + gq * 8;
-        const int q = k / CINP, ci = k - (k / CINP) * CINP;
-        const bool split = q != par;   // wave-uniform: one source offset per K step
-        const int sy = m + py - 1 + (q >> 1);
-        bf16x8 av[T];
-#pragma unroll
-        for (int t = 0; t < T; ++t) {
-            const int nn = c0 + t * 16 + r;
-            const int sx = nn + px - 1 + (q & 1);
-            u32x4 v = {0u, 0u, 0u, 0u};
-            if (nn < Ws && sy >= 0 && sy < Hs && sx >= 0 && sx < Ws)
-                v = ld16(in + (((size_t)nimg * Hs + sy) * Ws + sx) * CINP + ci);
-            av[t] = as_bf(v);
-        }
-#pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const size_t wo = ((size_t)((k0 / 32) * (COUT / 16) + cbase / 16 + j) * 64 + lane) * 8;
-            const bf16x8 b = as_bf(ld16(gp + wo));
-#pragma unroll
-            for (int t = 0; t < T; ++t) acc[t][j] = mfma(av[t], b, acc[t][j]);
-            if (split) {
-                const bf16x8 bl = as_bf(ld16(gl + wo));
-#pragma unroll
-                for (int t = 0; t < T; ++t) acc[t][j] = mfma(av[t], bl, acc[t][j]);
-            }
-        }
-    }
-    const size_t orow = ((size_t)nimg * Ho + 2 * m + py) * Wo;
-    __shared__ EpiTile<NT> st[4];
-#pragma unroll
-    for (int t = 0; t < T; ++t)
-        epilogue_tile(st[threadIdx.x >> 6], acc[t], lane, [&](int pix, int c8, f32x4 lo, f32x4 hi) {
-            const int nn = c0 + t * 16 + pix;
-            if (!live || nn >= Ws) return;
-            const size_t p = orow + 2 * nn + px;
-            const int co = cbase + c8;
-            fwd_store8<SKIP>(out + p * COUT + co, lo, hi, bias + co, SKIP ? skip + p * COUT + co : nullptr);
-        });
-}
-
 // ============================================================================
 // Workgroups of the staged forward kernels go round-robin to the 8 XCDs;
 // remapped so that XCD x takes the x-th contiguous band of tiles, the
@@ -470,26 +394,30 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *in, int Hs, in
         });
 }
 
-// the same on a source tile staged in LDS: a workgroup = the 4 output
+// Forward of an upsampled layer on the parity-folded weights (split into
+// high and low halves; the one-tap offset has no low half: 7 cinp
+// multiply-adds per output instead of 9 cinp).  A workgroup = the 4 output
 // parities (one per wave) of one (image, source row m, run of 16 T source
-// columns); it stages source rows m - 1 .. m + 1 and columns c0 - 1 ..
-// c0 + 16 T, which every parity's 2x2 offsets read
-template <int CINP, int COUT, bool SKIP, int T>
-__global__ __launch_bounds__(256) void k_conv_fwd_up_st(const uint16_t *in, int Hs, int Ws, const uint16_t *gu,
-                                                        const float *bias, const uint16_t *skip, uint16_t *out, int N)
+// columns) and one of NS shares of the output channels; it stages source
+// rows m - 1 .. m + 1 and columns c0 - 1 .. c0 + 16 T, which every parity's
+// 2x2 offsets read, in LDS.
+template <int CINP, int COUT, bool SKIP, int T, int NS>
+__global__ __launch_bounds__(256) void k_conv_fwd_up(const uint16_t *in, int Hs, int Ws, const uint16_t *gu,
+                                                     const float *bias, const uint16_t *skip, uint16_t *out, int N)
 {
     constexpr int K4 = 4 * CINP;
-    constexpr int NT = COUT / 16;
+    constexpr int NT = COUT / 16 / NS;
     constexpr int TC = 16 * T + 2;
     constexpr int RS = CINP * 2 + 16;
     static_assert(CINP % 32 == 0, "a K step stays inside one source offset");
     __shared__ __attribute__((aligned(16))) unsigned char tile[3 * TC * RS];
     const int lane = (int)threadIdx.x & 63, r = lane & 15, gq = lane >> 4;
     const int runs = (Ws + 16 * T - 1) / (16 * T);
-    const long ntiles = (long)N * Hs * runs;
+    const long ntiles = (long)N * Hs * runs * NS;
     const long wt = xcd_band_tile(ntiles);
     const bool live = wt < ntiles;
-    const long gt = live ? wt : 0;
+    const int cbase = (int)(wt % NS) * (COUT / NS);
+    const long gt = live ? wt / NS : 0;
     const int run = (int)(gt % runs);
     const long nm = gt / runs;
     const int nimg = (int)(nm / Hs), m = (int)(nm - (long)nimg * Hs);
@@ -517,7 +445,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd_up_st(const uint16_t *in, int 
             av[t] = as_bf(*reinterpret_cast<const u32x4 *>(tile + (row * TC + t * 16 + r + px + (q & 1)) * RS + ci * 2));
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            const size_t wo = ((size_t)((k0 / 32) * (COUT / 16) + j) * 64 + lane) * 8;
+            const size_t wo = ((size_t)((k0 / 32) * (COUT / 16) + cbase / 16 + j) * 64 + lane) * 8;
             const bf16x8 b = as_bf(ld16(gp + wo));
 #pragma unroll
             for (int t = 0; t < T; ++t) acc[t][j] = mfma(av[t], b, acc[t][j]);
@@ -536,7 +464,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd_up_st(const uint16_t *in, int 
             const int nn = c0 + t * 16 + pix;
             if (!live || nn >= Ws) return;
             const size_t p = orow + 2 * nn + px;
-            fwd_store8<SKIP>(out + p * COUT + c8, lo, hi, bias + c8, SKIP ? skip + p * COUT + c8 : nullptr);
+            const int co = cbase + c8;
+            fwd_store8<SKIP>(out + p * COUT + co, lo, hi, bias + co, SKIP ? skip + p * COUT + co : nullptr);
         });
 }
 
@@ -1021,7 +950,8 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float *partial, cons
 // One workgroup per 16x16 output tile of one image: the tile's d1 with a
 // one-pixel halo (zeros outside the image) is staged in LDS once, and the 288
 // weights, the same for every lane, are read through the scalar cache.  The
-// sum runs tap by tap, channel by channel, from the bias.
+// sum runs tap by tap, channel by channel, from the bias, one fused
+// multiply-add (a single rounding) per term.
 __global__ __launch_bounds__(256) void k_head_fwd(const uint16_t *d1, const float *__restrict__ w,
                                                   const float *__restrict__ b, const float *dm, float *out, int N,
                                                   int H, int W)
@@ -1048,7 +978,7 @@ __global__ __launch_bounds__(256) void k_head_fwd(const uint16_t *d1, const floa
         for (int q = 0; q < 4; ++q) {
             const u32x4 v = src[q];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) s += w[tap * 32 + 8 * q + e] * bf2f((uint16_t)(v[e >> 1] >> (16 * (e & 1))));
+            for (int e = 0; e < 8; ++e) s = fmaf(w[tap * 32 + 8 * q + e], bf2f((uint16_t)(v[e >> 1] >> (16 * (e & 1)))), s);
         }
     }
     const size_t p = ((size_t)n * H + y) * W + x;
@@ -1302,28 +1232,21 @@ hipError_t launch_pack(const Net &net, const float *params, uint16_t *g, uint16_
     return hipGetLastError();
 }
 
-// workgroups of k_conv_fwd_up: N Hs source rows x column runs of 16 T x 4 parities x NS waves
-static dim3 up_grid(int N, int Hs, int Ws, int T, int NS)
-{
-    const long waves = (long)N * Hs * ((Ws + 16 * T - 1) / (16 * T)) * 4 * NS;
-    return dim3((unsigned)((waves + 3) / 4));
-}
 
 hipError_t launch_conv_fwd(int layer, const uint16_t *in, int Hs, int Ws, const uint16_t *g, const float *bias,
                            const uint16_t *skip, uint16_t *out, int N, int Ho, int Wo, hipStream_t s)
 {
-    // encoder tiles: 4 / NS output rows x 16 T columns per workgroup; the
-    // deeper, smaller layers split their output channels over 2 or 4 waves;
-    // d3 (the smallest decoder) runs one wave per (source row, parity,
-    // column run, channel half), d2 and d1 stage their source tiles
-    // (shapes measured at 640x480)
+    // encoder tiles: 4 / NS output rows x 16 T columns per workgroup, the
+    // deeper, smaller layers splitting their output channels over 2 or 4
+    // waves; decoder tiles: one source row x 16 T columns, the smaller
+    // layers' channels split over NS workgroups (shapes measured at 640x480)
     const dim3 b(256);
     auto enc_grid = [&](int T, int NS) {
         const long nt = (long)N * ((Ho + 4 / NS - 1) / (4 / NS)) * ((Wo + 16 * T - 1) / (16 * T));
         return dim3((unsigned)((nt + 7) / 8 * 8));
     };
-    auto up_st_grid = [&](int T) {
-        const long nt = (long)N * Hs * ((Ws + 16 * T - 1) / (16 * T));
+    auto up_grid = [&](int T, int NS) {
+        const long nt = (long)N * Hs * ((Ws + 16 * T - 1) / (16 * T)) * NS;
         return dim3((unsigned)((nt + 7) / 8 * 8));
     };
     if (layer < 4 && skip) return hipErrorInvalidValue;
@@ -1333,9 +1256,9 @@ hipError_t launch_conv_fwd(int layer, const uint16_t *in, int Hs, int Ws, const 
     case 1: hipLaunchKernelGGL((k_conv_fwd<32, 64, 2, 2, 2>), enc_grid(2, 2), b, 0, s, in, Hs, Ws, g, bias, out, N, Ho, Wo); break;
     case 2: hipLaunchKernelGGL((k_conv_fwd<64, 64, 2, 1, 4>), enc_grid(1, 4), b, 0, s, in, Hs, Ws, g, bias, out, N, Ho, Wo); break;
     case 3: hipLaunchKernelGGL((k_conv_fwd<64, 128, 2, 1, 4>), enc_grid(1, 4), b, 0, s, in, Hs, Ws, g, bias, out, N, Ho, Wo); break;
-    case 4: hipLaunchKernelGGL((k_conv_fwd_up<128, 64, true, 1, 2>), up_grid(N, Hs, Ws, 1, 2), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
-    case 5: hipLaunchKernelGGL((k_conv_fwd_up_st<64, 64, true, 2>), up_st_grid(2), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
-    case 6: hipLaunchKernelGGL((k_conv_fwd_up_st<64, 32, true, 2>), up_st_grid(2), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
+    case 4: hipLaunchKernelGGL((k_conv_fwd_up<128, 64, true, 2, 4>), up_grid(2, 4), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
+    case 5: hipLaunchKernelGGL((k_conv_fwd_up<64, 64, true, 2, 2>), up_grid(2, 2), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
+    case 6: hipLaunchKernelGGL((k_conv_fwd_up<64, 32, true, 2, 1>), up_grid(2, 1), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
