@@ -666,20 +666,29 @@ __global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, f
                 t += mu_v;
             } else {
                 F = trilinear<kOff32>(v, &tbl, P0, P1, P2, cc);
-                if (state == SEARCH_BLOCK_FINE) {
-                    state = (F < 0.0f) ? WRONG_SIDE : SEARCH_SURFACE;
-                } else if (state == SEARCH_SURFACE) {
+                if (state == SEARCH_SURFACE) {
                     if (F < 0.0f) {
                         state = BEHIND_SURFACE;
                         break;
                     }
                     const float s = F * mu_v;
                     t += (s > 1.0f) ? s : 1.0f;
-                } else {
-                    if (F >= 0.0f) {
-                        state = SEARCH_SURFACE;
+                } else if (F < 0.0f) {
+                    if (state == SEARCH_BLOCK_FINE) {
+                        state = WRONG_SIDE;
                     } else {
                         const float s = -F * mu_v;
+                        t += (s > 1.0f) ? s : 1.0f;
+                    }
+                } else {
+                    // FINE or WRONG_SIDE meeting F >= 0 turns to SURFACE without
+                    // a step; the SURFACE iteration that follows (if the step
+                    // bound allows it) reads the same cell at the same t, so
+                    // its step is taken here with this F
+                    state = SEARCH_SURFACE;
+                    if (steps < kMaxRaySteps) {
+                        ++steps;
+                        const float s = F * mu_v;
                         t += (s > 1.0f) ? s : 1.0f;
                     }
                 }
