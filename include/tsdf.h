@@ -278,7 +278,9 @@ typedef struct {
 /* Device workspace for n_submaps submaps of parameters p (p->max_width x
  * p->max_height bounds the depth frames; swap_transfer_blocks must be 0),
  * views up to view_w x view_h, and bin_capacity (block, tile) entries per
- * raycast call over all its views.  0 if an argument is out of range. */
+ * raycast call over all its views, plus 256 MiB of world-cell submap masks
+ * (which submaps' blocks reach each 8-voxel world cell).  0 if an argument
+ * is out of range. */
 size_t tf_multi_workspace_bytes(const tf_params *p, uint32_t n_submaps, uint32_t view_w, uint32_t view_h,
                                 uint32_t bin_capacity);
 /* Bytes of the pinned host parameter buffer. */

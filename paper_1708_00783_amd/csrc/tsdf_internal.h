@@ -21,6 +21,7 @@ constexpr int kMaxRaySteps = 65536;     // hard bound on raycast iterations
 constexpr int kMaxSegmentSamples = 64;  // samples kept per pixel segment
 constexpr int kIntegrateGrid = 2048;    // workgroups of the integration launch
 constexpr uint32_t kBrickWords = 1u << 19;   // block-occupancy bricks: 2 MiB per volume
+constexpr uint32_t kWorldCells = 1u << 25;   // submap masks of world cells (512 x 512 x 128 window): 256 MiB per batched map
 constexpr int kKeepGroups = 64;         // allocation workgroups past the image: the previous list's frustum test
 
 // vis[] byte per hash entry, reset by the visible-list compaction
@@ -206,12 +207,13 @@ struct MTiles {
     Rec *bins;            // entries, pad = submap index
     MCtrl *mc;
     unsigned long long *acc_hits;   // per tile: pixels with a hit
-    uint32_t *wocc;       // world occupancy bricks (kBrickWords): 8-voxel world cells any submap block may reach
+    unsigned long long *wmask;   // per 8-voxel world cell (kWorldCells, see wcell_index): the submaps whose blocks may reach it
     uint32_t cap;         // capacity of bins
     uint32_t n_tiles;     // tiles over all views
 };
 
-hipError_t launch_m_alloc(const Vol *vols, const MSub *subs, const MFrame *f, uint32_t *wocc, int max_w, int max_h,
+hipError_t launch_m_alloc(const Vol *vols, const MSub *subs, const MFrame *f, unsigned long long *wmask, int max_w,
+                          int max_h,
                           hipStream_t s);
 hipError_t launch_m_integrate(const Vol *vols, const MFrame *f, int nt, int grid, bool dry, hipStream_t s);
 hipError_t launch_m_bin(const MSub *subs, const MFrame *f, const MTiles &t, int n_views, int grid, float voxel,

@@ -172,16 +172,30 @@ __global__ __launch_bounds__(256) void k_m_clear(MTiles t)
         t.off[i] = 0u;
         t.acc_hits[i] = 0ull;
     }
-    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < kBrickWords; i += gridDim.x * 256u) t.wocc[i] = 0u;
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < kWorldCells; i += gridDim.x * 256u) t.wmask[i] = 0ull;
     if (blockIdx.x == 0 && threadIdx.x == 0) t.off[t.n_tiles] = 0u;
 }
 
-// World occupancy: every block a selected submap gained this frame (its
-// allocated list past n_marked) marks the 8-voxel world cells of its cube's
-// world-space box, grown by one voxel (far above the rounding of the pose
-// transforms).  A clear cell then proves that no submap has a block at any
-// point of it.  Blocks are never removed, so marks are never cleared.
-__global__ __launch_bounds__(256) void k_m_mark(const Vol *vols, const MSub *subs, const MFrame *f, uint32_t *wocc)
+// slot of world cell (cx, cy, cz) (8-voxel cells of world voxel units) in the
+// submap-mask array: a 512 x 512 x 128 window, cells a window apart share a
+// slot (their masks merge, which only adds submaps to visit)
+__device__ __forceinline__ uint32_t wcell_index(int cx, int cy, int cz)
+{
+    return (((uint32_t)cx & 511u) << 16) | (((uint32_t)cy & 511u) << 7) | ((uint32_t)cz & 127u);
+}
+
+// World submap masks: every block a selected submap gained this frame (its
+// allocated list past n_marked) sets the submap's bit in the 8-voxel world
+// cells of its cube's world-space box, grown by two voxels.  A trilinear
+// read at a point reaches voxels within one voxel per submap axis, i.e.
+// within sqrt(3) voxels of the point in world space, so a submap with any
+// voxel of a block under the read of point P has its bit in P's cell (the
+// growth also covers the rounding of the pose transforms).  A cell's mask
+// thus lists every submap that can be allocated at, or weigh in the field
+// at, any point of the cell.  Blocks are never removed, so bits are never
+// cleared.
+__global__ __launch_bounds__(256) void k_m_mark(const Vol *vols, const MSub *subs, const MFrame *f,
+                                                unsigned long long *wmask)
 {
     const int y = (int)blockIdx.y;
     if (y >= f->n_sel) return;
@@ -209,12 +223,13 @@ __global__ __launch_bounds__(256) void k_m_mark(const Vol *vols, const MSub *sub
         }
         int c0[3], c1[3];
         for (int r = 0; r < 3; ++r) {
-            c0[r] = ((int)floorf(lo[r] - 1.0f)) >> 3;
-            c1[r] = ((int)floorf(hi[r] + 1.0f)) >> 3;
+            c0[r] = ((int)floorf(lo[r] - 2.0f)) >> 3;
+            c1[r] = ((int)floorf(hi[r] + 2.0f)) >> 3;
         }
+        const unsigned long long bit = 1ull << (uint32_t)si;
         for (int cx = c0[0]; cx <= c1[0]; ++cx)
             for (int cy = c0[1]; cy <= c1[1]; ++cy)
-                for (int cz = c0[2]; cz <= c1[2]; ++cz) atomicOr(&wocc[brick_word(cx, cy, cz)], brick_bit(cx, cy, cz));
+                for (int cz = c0[2]; cz <= c1[2]; ++cz) atomicOr(&wmask[wcell_index(cx, cy, cz)], bit);
     }
 }
 
@@ -388,11 +403,30 @@ __device__ __forceinline__ void to_sub(const MTileLds<NT> &L, int k, float P0, f
     Q2 = ((R[6] * P0 + R[7] * P1) + R[8] * P2) + R[11];
 }
 
-// "allocated" of the combined map: some submap has a device block at floor(P_i X)
+// position in the tile's submap list of submap sm (a bit of L.mask)
 template <int NT>
-__device__ __forceinline__ bool m_allocated(const MTileLds<NT> &L, int ns, float P0, float P1, float P2, bool local)
+__device__ __forceinline__ int tile_slot(const MTileLds<NT> &L, int sm)
 {
-    for (int k = 0; k < ns; ++k) {
+    return __popcll(L.mask & ((1ull << (uint32_t)sm) - 1ull));
+}
+
+// the tile's submaps that can be allocated at, or weigh in the field at,
+// world voxel-unit point P: the mask of P's world cell within the tile's set
+template <int NT>
+__device__ __forceinline__ unsigned long long m_cell_mask(const MTiles &t, const MTileLds<NT> &L, float P0, float P1,
+                                                          float P2)
+{
+    return gload(t.wmask + wcell_index(block_of(P0), block_of(P1), block_of(P2))) & L.mask;
+}
+
+// "allocated" of the combined map: some submap has a device block at
+// floor(P_i X); only the submaps of P's cell mask cm can
+template <int NT>
+__device__ __forceinline__ bool m_allocated(const MTileLds<NT> &L, unsigned long long cm, float P0, float P1, float P2,
+                                            bool local)
+{
+    for (; cm; cm &= cm - 1ull) {
+        const int k = tile_slot(L, __ffsll((long long)cm) - 1);
         float Q0, Q1, Q2;
         to_sub(L, k, P0, P1, P2, Q0, Q1, Q2);
         if (m_lookup(L, k, block_of(Q0), block_of(Q1), block_of(Q2), local) >= 0) return true;
@@ -400,13 +434,17 @@ __device__ __forceinline__ bool m_allocated(const MTileLds<NT> &L, int ns, float
     return false;
 }
 
-// combined field at world voxel-unit P
+// combined field at world voxel-unit P over the submaps of P's cell mask cm
+// (every submap with positive weight at P is one of them), in ascending
+// submap order
 template <int NT>
-__device__ __forceinline__ float m_field(const MTileLds<NT> &L, int ns, float P0, float P1, float P2, bool local)
+__device__ __forceinline__ float m_field(const MTileLds<NT> &L, unsigned long long cm, float P0, float P1, float P2,
+                                         bool local)
 {
     int cnt = 0;
     float first = 1.0f, num = 0.0f, den = 0.0f;
-    for (int k = 0; k < ns; ++k) {
+    for (; cm; cm &= cm - 1ull) {
+        const int k = tile_slot(L, __ffsll((long long)cm) - 1);
         float Q0, Q1, Q2;
         to_sub(L, k, P0, P1, P2, Q0, Q1, Q2);
         const float fbx = floorf(Q0), fby = floorf(Q1), fbz = floorf(Q2);
@@ -502,7 +540,6 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
     float zmin, zmax;
     m_tile_setup<NT, TW, TH>(subs, t, (uint32_t)g, tx0, ty0, L);
     m_pixel_range<NT>(L, ly * TW + lx, zmin, zmax);
-    const int ns = __popcll(L.mask);
     const bool full = L.n_tab <= (uint32_t)(MTileLds<NT>::TT / 2) && !L.unfit;   // the table holds the whole bin
     const bool inside = px < W && py < H;
     float4 out_p = make_float4(0.f, 0.f, 0.f, 0.f), out_n = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -534,14 +571,12 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
                 const float stp = state == M_COARSE ? 8.0f : mu_v;
                 constexpr int kSkip = 4;
                 float tk[kSkip];
-                uint32_t bk[kSkip], wk[kSkip];
+                unsigned long long wk[kSkip];
                 float t2 = tt;
 #pragma unroll
                 for (int k = 0; k < kSkip; ++k) {
                     tk[k] = t2;
-                    const int c0 = block_of(ox + t2 * dx), c1 = block_of(oy + t2 * dy), c2 = block_of(oz + t2 * dz);
-                    bk[k] = brick_bit(c0, c1, c2);
-                    wk[k] = gload(t.wocc + brick_word(c0, c1, c2));
+                    wk[k] = m_cell_mask<NT>(t, L, ox + t2 * dx, oy + t2 * dy, oz + t2 * dz);
                     t2 += stp;
                 }
                 bool stop = false;
@@ -549,7 +584,7 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
                 for (int k = 0; k < kSkip; ++k) {
                     if (stop) continue;
                     tt = tk[k];
-                    if (!(tt < t_end && steps < kMaxRaySteps) || (wk[k] & bk[k])) {
+                    if (!(tt < t_end && steps < kMaxRaySteps) || wk[k]) {
                         stop = true;
                         continue;
                     }
@@ -561,10 +596,9 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
             ++steps;
             const float P0 = ox + tt * dx, P1 = oy + tt * dy, P2 = oz + tt * dz;
             const bool local = full && tt * zscale >= kZNear;
-            // a world cell no submap block reaches: nothing is allocated there
-            const int c0 = block_of(P0), c1 = block_of(P1), c2 = block_of(P2);
-            const bool alloc = (gload(t.wocc + brick_word(c0, c1, c2)) & brick_bit(c0, c1, c2)) &&
-                               m_allocated(L, ns, P0, P1, P2, local);
+            // only the submaps of P's world cell can be allocated there
+            const unsigned long long cm = m_cell_mask<NT>(t, L, P0, P1, P2);
+            const bool alloc = cm && m_allocated(L, cm, P0, P1, P2, local);
             if (state == M_COARSE) {
                 if (!alloc) {
                     tt += 8.0f;
@@ -576,21 +610,30 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
                 state = M_FINE;
                 tt += mu_v;
             } else {
-                F = m_field(L, ns, P0, P1, P2, local);
-                if (state == M_FINE) {
-                    state = (F < 0.0f) ? M_WRONG_SIDE : M_SURFACE;
-                } else if (state == M_SURFACE) {
+                F = m_field(L, cm, P0, P1, P2, local);
+                if (state == M_SURFACE) {
                     if (F < 0.0f) {
                         state = M_BEHIND;
                         break;
                     }
                     const float s = F * mu_v;
                     tt += (s > 1.0f) ? s : 1.0f;
-                } else {
-                    if (F >= 0.0f) {
-                        state = M_SURFACE;
+                } else if (F < 0.0f) {
+                    if (state == M_FINE) {
+                        state = M_WRONG_SIDE;
                     } else {
                         const float s = -F * mu_v;
+                        tt += (s > 1.0f) ? s : 1.0f;
+                    }
+                } else {
+                    // FINE or WRONG_SIDE meeting F >= 0 turns to SURFACE without
+                    // a step; the SURFACE iteration that follows (if the step
+                    // bound allows it) reads the same field at the same t, so
+                    // its step is taken here with this F
+                    state = M_SURFACE;
+                    if (steps < kMaxRaySteps) {
+                        ++steps;
+                        const float s = F * mu_v;
                         tt += (s > 1.0f) ? s : 1.0f;
                     }
                 }
@@ -599,16 +642,17 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
         if (state == M_BEHIND) {
             tt += F * mu_v;
             float P0 = ox + tt * dx, P1 = oy + tt * dy, P2 = oz + tt * dz;
-            F = m_field(L, ns, P0, P1, P2, full && tt * zscale >= kZNear);
+            F = m_field(L, m_cell_mask<NT>(t, L, P0, P1, P2), P0, P1, P2, full && tt * zscale >= kZNear);
             tt += F * mu_v;
             P0 = ox + tt * dx;
             P1 = oy + tt * dy;
             P2 = oz + tt * dz;
             out_p = make_float4(P0 * voxel, P1 * voxel, P2 * voxel, 1.0f);
             const bool lh = full && tt * zscale >= kZNear;   // the taps lie within 2 voxels of the hit
-            const float gx = (m_field(L, ns, P0 + 1.0f, P1, P2, lh) - m_field(L, ns, P0 - 1.0f, P1, P2, lh)) * 0.5f;
-            const float gy = (m_field(L, ns, P0, P1 + 1.0f, P2, lh) - m_field(L, ns, P0, P1 - 1.0f, P2, lh)) * 0.5f;
-            const float gz = (m_field(L, ns, P0, P1, P2 + 1.0f, lh) - m_field(L, ns, P0, P1, P2 - 1.0f, lh)) * 0.5f;
+            auto fld = [&](float X, float Y, float Z) { return m_field(L, m_cell_mask<NT>(t, L, X, Y, Z), X, Y, Z, lh); };
+            const float gx = (fld(P0 + 1.0f, P1, P2) - fld(P0 - 1.0f, P1, P2)) * 0.5f;
+            const float gy = (fld(P0, P1 + 1.0f, P2) - fld(P0, P1 - 1.0f, P2)) * 0.5f;
+            const float gz = (fld(P0, P1, P2 + 1.0f) - fld(P0, P1, P2 - 1.0f)) * 0.5f;
             const float gn = sqrtf((gx * gx + gy * gy) + gz * gz);
             if (gn > 0.0f) out_n = make_float4(gx / gn, gy / gn, gz / gn, 1.0f);
         }
@@ -648,7 +692,7 @@ __global__ __launch_bounds__(TW *TH) void k_m_range_write(const MSub *subs, cons
 // ============================================================================
 // launchers
 // ============================================================================
-hipError_t launch_m_alloc(const Vol *vols, const MSub *subs, const MFrame *f, uint32_t *wocc, int w, int h,
+hipError_t launch_m_alloc(const Vol *vols, const MSub *subs, const MFrame *f, unsigned long long *wmask, int w, int h,
                           hipStream_t s)
 {
     const int npix = w * h;
@@ -656,7 +700,7 @@ hipError_t launch_m_alloc(const Vol *vols, const MSub *subs, const MFrame *f, ui
     if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     hipLaunchKernelGGL(k_m_insert, dim3(128, kMaxSel), dim3(256), 0, s, vols, f);
     if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
-    hipLaunchKernelGGL(k_m_mark, dim3(64, kMaxSel), dim3(256), 0, s, vols, subs, f, wocc);
+    hipLaunchKernelGGL(k_m_mark, dim3(64, kMaxSel), dim3(256), 0, s, vols, subs, f, wmask);
     if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     hipLaunchKernelGGL(k_m_visible, dim3(256, kMaxSel), dim3(256), 0, s, vols, f);
     return hipGetLastError();
@@ -724,7 +768,7 @@ hipError_t launch_m_range_write(const MSub *subs, const MFrame *f, const MTiles 
 
 hipError_t launch_m_clear(const MTiles &t, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_m_clear, dim3((t.n_tiles + 255) / 256 + 1), dim3(256), 0, s, t);
+    hipLaunchKernelGGL(k_m_clear, dim3(2048), dim3(256), 0, s, t);
     return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct MLayout {
-    size_t sub_bytes, subs, vols, msubs, frames, alists, depth, cnt, cur, off, hits, mc, wocc, bins, total;
+    size_t sub_bytes, subs, vols, msubs, frames, alists, depth, cnt, cur, off, hits, mc, wmask, bins, total;
     uint32_t max_tiles;
 };
 
@@ -51,7 +51,7 @@ bool mlayout(const tf_params *p, uint32_t n, uint32_t vw, uint32_t vh, uint32_t 
     L.off = take((size_t)4 * (L.max_tiles + 1));
     L.hits = take((size_t)8 * L.max_tiles);
     L.mc = take(sizeof(MCtrl));
-    L.wocc = take((size_t)4 * kBrickWords);
+    L.wmask = take((size_t)8 * kWorldCells);
     L.bins = take((size_t)sizeof(Rec) * cap);
     L.total = o;
     return true;
@@ -207,7 +207,7 @@ hipError_t enqueue(tf_multi *m, int h, bool do_int, bool do_ray, int fw, int fh,
     hipError_t e = hipMemcpyAsync(m->d_frame[h], m->h_frame[h], sizeof(MFrame), hipMemcpyHostToDevice, s);
     const MFrame *f = m->d_frame[h];
     if (e == hipSuccess && do_int) {
-        e = launch_m_alloc(m->d_vols, m->d_msubs, f, m->t.wocc, fw, fh, s);
+        e = launch_m_alloc(m->d_vols, m->d_msubs, f, m->t.wmask, fw, fh, s);
         if (e == hipSuccess)
             e = launch_m_integrate(m->d_vols, f, m->cfg.integrate_threads, m->cfg.integrate_groups, dry, s);
     }
@@ -326,7 +326,7 @@ int tf_multi_create(const tf_params *p, uint32_t n, const float *poses, uint32_t
     m->t.off = (uint32_t *)(b + L.off);
     m->t.acc_hits = (unsigned long long *)(b + L.hits);
     m->t.mc = (MCtrl *)(b + L.mc);
-    m->t.wocc = (uint32_t *)(b + L.wocc);
+    m->t.wmask = (unsigned long long *)(b + L.wmask);
     m->t.bins = (Rec *)(b + L.bins);
     m->t.cap = cap;
     m->t.n_tiles = L.max_tiles;

@@ -59,8 +59,10 @@ def test_multi_workspace_size_and_validation():
     L = T.lib()
     one = T.tf_workspace_bytes(p)
     n3 = L.tf_multi_workspace_bytes(ctypes.byref(p), 3, 200, 150, 1 << 16)
-    # three submap workspaces, their block lists and the bins
-    assert 3 * one + 3 * 16 * p.n_blocks + (1 << 16) * 32 <= n3 < 3 * one + 3 * 16 * p.n_blocks + (1 << 16) * 32 + (8 << 20)
+    # three submap workspaces, their block lists, the bins and the world-cell
+    # submap masks (2^25 cells of 8 bytes)
+    base = 3 * one + 3 * 16 * p.n_blocks + (1 << 16) * 32 + (8 << 25)
+    assert base <= n3 < base + (8 << 20)
     assert L.tf_multi_workspace_bytes(ctypes.byref(p), 0, 200, 150, 1 << 16) == 0
     assert L.tf_multi_workspace_bytes(ctypes.byref(p), 65, 200, 150, 1 << 16) == 0
     assert L.tf_multi_workspace_bytes(ctypes.byref(p), 3, 200, 150, 0) == 0
