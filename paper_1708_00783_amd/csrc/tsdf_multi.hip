@@ -70,40 +70,146 @@ __global__ __launch_bounds__(NT) void k_m_integrate(const Vol *vols, const MFram
 // ============================================================================
 // tile bins of every view
 // ============================================================================
+// LDS of a binning workgroup: the distinct tiles of one chunk of blocks
+// (open addressing on the tile index) with their entry counts, then their
+// reserved positions
+constexpr int kBinSlots = 1024;
+constexpr int kBinProbes = 32;        // probes before a tile takes the global path
+constexpr int kBinDirect = 16;        // blocks over more tiles take the global path for all of them
+constexpr uint32_t kNoTile = 0xffffffffu;
+struct MBinLds {
+    uint32_t tile[kBinSlots];
+    uint32_t cnt[kBinSlots];
+    uint32_t pos[kBinSlots];
+    uint32_t first[kMaxSubmaps + 1];   // flat index of each submap's first block
+    float C[kMaxSubmaps][12];          // the view's camera composed with each submap pose
+};
+
+// slot of tile g in the chunk table, inserting it when `insert`; -1 when
+// the first kBinProbes slots of its probe sequence hold other tiles (or,
+// without insert, do not hold g).  Slots are never emptied within a chunk,
+// so a tile refused once is refused for the rest of the chunk.
+__device__ __forceinline__ int bin_slot(MBinLds &B, uint32_t g, bool insert)
+{
+    uint32_t sl = (g * 0x9e3779b1u) >> 22;   // 10 bits
+    for (int k = 0; k < kBinProbes; ++k) {
+        const uint32_t cur = insert ? atomicCAS(&B.tile[sl], kNoTile, g) : B.tile[sl];
+        if (cur == g || (insert && cur == kNoTile)) return (int)sl;
+        if (cur == kNoTile) return -1;
+        sl = (sl + 1u) & (uint32_t)(kBinSlots - 1);
+    }
+    return -1;
+}
+
+// Every allocated block of every submap against view blockIdx.y: its cube
+// grown by kExpand voxels gives the tiles whose bins take its record.  Count
+// pass (FILL false): entries per tile; fill pass: the records at the tile's
+// offset.  The blocks of all submaps form one flat index range (submap by
+// submap); a workgroup takes 256 consecutive blocks at a time and aggregates
+// their (block, tile) entries per distinct tile in LDS, so a tile costs one
+// global atomic per chunk instead of one per entry (an entry whose tile the
+// chunk table refuses, or of a block over many tiles, takes a global atomic
+// of its own).  The order of records within a bin is not fixed.
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_m_bin(const MSub *subs, const MFrame *f, MTiles t, float voxel)
 {
+    __shared__ MBinLds B;
     const int vi = (int)blockIdx.y;
     if (vi >= f->n_views) return;
     const Cam vc = f->view[vi].cam;
     const int ntx = f->view[vi].ntx, base = f->view[vi].tile_base;
     const int tw = f->tw, th = f->th;
     const int n_sub = f->n_sub;
-    for (int sm = 0; sm < n_sub; ++sm) {
-        const uint32_t n = subs[sm].ctrl->n_alloc;
-        const int4 *al = subs[sm].alist;
-        const float *M = f->C[vi][sm];
-        for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
-            const int4 b = al[i];
-            const int bx = (int16_t)(b.x & 0xffff), by = (int16_t)((uint32_t)b.x >> 16), bz = b.y;
-            Rec ex;
-            const bool hit =
-                cube_record(M, vc, voxel, 8 * bx - kExpand, 8 * by - kExpand, 8 * bz - kExpand, 8 + 2 * kExpand, ex);
-            if (!FILL) {
-                const unsigned long long m = __ballot(hit);
-                if (lane_id() == (uint32_t)(__ffsll((long long)m) - 1))
-                    atomicAdd(&t.mc->tot_blkview, (unsigned long long)__popcll(m));
+    for (int k = threadIdx.x; k < kBinSlots; k += 256) {
+        B.tile[k] = kNoTile;
+        B.cnt[k] = 0u;
+    }
+    for (int k = threadIdx.x; k < n_sub * 12; k += 256) B.C[k / 12][k % 12] = f->C[vi][k / 12][k % 12];
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0u;
+        for (int sm = 0; sm < n_sub; ++sm) {
+            B.first[sm] = acc;
+            acc += subs[sm].ctrl->n_alloc;
+        }
+        B.first[n_sub] = acc;
+    }
+    // Frustum pre-test: a grown cube whose bounding sphere lies wholly behind
+    // the near plane, or wholly beyond one of the planes through the camera
+    // centre and the image borders moved out by 2 pixels, has no point in
+    // front of the near plane that projects onto the image, so cube_record
+    // would reject it.  The planes in camera coordinates (x, y, z): u < -2 is
+    // fx x + (cx + 2) z < 0 and u > W + 1 is fx x + (cx - W - 1) z > 0 for
+    // z > 0, likewise v; their normals' lengths scale the sphere radius.  The
+    // radius (half the grown cube's diagonal) is padded far beyond the
+    // rounding of the centre's transform.
+    const float rad = (float)(4 + kExpand) * 1.7320508f * voxel * 1.01f + 1e-4f;
+    const float al_ = vc.cx + 2.0f, ar_ = vc.cx - (float)vc.W - 1.0f;
+    const float at_ = vc.cy + 2.0f, ab_ = vc.cy - (float)vc.H - 1.0f;
+    const float rl = rad * sqrtf(vc.fx * vc.fx + al_ * al_), rr = rad * sqrtf(vc.fx * vc.fx + ar_ * ar_);
+    const float rt = rad * sqrtf(vc.fy * vc.fy + at_ * at_), rb = rad * sqrtf(vc.fy * vc.fy + ab_ * ab_);
+    __syncthreads();
+    const uint32_t total = B.first[n_sub];
+    // whole chunks for every thread of the workgroup (barriers inside)
+    for (uint32_t c0 = blockIdx.x * 256u; c0 < total; c0 += gridDim.x * 256u) {
+        const uint32_t gi = c0 + threadIdx.x;
+        bool hit = false;
+        Rec ex, r;
+        int bx = 0, by = 0, bz = 0, ptr = 0, sm = 0;
+        const float *M = B.C[0];
+        if (gi < total) {
+            // the submap of flat index gi: the last with first[sm] <= gi
+#pragma unroll
+            for (int step = kMaxSubmaps / 2; step; step >>= 1)
+                if (sm + step < n_sub && B.first[sm + step] <= gi) sm += step;
+            M = B.C[sm];
+            const int4 b = subs[sm].alist[gi - B.first[sm]];
+            bx = (int16_t)(b.x & 0xffff);
+            by = (int16_t)((uint32_t)b.x >> 16);
+            bz = b.y;
+            ptr = b.z;
+            const float X = (float)(8 * bx + 4) * voxel, Y = (float)(8 * by + 4) * voxel;
+            const float Z = (float)(8 * bz + 4) * voxel;
+            const float xc = ((M[0] * X + M[1] * Y) + M[2] * Z) + M[3];
+            const float yc = ((M[4] * X + M[5] * Y) + M[6] * Z) + M[7];
+            const float zc = ((M[8] * X + M[9] * Y) + M[10] * Z) + M[11];
+            const bool outside = zc + rad < kZNear || vc.fx * xc + al_ * zc < -rl || vc.fx * xc + ar_ * zc > rr ||
+                                 vc.fy * yc + at_ * zc < -rt || vc.fy * yc + ab_ * zc > rb;
+            hit = !outside && cube_record(M, vc, voxel, 8 * bx - kExpand, 8 * by - kExpand, 8 * bz - kExpand,
+                                          8 + 2 * kExpand, ex);
+        }
+        if (!FILL) {
+            const unsigned long long m = __ballot(hit);
+            if (m && lane_id() == (uint32_t)(__ffsll((long long)m) - 1))
+                atomicAdd(&t.mc->tot_blkview, (unsigned long long)__popcll(m));
+        }
+        const int tx0 = hit ? ex.x0 / tw : 1, tx1 = hit ? ex.x1 / tw : 0;
+        const int ty0 = hit ? ex.y0 / th : 1, ty1 = hit ? ex.y1 / th : 0;
+        const bool direct = (tx1 - tx0 + 1) * (ty1 - ty0 + 1) > kBinDirect;
+        // entries per distinct tile of the chunk
+        for (int ty = ty0; ty <= ty1; ++ty)
+            for (int tx = tx0; tx <= tx1; ++tx) {
+                const uint32_t g = (uint32_t)(base + ty * ntx + tx);
+                const int sl = direct ? -1 : bin_slot(B, g, true);
+                if (sl >= 0)
+                    atomicAdd(&B.cnt[sl], 1u);
+                else if (!FILL)
+                    atomicAdd(&t.cnt[g], 1);
             }
-            if (!hit) continue;
-            const int tx0 = ex.x0 / tw, tx1 = ex.x1 / tw, ty0 = ex.y0 / th, ty1 = ex.y1 / th;
-            if (!FILL) {
-                for (int ty = ty0; ty <= ty1; ++ty)
-                    for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&t.cnt[base + ty * ntx + tx], 1);
-                continue;
-            }
-            // the search-range box of the block itself (empty when it is behind
-            // the near plane or off the image: then it only feeds the table)
-            Rec r;
+        __syncthreads();
+        // one global atomic per distinct tile: its count, or its range in the bin
+        for (int k = threadIdx.x; k < kBinSlots; k += 256) {
+            const uint32_t g = B.tile[k];
+            if (g == kNoTile) continue;
+            if (FILL)
+                B.pos[k] = t.off[g] + (uint32_t)atomicAdd(&t.cur[g], (int)B.cnt[k]);
+            else
+                atomicAdd(&t.cnt[g], (int)B.cnt[k]);
+        }
+        __syncthreads();
+        if (FILL && hit) {
+            // the search-range box of the block itself (empty when it is
+            // behind the near plane or off the image: then it only feeds
+            // the table)
             if (!cube_record(M, vc, voxel, 8 * bx, 8 * by, 8 * bz, 8, r)) {
                 r.x0 = 1;
                 r.x1 = 0;
@@ -116,15 +222,23 @@ __global__ __launch_bounds__(256) void k_m_bin(const MSub *subs, const MFrame *f
             r.by = (int16_t)by;
             r.bz = (int16_t)bz;
             r.pad = (int16_t)sm;
-            r.ptr = b.z;
+            r.ptr = ptr;
             r.pad2 = 0;
             for (int ty = ty0; ty <= ty1; ++ty)
                 for (int tx = tx0; tx <= tx1; ++tx) {
-                    const int g = base + ty * ntx + tx;
-                    const uint32_t idx = t.off[g] + (uint32_t)atomicAdd(&t.cur[g], 1);
+                    const uint32_t g = (uint32_t)(base + ty * ntx + tx);
+                    const int sl = direct ? -1 : bin_slot(B, g, false);
+                    const uint32_t idx =
+                        sl >= 0 ? atomicAdd(&B.pos[sl], 1u) : t.off[g] + (uint32_t)atomicAdd(&t.cur[g], 1);
                     if (idx < t.cap) t.bins[idx] = r;
                 }
         }
+        if (FILL) __syncthreads();   // every slot position taken before the table is cleared
+        for (int k = threadIdx.x; k < kBinSlots; k += 256) {
+            B.tile[k] = kNoTile;
+            B.cnt[k] = 0u;
+        }
+        __syncthreads();
     }
 }
 
