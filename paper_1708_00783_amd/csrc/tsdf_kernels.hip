@@ -342,10 +342,18 @@ __device__ __forceinline__ int lookup_block(const Vol &v, const TileTable *tt, i
         sl = (sl + 1u) & (uint32_t)(kTileTable - 1);
     }
     if (local) return -1;
-    if (!(gload(v.brick + brick_word(bx, by, bz)) & brick_bit(bx, by, bz))) return -1;
+    // the block's occupancy brick and its bucket entry, loaded together; the
+    // chain beyond the bucket only when the entry is another block's
+    const uint32_t h = hash_index(bx, by, bz, v.n_buckets - 1u);
+    const uint32_t bw = gload(v.brick + brick_word(bx, by, bz));
+    const int4 w = load_entry(v.entries, h);
+    if (!(bw & brick_bit(bx, by, bz))) return -1;
+    const uint32_t kxy = (uint32_t)(uint16_t)bx | ((uint32_t)(uint16_t)by << 16);
+    if ((uint32_t)w.x == kxy && (int16_t)(w.y & 0xffff) == (int16_t)bz && w.w >= 0) return w.w;
+    if (w.z < 1 || (uint32_t)(w.z - 1) >= v.n_excess) return -1;
     int ptr = -1;
-    const int e = find_entry_from(v.entries, v.n_buckets, v.n_excess, hash_index(bx, by, bz, v.n_buckets - 1u), bx,
-                                  by, bz, 0, &ptr);
+    const int e = find_entry_from(v.entries, v.n_buckets, v.n_excess, v.n_buckets + (uint32_t)(w.z - 1), bx, by, bz, 0,
+                                  &ptr);
     return e >= 0 ? ptr : -1;
 }
 

@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void k_m_bin(const MSub *subs, const MFrame *f
             r.bz = (int16_t)bz;
             r.pad = (int16_t)sm;
             r.ptr = ptr;
-            r.pad2 = 0;
+            r.pad2 = (int32_t)__float_as_uint(ex.zlo);   // the grown cube's least camera depth (table depth cut)
             for (int ty = ty0; ty <= ty1; ++ty)
                 for (int tx = tx0; tx <= tx1; ++tx) {
                     const uint32_t g = (uint32_t)(base + ty * ntx + tx);
@@ -352,6 +352,24 @@ __global__ __launch_bounds__(256) void k_m_mark(const Vol *vols, const MSub *sub
 // ============================================================================
 namespace {
 
+// Depth buckets of the table cut: 1/32 octave each from the near plane up
+// (the float bits of a depth above the near plane, shifted), 256 buckets
+// (about 0.05 to 12.8 m; deeper depths share the last)
+constexpr uint32_t kZBuckets = 256;
+constexpr uint32_t kZNearBits = 0x3d4ccccdu;   // kZNear's float bits
+
+__device__ __forceinline__ uint32_t zbucket(uint32_t zbits)
+{
+    const int b = (int)(zbits >> 18) - (int)(kZNearBits >> 18);
+    return b < 0 ? 0u : (b >= (int)kZBuckets ? kZBuckets - 1u : (uint32_t)b);
+}
+
+// least depth of bucket b (b >= 1)
+__device__ __forceinline__ float zbucket_floor(uint32_t b)
+{
+    return __uint_as_float(((kZNearBits >> 18) + b) << 18);
+}
+
 // LDS of one tile: the (submap, block) -> pointer table, the tile's submaps
 // in ascending order with what the field reads, and the per-pixel range
 template <int NT>
@@ -366,6 +384,8 @@ struct MTileLds {
     int smid[kMaxSubmaps];
     unsigned long long mask;
     uint32_t n_tab, hits, unfit;                // unfit: a record whose key or pointer does not pack
+    uint32_t cut;                               // depth buckets 0 .. cut - 1 are in the table
+    float dlim;                                 // a lookup miss proves absence for reads of points shallower than this
     uint32_t zlo[NT], zhi[NT];                  // per-pixel range as float bits (all values > 0)
     uint32_t zlo_all, zhi_all;                  // from records covering the whole tile
 };
@@ -415,12 +435,36 @@ __device__ __forceinline__ void m_tile_setup(const MSub *subs, const MTiles &t, 
     uint32_t o1 = t.off[g + 1];
     if (o1 > t.cap) o1 = t.cap;
     const int n = o1 > o0 ? (int)(o1 - o0) : 0;
+    uint32_t cut = kZBuckets;
+    if (n > TT / 2) {
+        // More records than the table holds: those nearest the camera go in.
+        // A histogram of the grown cubes' least depths (in the table's first
+        // slots, cleared again below) gives the largest bucket prefix that
+        // fits; a read at a point shallower than the first left-out bucket
+        // cannot touch a left-out block (it lies in that block's grown cube).
+        __syncthreads();
+        uint32_t *hist = reinterpret_cast<uint32_t *>(L.slot);
+        for (int j = (int)threadIdx.x; j < n; j += NT)
+            atomicAdd(&hist[zbucket((uint32_t)t.bins[o0 + (uint32_t)j].pad2)], 1u);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t acc = 0u, c = 0u;
+            while (c < kZBuckets && acc + hist[c] <= (uint32_t)(TT / 2)) acc += hist[c++];
+            L.cut = c;
+        }
+        __syncthreads();
+        cut = L.cut;
+        for (int k = threadIdx.x; k < kZBuckets; k += NT) hist[k] = 0u;
+    }
+    if (threadIdx.x == 0) L.dlim = cut >= kZBuckets ? __builtin_inff() : zbucket_floor(cut);
     __syncthreads();
     for (int j = (int)threadIdx.x; j < n; j += NT) {
         const Rec r = t.bins[o0 + (uint32_t)j];
         atomicOr(&L.mask, 1ull << (uint32_t)r.pad);
-        // keys in one bin are distinct; keep the table at most half full
-        if (!mfits(r.bx, r.by, r.bz) || r.ptr >= (1 << 24)) {
+        // keys in one bin are distinct; the table is at most half full
+        if (zbucket((uint32_t)r.pad2) >= cut) {
+            // left out: deeper than the table's depth limit
+        } else if (!mfits(r.bx, r.by, r.bz) || r.ptr >= (1 << 24)) {
             L.unfit = 1u;
         } else if (atomicAdd(&L.n_tab, 1u) < (uint32_t)(TT / 2)) {
             const unsigned long long val = mkey(r.pad, r.bx, r.by, r.bz) | (unsigned long long)r.ptr;
@@ -500,10 +544,17 @@ __device__ __forceinline__ int m_lookup(const MTileLds<NT> &L, int k, int bx, in
         }
     }
     if (local) return -1;
+    // the bucket's occupancy bit and its entry, loaded together; the chain
+    // beyond the bucket only when the entry is another block's
     const uint32_t h = hash_index(bx, by, bz, L.nb[k] - 1u);
-    if (!((gload(L.occ[k] + (h >> 5)) >> (h & 31u)) & 1u)) return -1;
+    const uint32_t ow = gload(L.occ[k] + (h >> 5));
+    const int4 w = load_entry(L.ent[k], h);
+    if (!((ow >> (h & 31u)) & 1u)) return -1;
+    const uint32_t kxy = (uint32_t)(uint16_t)bx | ((uint32_t)(uint16_t)by << 16);
+    if ((uint32_t)w.x == kxy && (int16_t)(w.y & 0xffff) == (int16_t)bz && w.w >= 0) return w.w;
+    if (w.z < 1 || (uint32_t)(w.z - 1) >= L.ne[k]) return -1;
     int ptr = -1;
-    const int e = find_entry_in(L.ent[k], L.nb[k], L.ne[k], bx, by, bz, 0, &ptr);
+    const int e = find_entry_from(L.ent[k], L.nb[k], L.ne[k], L.nb[k] + (uint32_t)(w.z - 1), bx, by, bz, 0, &ptr);
     return e >= 0 ? ptr : -1;
 }
 
@@ -654,7 +705,11 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
     float zmin, zmax;
     m_tile_setup<NT, TW, TH>(subs, t, (uint32_t)g, tx0, ty0, L);
     m_pixel_range<NT>(L, ly * TW + lx, zmin, zmax);
-    const bool full = L.n_tab <= (uint32_t)(MTileLds<NT>::TT / 2) && !L.unfit;   // the table holds the whole bin
+    // the table holds every record of the bin shallower than its depth cut
+    const bool full = L.n_tab <= (uint32_t)(MTileLds<NT>::TT / 2) && !L.unfit;
+    // reads at points shallower than dcut (the cut less a voxel for the
+    // normal's taps and a millimetre for rounding) can trust a table miss
+    const float dcut = L.dlim - voxel - 1e-3f;
     const bool inside = px < W && py < H;
     float4 out_p = make_float4(0.f, 0.f, 0.f, 0.f), out_n = make_float4(0.f, 0.f, 0.f, 0.f);
     if (inside && zmin <= zmax) {
@@ -709,7 +764,7 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
             }
             ++steps;
             const float P0 = ox + tt * dx, P1 = oy + tt * dy, P2 = oz + tt * dz;
-            const bool local = full && tt * zscale >= kZNear;
+            const bool local = full && tt * zscale >= kZNear && tt * zscale < dcut;
             // only the submaps of P's world cell can be allocated there
             const unsigned long long cm = m_cell_mask<NT>(t, L, P0, P1, P2);
             const bool alloc = cm && m_allocated(L, cm, P0, P1, P2, local);
@@ -756,13 +811,15 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
         if (state == M_BEHIND) {
             tt += F * mu_v;
             float P0 = ox + tt * dx, P1 = oy + tt * dy, P2 = oz + tt * dz;
-            F = m_field(L, m_cell_mask<NT>(t, L, P0, P1, P2), P0, P1, P2, full && tt * zscale >= kZNear);
+            F = m_field(L, m_cell_mask<NT>(t, L, P0, P1, P2), P0, P1, P2,
+                        full && tt * zscale >= kZNear && tt * zscale < dcut);
             tt += F * mu_v;
             P0 = ox + tt * dx;
             P1 = oy + tt * dy;
             P2 = oz + tt * dz;
             out_p = make_float4(P0 * voxel, P1 * voxel, P2 * voxel, 1.0f);
-            const bool lh = full && tt * zscale >= kZNear;   // the taps lie within 2 voxels of the hit
+            // the taps lie within a voxel of the hit, which the cut's margin covers
+            const bool lh = full && tt * zscale >= kZNear && tt * zscale < dcut;
             auto fld = [&](float X, float Y, float Z) { return m_field(L, m_cell_mask<NT>(t, L, X, Y, Z), X, Y, Z, lh); };
             const float gx = (fld(P0 + 1.0f, P1, P2) - fld(P0 - 1.0f, P1, P2)) * 0.5f;
             const float gy = (fld(P0, P1 + 1.0f, P2) - fld(P0, P1 - 1.0f, P2)) * 0.5f;
