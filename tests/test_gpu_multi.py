@@ -165,3 +165,30 @@ def test_autotune_picks_a_supported_shape_and_keeps_results():
     mp.integrate(4)
     for i in SCHEDULE[4]:
         compare_tables(mp.g.submap(i), mp.ovols[i], f"after autotune, submap {i}")
+
+
+def test_tiny_views_whose_bins_overflow_the_tile_table():
+    """One-tile views (16x16 pixels for 16x16 tiles, 8x8 for 8x8) that see the
+    whole scene: every block of the three submaps lands in the view's one
+    tile, so its bin holds more records than the tile's LDS table (2048 at
+    16x16, 1024 at 8x8) and the table keeps the records nearest the camera;
+    the outputs still match the oracle."""
+    mp = MultiPair()
+    for k in range(len(mp.d)):
+        mp.integrate(k)
+    import torch
+    eye = look_at([1.1, -0.9, 0.8], [0.0, 0.0, 0.2]).astype(np.float32)
+    for tw, th, intr, cap in ((16, 16, Intrinsics(9.0, 9.0, 7.5, 7.5, 16, 16), 2048),
+                              (8, 8, Intrinsics(4.5, 4.5, 3.5, 3.5, 8, 8), 1024)):
+        mp.g.set_config(tile_w=tw, tile_h=th)
+        pts = torch.full((intr.height, intr.width, 4), -7.0, dtype=torch.float32, device="cuda")
+        nrm = torch.full_like(pts, -7.0)
+        b0 = mp.g.stats()["total_bin_entries"]
+        mp.g.raycast([(intr, eye, pts, nrm)])
+        entries = mp.g.stats()["total_bin_entries"] - b0
+        _log(f"one {tw}x{th} tile: {entries} bin entries, table {cap}")
+        assert entries > cap
+        op, on = mp.o.raycast(intr.width, intr.height, intr.as_array(), eye)
+        nhit, flips = compare_raycast(pts.cpu().numpy(), nrm.cpu().numpy(), op, on, f"one-tile view {tw}x{th}")
+        _log(f"one-tile view {intr.width}x{intr.height}: hits {nhit} flips {flips}")
+        assert nhit > 0.2 * intr.width * intr.height
