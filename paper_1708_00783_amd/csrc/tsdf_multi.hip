@@ -527,6 +527,60 @@ __device__ __forceinline__ void m_pixel_range(const MTileLds<NT> &L, int pi, flo
 // the tile's bin and the read belongs to a ray point at or beyond the near
 // plane: every block within 3 voxels of such a point is in the bin (blocks
 // are binned by their cube grown by 3 voxels), so a miss proves absence.
+// A lookup in two halves, so that two submaps' lookups can be in flight
+// together: begin probes the LDS table and, when the table cannot answer,
+// issues the bucket's occupancy word and entry loads; end resolves them
+// (walking the chain beyond the bucket when the entry is another block's).
+struct MLookup {
+    int ptr;        // the answer when `pending` is false
+    bool pending;
+    uint32_t h, ow;
+    int4 w;
+};
+
+template <int NT>
+__device__ __forceinline__ void m_lookup_begin(const MTileLds<NT> &L, int k, int bx, int by, int bz, bool local,
+                                               MLookup &q)
+{
+    constexpr int TT = MTileLds<NT>::TT;
+    q.pending = false;
+    q.ptr = -1;
+    if (!in_short_range(bx) || !in_short_range(by) || !in_short_range(bz)) return;
+    const int sm = L.smid[k];
+    if (mfits(bx, by, bz)) {
+        const unsigned long long key = mkey(sm, bx, by, bz) >> 24;
+        uint32_t sl = mslot<NT>(sm, bx, by, bz);
+        for (int it = 0; it < TT; ++it) {
+            const unsigned long long kk = L.slot[sl];
+            if ((kk >> 24) == key) {
+                q.ptr = (int)(kk & 0xffffffull);
+                return;
+            }
+            if (kk == 0ull) break;
+            sl = (sl + 1u) & (uint32_t)(TT - 1);
+        }
+    }
+    if (local) return;
+    q.pending = true;
+    q.h = hash_index(bx, by, bz, L.nb[k] - 1u);
+    q.ow = gload(L.occ[k] + (q.h >> 5));
+    q.w = load_entry(L.ent[k], q.h);
+}
+
+template <int NT>
+__device__ __forceinline__ int m_lookup_end(const MTileLds<NT> &L, int k, int bx, int by, int bz, const MLookup &q)
+{
+    if (!q.pending) return q.ptr;
+    if (!((q.ow >> (q.h & 31u)) & 1u)) return -1;
+    const uint32_t kxy = (uint32_t)(uint16_t)bx | ((uint32_t)(uint16_t)by << 16);
+    const int4 w = q.w;
+    if ((uint32_t)w.x == kxy && (int16_t)(w.y & 0xffff) == (int16_t)bz && w.w >= 0) return w.w;
+    if (w.z < 1 || (uint32_t)(w.z - 1) >= L.ne[k]) return -1;
+    int ptr = -1;
+    const int e = find_entry_from(L.ent[k], L.nb[k], L.ne[k], L.nb[k] + (uint32_t)(w.z - 1), bx, by, bz, 0, &ptr);
+    return e >= 0 ? ptr : -1;
+}
+
 template <int NT>
 __device__ __forceinline__ int m_lookup(const MTileLds<NT> &L, int k, int bx, int by, int bz, bool local)
 {
@@ -599,75 +653,130 @@ __device__ __forceinline__ bool m_allocated(const MTileLds<NT> &L, unsigned long
     return false;
 }
 
+// one submap's trilinear cell at P: the fractions, the base voxel and its
+// block, the crossed faces and (once set up) the corner pointers
+struct MCell {
+    float tx, ty, tz;
+    int ix, iy, iz;
+    int p[8];
+};
+
+template <int NT>
+__device__ __forceinline__ void m_cell_begin(const MTileLds<NT> &L, int k, float P0, float P1, float P2, bool local,
+                                             MCell &C, MLookup &q)
+{
+    float Q0, Q1, Q2;
+    to_sub(L, k, P0, P1, P2, Q0, Q1, Q2);
+    const float fbx = floorf(Q0), fby = floorf(Q1), fbz = floorf(Q2);
+    C.tx = Q0 - fbx;
+    C.ty = Q1 - fby;
+    C.tz = Q2 - fbz;
+    C.ix = (int)fbx;
+    C.iy = (int)fby;
+    C.iz = (int)fbz;
+    m_lookup_begin(L, k, C.ix >> 3, C.iy >> 3, C.iz >> 3, local, q);
+}
+
+// the corner pointers: the cell's own block from the pending lookup, the
+// blocks across crossed faces looked up directly
+template <int NT>
+__device__ __forceinline__ void m_cell_end(const MTileLds<NT> &L, int k, bool local, MCell &C, const MLookup &q)
+{
+    const int Bx = C.ix >> 3, By = C.iy >> 3, Bz = C.iz >> 3;
+    const bool sx = (C.ix & 7) == 7, sy = (C.iy & 7) == 7, sz = (C.iz & 7) == 7;
+    const int p000 = m_lookup_end(L, k, Bx, By, Bz, q);
+    int p100 = p000, p010 = p000, p001 = p000, p110 = p000, p101 = p000, p011 = p000, p111 = p000;
+    if (sx | sy | sz) {
+        if (sx) p100 = m_lookup(L, k, Bx + 1, By, Bz, local);
+        if (sy) p010 = m_lookup(L, k, Bx, By + 1, Bz, local);
+        if (sz) p001 = m_lookup(L, k, Bx, By, Bz + 1, local);
+        p110 = (sx & sy) ? m_lookup(L, k, Bx + 1, By + 1, Bz, local) : (sx ? p100 : p010);
+        p101 = (sx & sz) ? m_lookup(L, k, Bx + 1, By, Bz + 1, local) : (sx ? p100 : p001);
+        p011 = (sy & sz) ? m_lookup(L, k, Bx, By + 1, Bz + 1, local) : (sy ? p010 : p001);
+        p111 = (sx & sy & sz) ? m_lookup(L, k, Bx + 1, By + 1, Bz + 1, local)
+                              : (sx & sy) ? p110 : (sx & sz) ? p101 : (sy & sz) ? p011 : sx ? p100 : sy ? p010 : p001;
+    }
+    C.p[0] = p000;
+    C.p[1] = p100;
+    C.p[2] = p010;
+    C.p[3] = p110;
+    C.p[4] = p001;
+    C.p[5] = p101;
+    C.p[6] = p011;
+    C.p[7] = p111;
+}
+
+// the cell's SDF and weight reads (an absent corner reads block 0; its
+// values are not used)
+template <int NT>
+__device__ __forceinline__ void m_cell_load(const MTileLds<NT> &L, int k, const MCell &C, int16_t (&s)[8],
+                                            uint8_t (&w8)[8])
+{
+    const uint8_t *vox = L.vox[k];
+    int j[8];
+    cell_index(C.ix, C.iy, C.iz, (C.ix & 7) == 7, (C.iy & 7) == 7, (C.iz & 7) == 7, j);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const uint8_t *blk = vox + (size_t)(C.p[c] >= 0 ? C.p[c] : 0) * kBlockBytes;
+        s[c] = gload(reinterpret_cast<const int16_t *>(blk) + j[c]);
+        w8[c] = gload(blk + 1024 + j[c]);
+    }
+}
+
+// one submap's term of the combined field: its trilinear weight (absent
+// voxels weigh 0, same lerp order as the SDF) and, when positive, its F
+__device__ __forceinline__ void m_cell_accumulate(const MCell &C, const int16_t (&s)[8], const uint8_t (&w8)[8],
+                                                  int &cnt, float &first, float &num, float &den)
+{
+    float wf[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) wf[c] = C.p[c] >= 0 ? (float)w8[c] : 0.0f;
+    const float c00 = wf[0] + (wf[1] - wf[0]) * C.tx;
+    const float c10 = wf[2] + (wf[3] - wf[2]) * C.tx;
+    const float c01 = wf[4] + (wf[5] - wf[4]) * C.tx;
+    const float c11 = wf[6] + (wf[7] - wf[6]) * C.tx;
+    const float c0 = c00 + (c10 - c00) * C.ty;
+    const float c1 = c01 + (c11 - c01) * C.ty;
+    const float w = c0 + (c1 - c0) * C.tz;
+    if (!(w > 0.0f)) return;
+    uint32_t present = 0u;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) present |= (C.p[c] >= 0 ? 1u : 0u) << c;
+    const float F = cell_lerp(present, s, C.tx, C.ty, C.tz);
+    if (cnt == 0) first = F;
+    num = num + w * F;
+    den = den + w;
+    ++cnt;
+}
+
 // combined field at world voxel-unit P over the submaps of P's cell mask cm
 // (every submap with positive weight at P is one of them), in ascending
-// submap order
+// submap order.  Submaps are taken two at a time: both cells' lookups, then
+// both cells' reads are in flight together before either term is added.
 template <int NT>
 __device__ __forceinline__ float m_field(const MTileLds<NT> &L, unsigned long long cm, float P0, float P1, float P2,
                                          bool local)
 {
     int cnt = 0;
     float first = 1.0f, num = 0.0f, den = 0.0f;
-    for (; cm; cm &= cm - 1ull) {
-        const int k = tile_slot(L, __ffsll((long long)cm) - 1);
-        float Q0, Q1, Q2;
-        to_sub(L, k, P0, P1, P2, Q0, Q1, Q2);
-        const float fbx = floorf(Q0), fby = floorf(Q1), fbz = floorf(Q2);
-        Cell C;
-        C.tx = Q0 - fbx;
-        C.ty = Q1 - fby;
-        C.tz = Q2 - fbz;
-        const int ix = (int)fbx, iy = (int)fby, iz = (int)fbz;
-        const int Bx = ix >> 3, By = iy >> 3, Bz = iz >> 3;
-        const bool sx = (ix & 7) == 7, sy = (iy & 7) == 7, sz = (iz & 7) == 7;
-        const int p000 = m_lookup(L, k, Bx, By, Bz, local);
-        int p100 = p000, p010 = p000, p001 = p000, p110 = p000, p101 = p000, p011 = p000, p111 = p000;
-        if (sx | sy | sz) {
-            if (sx) p100 = m_lookup(L, k, Bx + 1, By, Bz, local);
-            if (sy) p010 = m_lookup(L, k, Bx, By + 1, Bz, local);
-            if (sz) p001 = m_lookup(L, k, Bx, By, Bz + 1, local);
-            p110 = (sx & sy) ? m_lookup(L, k, Bx + 1, By + 1, Bz, local) : (sx ? p100 : p010);
-            p101 = (sx & sz) ? m_lookup(L, k, Bx + 1, By, Bz + 1, local) : (sx ? p100 : p001);
-            p011 = (sy & sz) ? m_lookup(L, k, Bx, By + 1, Bz + 1, local) : (sy ? p010 : p001);
-            p111 = (sx & sy & sz) ? m_lookup(L, k, Bx + 1, By + 1, Bz + 1, local)
-                                  : (sx & sy) ? p110 : (sx & sz) ? p101 : (sy & sz) ? p011 : sx ? p100 : sy ? p010 : p001;
-        }
-        C.p[0] = p000;
-        C.p[1] = p100;
-        C.p[2] = p010;
-        C.p[3] = p110;
-        C.p[4] = p001;
-        C.p[5] = p101;
-        C.p[6] = p011;
-        C.p[7] = p111;
-        const uint8_t *vox = L.vox[k];
-        int16_t s[8];
-        uint8_t w8[8];
-        cell_index(ix, iy, iz, sx, sy, sz, C.j);
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            // an absent corner reads block 0 (its values are not used)
-            const uint8_t *blk = vox + (size_t)(C.p[c] >= 0 ? C.p[c] : 0) * kBlockBytes;
-            s[c] = gload(reinterpret_cast<const int16_t *>(blk) + C.j[c]);
-            w8[c] = gload(blk + 1024 + C.j[c]);
-        }
-        // trilinear weight (absent voxels weigh 0), same order as the SDF
-        float wf[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) wf[c] = C.p[c] >= 0 ? (float)w8[c] : 0.0f;
-        const float c00 = wf[0] + (wf[1] - wf[0]) * C.tx;
-        const float c10 = wf[2] + (wf[3] - wf[2]) * C.tx;
-        const float c01 = wf[4] + (wf[5] - wf[4]) * C.tx;
-        const float c11 = wf[6] + (wf[7] - wf[6]) * C.tx;
-        const float c0 = c00 + (c10 - c00) * C.ty;
-        const float c1 = c01 + (c11 - c01) * C.ty;
-        const float w = c0 + (c1 - c0) * C.tz;
-        if (!(w > 0.0f)) continue;
-        const float F = cell_interp(C, s);
-        if (cnt == 0) first = F;
-        num = num + w * F;
-        den = den + w;
-        ++cnt;
+    while (cm) {
+        const int ka = tile_slot(L, __ffsll((long long)cm) - 1);
+        cm &= cm - 1ull;
+        const bool two = cm != 0ull;
+        const int kb = two ? tile_slot(L, __ffsll((long long)cm) - 1) : ka;
+        if (two) cm &= cm - 1ull;
+        MCell A, B;
+        MLookup qa, qb;
+        m_cell_begin(L, ka, P0, P1, P2, local, A, qa);
+        if (two) m_cell_begin(L, kb, P0, P1, P2, local, B, qb);
+        m_cell_end(L, ka, local, A, qa);
+        if (two) m_cell_end(L, kb, local, B, qb);
+        int16_t sa[8], sb[8];
+        uint8_t wa[8], wb[8];
+        m_cell_load(L, ka, A, sa, wa);
+        if (two) m_cell_load(L, kb, B, sb, wb);
+        m_cell_accumulate(A, sa, wa, cnt, first, num, den);
+        if (two) m_cell_accumulate(B, sb, wb, cnt, first, num, den);
     }
     if (cnt == 0) return 1.0f;
     if (cnt == 1) return first;
@@ -820,10 +929,27 @@ __global__ __launch_bounds__(TW *TH) void k_m_raycast(const MSub *subs, const MF
             out_p = make_float4(P0 * voxel, P1 * voxel, P2 * voxel, 1.0f);
             // the taps lie within a voxel of the hit, which the cut's margin covers
             const bool lh = full && tt * zscale >= kZNear && tt * zscale < dcut;
-            auto fld = [&](float X, float Y, float Z) { return m_field(L, m_cell_mask<NT>(t, L, X, Y, Z), X, Y, Z, lh); };
-            const float gx = (fld(P0 + 1.0f, P1, P2) - fld(P0 - 1.0f, P1, P2)) * 0.5f;
-            const float gy = (fld(P0, P1 + 1.0f, P2) - fld(P0, P1 - 1.0f, P2)) * 0.5f;
-            const float gz = (fld(P0, P1, P2 + 1.0f) - fld(P0, P1, P2 - 1.0f)) * 0.5f;
+            // the six taps P +- e_a, one per step of a rolled loop (one copy
+            // of the field code, kept by selects)
+            float fp0 = 0.0f, fm0 = 0.0f, fp1 = 0.0f, fm1 = 0.0f, fp2 = 0.0f, fm2 = 0.0f;
+#pragma unroll 1
+            for (int tap = 0; tap < 6; ++tap) {
+                const int ax = tap >> 1;
+                const bool minus = (tap & 1) != 0;
+                const float X = ax == 0 ? (minus ? P0 - 1.0f : P0 + 1.0f) : P0;
+                const float Y = ax == 1 ? (minus ? P1 - 1.0f : P1 + 1.0f) : P1;
+                const float Z = ax == 2 ? (minus ? P2 - 1.0f : P2 + 1.0f) : P2;
+                const float f = m_field(L, m_cell_mask<NT>(t, L, X, Y, Z), X, Y, Z, lh);
+                fp0 = tap == 0 ? f : fp0;
+                fm0 = tap == 1 ? f : fm0;
+                fp1 = tap == 2 ? f : fp1;
+                fm1 = tap == 3 ? f : fm1;
+                fp2 = tap == 4 ? f : fp2;
+                fm2 = tap == 5 ? f : fm2;
+            }
+            const float gx = (fp0 - fm0) * 0.5f;
+            const float gy = (fp1 - fm1) * 0.5f;
+            const float gz = (fp2 - fm2) * 0.5f;
             const float gn = sqrtf((gx * gx + gy * gy) + gz * gz);
             if (gn > 0.0f) out_n = make_float4(gx / gn, gy / gn, gz / gn, 1.0f);
         }
