@@ -588,10 +588,10 @@ __global__ __launch_bounds__(256) void k_raycast(Vol v, Cam c, int all_blocks, f
     __shared__ TileTable tbl;
     const int ntx = (c.W + kTile - 1) / kTile, nty = (c.H + kTile - 1) / kTile;
     const int ntiles = ntx * nty;
-    // workgroups go round-robin to the 8 XCDs: XCD k gets the k-th band of
-    // tiles, so its L2 holds the blocks of one band of the image
-    const int per = (ntiles + 7) / 8;
-    const int tile = (int)(blockIdx.x % 8u) * per + (int)(blockIdx.x / 8u);
+    // workgroups go round-robin to the 8 XCDs; tiles in launch order, so that
+    // the slow tiles of a region (long rays) spread over all XCDs (a band of
+    // the image per XCD, for L2 locality, measured 2% slower)
+    const int tile = (int)blockIdx.x;
     const bool real = tile < ntiles;
     const int q = (int)threadIdx.x >> 6, i = (int)threadIdx.x & 63;
     const int lx = (q & 1) * 8 + (i & 7), ly = (q >> 1) * 8 + (i >> 3);
@@ -1059,8 +1059,7 @@ hipError_t launch_range_bin(const Vol &v, const Cam &c, bool all_blocks, hipStre
 
 hipError_t launch_raycast(const Vol &v, const Cam &c, bool all_blocks, float4 *pts, float4 *nrm, hipStream_t s)
 {
-    const int ntiles = ((c.W + kTile - 1) / kTile) * ((c.H + kTile - 1) / kTile);
-    const int grid = ((ntiles + 7) / 8) * 8;     // whole rounds of the 8 XCDs (see the tile mapping)
+    const int grid = ((c.W + kTile - 1) / kTile) * ((c.H + kTile - 1) / kTile);   // one workgroup per tile
     if ((size_t)v.n_blocks * kBlockBytes <= 0xffffffffu)
         hipLaunchKernelGGL(k_raycast<true>, dim3(grid), dim3(256), 0, s, v, c, all_blocks ? 1 : 0, pts, nrm);
     else
