@@ -192,3 +192,40 @@ def test_tiny_views_whose_bins_overflow_the_tile_table():
         nhit, flips = compare_raycast(pts.cpu().numpy(), nrm.cpu().numpy(), op, on, f"one-tile view {tw}x{th}")
         _log(f"one-tile view {intr.width}x{intr.height}: hits {nhit} flips {flips}")
         assert nhit > 0.2 * intr.width * intr.height
+
+
+def test_close_view_blocks_over_many_tiles():
+    """A 200x150 view 7 cm from the sphere's surface: a block's grown cube
+    covers dozens of 16x16 tiles, so the binning takes its global path for
+    those blocks (no per-chunk aggregation); the outputs match the oracle."""
+    mp = MultiPair()
+    for k in range(len(mp.d)):
+        mp.integrate(k)
+    import torch
+    eye = look_at([0.26, -0.15, 0.35], [0.0, 0.0, 0.25]).astype(np.float32)
+    mp.g.set_config(tile_w=16, tile_h=16)
+    pts = torch.full((VIEW2.height, VIEW2.width, 4), -7.0, dtype=torch.float32, device="cuda")
+    nrm = torch.full_like(pts, -7.0)
+    b0 = mp.g.stats()
+    mp.g.raycast([(VIEW2, eye, pts, nrm)])
+    b1 = mp.g.stats()
+    entries = b1["total_bin_entries"] - b0["total_bin_entries"]
+    pairs = b1["total_block_views"] - b0["total_block_views"]
+    # tiles of the grown cubes (3 voxels) of submap 0's blocks (its pose is the identity)
+    pos = mp.ovols[0].allocated_positions().astype(np.float64)
+    c = np.array([[(k & 1), (k >> 1) & 1, k >> 2] for k in range(8)], np.float64)
+    X = ((pos[:, None, :] * 8 - 3) + c[None] * 14) * VP.voxel_size
+    Pc = X @ eye[:3, :3].T.astype(np.float64) + eye[:3, 3]
+    front = (Pc[..., 2] > 0.05).all(1)
+    u = VIEW2.fx * Pc[front][..., 0] / Pc[front][..., 2] + VIEW2.cx
+    v = VIEW2.fy * Pc[front][..., 1] / Pc[front][..., 2] + VIEW2.cy
+    u0, u1 = np.clip(u.min(1), 0, VIEW2.width - 1), np.clip(u.max(1), 0, VIEW2.width - 1)
+    v0, v1 = np.clip(v.min(1), 0, VIEW2.height - 1), np.clip(v.max(1), 0, VIEW2.height - 1)
+    ntiles = (u1 // 16 - u0 // 16 + 1) * (v1 // 16 - v0 // 16 + 1)
+    _log(f"close view: {pairs} blocks in view, {entries} bin entries; submap 0: {int((ntiles > 16).sum())} "
+         f"blocks over 16 tiles, at most {int(ntiles.max())}")
+    assert (ntiles > 16).sum() > 10
+    op, on = mp.o.raycast(VIEW2.width, VIEW2.height, VIEW2.as_array(), eye)
+    nhit, flips = compare_raycast(pts.cpu().numpy(), nrm.cpu().numpy(), op, on, "close view")
+    _log(f"close view: hits {nhit} flips {flips}")
+    assert nhit > 0.2 * VIEW2.width * VIEW2.height
