@@ -127,34 +127,22 @@ __device__ __forceinline__ void cam_transform(const Cam &c, float X, float Y, fl
 
 // Pop up to one element per requesting lane from a stack whose height is
 // *head (Sec. 4.2 "atomic subtraction on a stack of free voxel block
-// indices"), with one atomic per wave; the height never goes below zero.
+// indices"), with one atomic subtraction per wave.  Past exhaustion the
+// height goes below zero and later pops get nothing; the visible-list kernel
+// that follows every insertion clamps it back to zero before the stack takes
+// any push.
 __device__ __forceinline__ int32_t wave_pop(int32_t *head, const int32_t *stack, bool want)
 {
     unsigned long long m = __ballot(want);
     if (m == 0) return -1;
     const int cnt = __popcll(m);
     const int leader = __ffsll((long long)m) - 1;
-    int base = 0, take = 0;
-    if ((int)lane_id() == leader) {
-        int cur = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        for (;;) {
-            take = cur < cnt ? cur : cnt;
-            if (take <= 0) {
-                take = 0;
-                break;
-            }
-            int prev = atomicCAS(head, cur, cur - take);
-            if (prev == cur) {
-                base = cur - take;
-                break;
-            }
-            cur = prev;
-        }
-    }
-    base = __shfl(base, leader);
-    take = __shfl(take, leader);
+    int old = 0;
+    if ((int)lane_id() == leader) old = atomicSub(head, cnt);
+    old = __shfl(old, leader);
+    const int take = old < 0 ? 0 : (old < cnt ? old : cnt);
     const int r = (int)rank_in(m);
-    if (want && r < take) return stack[base + take - 1 - r];
+    if (want && r < take) return stack[old - 1 - r];
     return -1;
 }
 
@@ -320,7 +308,12 @@ __device__ __forceinline__ void insert_body(const Vol &v, const Cam &c)
     const uint32_t lane = lane_id();
     const uint32_t gwave = (blockIdx.x * 256u + threadIdx.x) / kWave;
     const uint32_t nwaves = gridDim.x * (256u / kWave);
+    // the request count and this wave's first requests load together (the
+    // list has max_req slots; those past the count are not used)
     uint32_t n = v.ctrl->n_req;
+    const uint32_t first = gwave * kWave;
+    Req rq = {};
+    if (first + lane < v.max_req) rq = v.reqs[first + lane];
     if (n > v.max_req) n = v.max_req;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         v.ctrl->sweep_req = v.ctrl->req_overflow;
@@ -328,14 +321,14 @@ __device__ __forceinline__ void insert_body(const Vol &v, const Cam &c)
         v.ctrl->n_vis = 0u;   // the compaction's counter (the previous list is re-tested)
     }
 
-    for (uint32_t base = gwave * kWave; base < n; base += nwaves * kWave) {
+    for (uint32_t base = first; base < n; base += nwaves * kWave) {
         const uint32_t i = base + lane;
         const bool active = i < n;
         int bx = 0, by = 0, bz = 0;
         if (active) {
-            Req r = v.reqs[i];
-            v.reqset[r.slot] = 0ull;
-            unpack_key(r.key, bx, by, bz);
+            if (base != first) rq = v.reqs[i];
+            v.reqset[rq.slot] = 0ull;
+            unpack_key(rq.key, bx, by, bz);
         }
         // a request for a swapped-out block revives its entry (Sec. 5)
         int revive = -1;
@@ -344,9 +337,13 @@ __device__ __forceinline__ void insert_body(const Vol &v, const Cam &c)
             const int e = find_entry(v, bx, by, bz, kPtrSwapped, &pp);
             if (e >= 0 && pp == kPtrSwapped) revive = e;
         }
+        // the bucket claim and the block pop go out together; a claim whose
+        // pop comes back empty (blocks exhausted) is released
+        const uint32_t h = hash_index(bx, by, bz, v.n_buckets - 1u);
+        int prev = kPtrClaimed;
+        if (active && revive < 0) prev = atomicCAS(&v.entries[h].ptr, kPtrEmpty, kPtrClaimed);
         const int32_t blk = wave_pop(&v.ctrl->free_blocks, v.free_blocks, active);
         if (active && blk < 0) atomicOr(&v.ctrl->flags, TF_FLAG_BLOCKS_EXHAUSTED);
-        const uint32_t h = hash_index(bx, by, bz, v.n_buckets - 1u);
         int entry = -1;
         bool need_excess = false;
         const unsigned long long posw = (unsigned long long)(uint16_t)bx | ((unsigned long long)(uint16_t)by << 16) |
@@ -355,7 +352,6 @@ __device__ __forceinline__ void insert_body(const Vol &v, const Cam &c)
             v.entries[revive].ptr = blk;
             entry = revive;
         } else if (active && blk >= 0) {
-            int prev = atomicCAS(&v.entries[h].ptr, kPtrEmpty, kPtrClaimed);
             if (prev == kPtrEmpty) {
                 *reinterpret_cast<unsigned long long *>(&v.entries[h]) = posw;
                 v.entries[h].ptr = blk;
@@ -363,6 +359,8 @@ __device__ __forceinline__ void insert_body(const Vol &v, const Cam &c)
             } else {
                 need_excess = true;
             }
+        } else if (active && revive < 0 && prev == kPtrEmpty) {
+            v.entries[h].ptr = kPtrEmpty;
         }
         const int32_t slot = wave_pop(&v.ctrl->free_excess, v.free_excess, need_excess);
         if (need_excess) {
@@ -374,7 +372,7 @@ __device__ __forceinline__ void insert_body(const Vol &v, const Cam &c)
                 const uint32_t idx = v.n_buckets + (uint32_t)slot;
                 *reinterpret_cast<unsigned long long *>(&v.entries[idx]) = posw;
                 v.entries[idx].ptr = blk;
-                int32_t old = __hip_atomic_load(&v.entries[h].offset, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                int32_t old = 0;   // first guess: the bucket has no chain yet
                 for (;;) {
                     v.entries[idx].offset = old;
                     int32_t pr = atomicCAS(&v.entries[h].offset, old, slot + 1);
@@ -425,6 +423,9 @@ __device__ __forceinline__ void visible_body(const Vol &v)
         C->n_req = 0u;
         C->frames += 1u;
         if (v.alist) C->n_marked = C->n_alloc;   // the marking kernel has run on the new blocks
+        // pops past exhaustion leave the stack heights below zero
+        if (C->free_blocks < 0) C->free_blocks = 0;
+        if (C->free_excess < 0) C->free_excess = 0;
         const uint32_t nr = C->n_ret;
         if (nr) {
             const int32_t h = C->free_blocks;
