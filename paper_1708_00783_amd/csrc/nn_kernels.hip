@@ -73,21 +73,30 @@ __device__ __forceinline__ float depth_at(const void *depth, size_t i)
     return d > 0.0f ? d : 0.0f;
 }
 
+// One workgroup per 16x16 tile of one image: the tile's depths in metres with
+// a one-pixel border (-1 outside the image) are converted once into LDS, then
+// each pixel sums its valid 3x3 neighbours from there in row-major order.
 template <int FMT>
 __global__ __launch_bounds__(256) void k_make_input(const void *depth, int N, int H, int W, uint16_t *x, float *dm)
 {
-    const long p = (long)blockIdx.x * 256 + threadIdx.x;
-    if (p >= (long)N * H * W) return;
-    const int n = (int)(p / ((long)H * W));
-    const int rem = (int)(p - (long)n * H * W);
-    const int y = rem / W, xx = rem - (rem / W) * W;
-    const float d = depth_at<FMT>(depth, (size_t)p);
+    __shared__ float t[18][18];
+    const int tx = (int)blockIdx.x * 16, ty = (int)blockIdx.y * 16, n = (int)blockIdx.z;
+    for (int k = (int)threadIdx.x; k < 18 * 18; k += 256) {
+        const int iy = ty - 1 + k / 18, ix = tx - 1 + k % 18;
+        float v = -1.0f;
+        if (iy >= 0 && iy < H && ix >= 0 && ix < W) v = depth_at<FMT>(depth, ((size_t)n * H + iy) * W + ix);
+        t[k / 18][k % 18] = v;
+    }
+    __syncthreads();
+    const int lx = (int)threadIdx.x & 15, ly = (int)threadIdx.x >> 4;
+    const int xx = tx + lx, y = ty + ly;
+    if (xx >= W || y >= H) return;
+    const size_t p = ((size_t)n * H + y) * W + xx;
+    const float d = t[ly + 1][lx + 1];
     float s = 0.0f, c = 0.0f;
-    for (int ky = -1; ky <= 1; ++ky)
-        for (int kx = -1; kx <= 1; ++kx) {
-            const int yy = y + ky, xk = xx + kx;
-            if (yy < 0 || yy >= H || xk < 0 || xk >= W) continue;
-            const float v = depth_at<FMT>(depth, ((size_t)n * H + yy) * W + xk);
+    for (int ky = 0; ky < 3; ++ky)
+        for (int kx = 0; kx < 3; ++kx) {
+            const float v = t[ly + ky][lx + kx];
             if (v > 0.0f) {
                 s += v;
                 c += 1.0f;
@@ -97,7 +106,7 @@ __global__ __launch_bounds__(256) void k_make_input(const void *depth, int N, in
     dm[p] = d;
     u32x4 v = {(uint32_t)f2bf(d * 0.25f) | ((uint32_t)(d > 0.0f ? f2bf(1.0f) : 0u) << 16), (uint32_t)f2bf(hp), 0u,
                0u};
-    *reinterpret_cast<u32x4 *>(x + (size_t)p * 8) = v;
+    *reinterpret_cast<u32x4 *>(x + p * 8) = v;
 }
 
 // ============================================================================
@@ -105,8 +114,9 @@ __global__ __launch_bounds__(256) void k_make_input(const void *depth, int N, in
 // 4 pixels of one channel per 16x16 tile, so the per-element bias / skip /
 // activation reads and the output writes would be 2-byte accesses.  A wave
 // stages each 16-pixel row tile in its own LDS tile instead; every lane then
-// handles whole 16-byte vectors (one pixel, 8 channels).  All 4 waves of the
-// workgroup call it the same number of times (it holds workgroup barriers).
+// handles whole 16-byte vectors (one pixel, 8 channels).  The tile is the
+// wave's own, so a wave-scope fence and barrier order the staging writes
+// before the other lanes' reads (a wave's LDS instructions execute in order).
 // ============================================================================
 template <int NT>
 struct alignas(16) EpiTile {
@@ -121,7 +131,9 @@ __device__ __forceinline__ void epilogue_tile(EpiTile<NT> &st, const f32x4 (&a)[
     for (int j = 0; j < NT; ++j)
 #pragma unroll
         for (int i = 0; i < 4; ++i) st.v[gq * 4 + i][j * 16 + r] = a[j][i];
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
     for (int u = 0; u < (32 * NT + 63) / 64; ++u) {
         const int v = lane + 64 * u;   // 16 pixels x 2 NT vectors of 8 channels
@@ -132,7 +144,9 @@ __device__ __forceinline__ void epilogue_tile(EpiTile<NT> &st, const f32x4 (&a)[
             emit(pix, c8, lo, hi);
         }
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // two floats to packed bf16 (low half = a) by v_cvt_pk_bf16_f32: round to
@@ -1199,7 +1213,7 @@ static dim3 grid1(long n, int per) { return dim3((unsigned)((n + per - 1) / per)
 
 hipError_t launch_make_input(const void *depth, int fmt, int N, int H, int W, uint16_t *x, float *dm, hipStream_t s)
 {
-    const dim3 g = grid1((long)N * H * W, 256);
+    const dim3 g((unsigned)((W + 15) / 16), (unsigned)((H + 15) / 16), (unsigned)N);
     if (fmt == TF_DEPTH_U16_MM)
         hipLaunchKernelGGL(k_make_input<TF_DEPTH_U16_MM>, g, dim3(256), 0, s, depth, N, H, W, x, dm);
     else
