@@ -188,6 +188,36 @@ def test_block_exhaustion_sets_flag_and_keeps_invariants():
     assert (pts.cpu().numpy()[..., 3] == 1).any()
 
 
+def test_exhaustion_in_consecutive_frames_keeps_the_stacks_consistent():
+    """Pops past an empty stack in several frames in a row (the stack height
+    goes below zero inside the insertion and is clamped before the next push).
+    Blocks exhausted: the allocated count stays at capacity and every allocated
+    entry holds a distinct block.  Excess slots exhausted (16 buckets, 32
+    slots): every slot holds a block, the free-slot count reads zero, and the
+    blocks popped for links that found no slot went back to the stack."""
+    import paper_1708_00783_amd as T
+    from synth.configs import VolumeParams
+    d, p, K, _ = configs.c1_frames(3)
+    g = T.Volume(VolumeParams(0.01, 0.04, 100, 1 << 16, 1 << 12, 500), K.width, K.height)
+    for k in range(3):
+        g.frame(to_device(d[k]), K, p[k])
+        st = g.stats()
+        assert st["flags"] & 1 and st["n_allocated"] == 500, (k, st)
+        _, _, ptr = g.entries()
+        alloc = ptr >= 0
+        assert int(alloc.sum()) == 500 and len(set(ptr[alloc].tolist())) == 500, k
+    g = T.Volume(VolumeParams(0.01, 0.04, 100, 1 << 4, 32, 1 << 14), K.width, K.height)
+    for k in range(2):
+        g.frame(to_device(d[k]), K, p[k])
+        st = g.stats()
+        assert st["flags"] & 2 and st["n_free_excess"] == 0, (k, st)
+        _, _, ptr = g.entries()
+        alloc = ptr >= 0
+        assert int(alloc[16:].sum()) == 32, k
+        assert st["n_allocated"] == int(alloc.sum()), (k, st)
+        assert len(set(ptr[alloc].tolist())) == int(alloc.sum()), k
+
+
 def test_repeatable():
     d, p, K, _ = configs.c1_frames(4)
     import paper_1708_00783_amd as T
