@@ -316,8 +316,14 @@ class Multi:
                              _p(Vv, _F), _p(zmin, _F), _p(zmax, _F))
         return zmin, zmax
 
-    def raycast(self, W, H, intr, V):
+    def raycast(self, W, H, intr, V, mask=None):
+        """combined-field raycast of a W x H view; with `mask` (H x W bool) only
+        those pixels are marched (the range image is still the whole view's;
+        the other pixels get an empty range and no hit)"""
         zmin, zmax = self.range_image(W, H, intr, V)
+        if mask is not None:
+            zmin = np.ascontiguousarray(np.where(mask, zmin, np.float32(np.inf)), np.float32)
+            zmax = np.ascontiguousarray(np.where(mask, zmax, np.float32(-np.inf)), np.float32)
         k = np.ascontiguousarray(intr, np.float32)
         Vv = np.ascontiguousarray(V, np.float32).reshape(16)
         pts = np.empty((H, W, 4), np.float32)

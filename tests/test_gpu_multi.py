@@ -229,3 +229,81 @@ def test_close_view_blocks_over_many_tiles():
     nhit, flips = compare_raycast(pts.cpu().numpy(), nrm.cpu().numpy(), op, on, "close view")
     _log(f"close view: hits {nhit} flips {flips}")
     assert nhit > 0.2 * VIEW2.width * VIEW2.height
+
+
+def _pool_map(fn, items):
+    import multiprocessing as mp
+    import os
+    n = max(1, min(16, len(os.sched_getaffinity(0))))
+    with mp.get_context("fork").Pool(n) as pool:
+        return pool.map(fn, items, chunksize=max(1, len(items) // (4 * n)))
+
+
+def _prefill_depth(a):
+    return configs.c4_prefill_frame(*a)
+
+
+def _walk_depth(k):
+    return configs.c4_frame(k)
+
+
+def test_benchmark_shape_sampled_parity():
+    """The benchmark's shape: 64 submaps with its volume parameters and poses
+    (5 mm voxels), each fused from 3 noiseless 320x240 viewpoints of its region
+    (a fixed schedule), then walk frames 0 and 1 at 640x480 fused into the
+    submaps they overlap; its 8 views, 320x240 to 1280x720, raycast on the
+    combined field.  The oracle fuses the same frames into its own submaps.
+    Compared: the tables of the submaps the last walk frame reaches (first 3),
+    every view's range image exactly, and the raycast at 1024 seeded pixels of
+    every view (the oracle marches only those, each from the whole view's range
+    image), at most one hit/miss disagreement per view."""
+    import torch
+    import paper_1708_00783_amd as T
+    from oracle import oracle as O
+    KW = configs.KINECT_INTR
+    KP = configs.C4_PREFILL_INTR
+    subs = configs.c4_submaps()
+    P = np.stack([s.pose for s in subs])
+    items = [(i, j) for i in range(len(subs)) for j in range(3)]
+    walk = configs.c4_poses()
+    prefill = _pool_map(_prefill_depth, items)
+    walk_d = _pool_map(_walk_depth, [0, 1])
+    _log(f"case benchmark shape: {len(subs)} submaps, {len(items)} prefill frames, 2 walk frames, 8 views")
+    ovols = [O.Volume.from_params(configs.C4_VOLUME) for _ in subs]
+    o = O.Multi(ovols, P)
+    g = T.MultiMap(configs.C4_VOLUME, P, KW.width, KW.height, 1280, 720, 1 << 25)
+    for (i, j), dep in zip(items, prefill):
+        pose = configs.c4_prefill_pose(i, j)
+        g.integrate(torch.from_numpy(dep).cuda(), KP, pose, [i])
+        o.integrate_frame(i, dep, KP.as_array(), pose)
+    sel = []
+    for k in range(2):
+        sel = configs.c4_select(walk[k])
+        g.integrate(to_device(walk_d[k]), KW, walk[k], sel)
+        for i in sel:
+            o.integrate_frame(i, oracle_depth(walk_d[k]), KW.as_array(), walk[k])
+    for i in sel[:3]:
+        compare_visible(g.submap(i), ovols[i], f"submap {i}")
+        nblk, nsd = compare_tables(g.submap(i), ovols[i], f"submap {i}")
+        _log(f"submap {i}: blocks {nblk} sdf-lsb-diffs {nsd}")
+    views = []
+    for intr, pose in configs.c4_views(1):
+        pts = torch.full((intr.height, intr.width, 4), -7.0, dtype=torch.float32, device="cuda")
+        views.append((intr, pose, pts, torch.full_like(pts, -7.0)))
+    g.raycast(views)
+    st = g.stats()
+    assert st["flags"] == 0, st   # no capacity or bin overflow
+    assert st["allocated_blocks"] == sum(len(v.allocated_positions()) for v in ovols)
+    rng = np.random.default_rng(11)
+    for vi, (intr, pose, pts, nrm) in enumerate(views):
+        W, H = intr.width, intr.height
+        gz0, gz1 = g.range_image(intr, pose)
+        oz0, oz1 = o.range_image(W, H, intr.as_array(), pose)
+        assert np.array_equal(gz0.cpu().numpy(), oz0) and np.array_equal(gz1.cpu().numpy(), oz1), f"view {vi} range"
+        m = np.zeros((H, W), bool)
+        m.flat[rng.choice(W * H, 1024, replace=False)] = True
+        op, on = o.raycast(W, H, intr.as_array(), pose, mask=m)
+        gp, gn = pts.cpu().numpy(), nrm.cpu().numpy()
+        nhit, flips = compare_raycast(gp[m], gn[m], op[m], on[m], f"view {vi} {W}x{H}")
+        _log(f"view {vi} {W}x{H}: sampled hits {nhit} of 1024, flips {flips}")
+        assert nhit > 500
