@@ -177,3 +177,19 @@ def test_partition_into_two_submaps_equals_plain(oracle_mod):
     assert np.mean(dp <= 1e-4) > 0.99, float(np.mean(dp <= 1e-4))
     dn = np.abs(nrm0[both][:, :3] - nrm1[both][:, :3]).max(axis=1)
     assert np.mean(dn <= 1e-3) > 0.99
+
+
+def test_masked_raycast_marches_only_the_masked_pixels(oracle_mod):
+    """The mask only empties the other pixels' ranges: masked pixels equal the
+    full raycast bit for bit, the others have no hit (used to sample pixels of
+    large views)."""
+    vol, d, p, _ = _plain(oracle_mod)
+    m = oracle_mod.Multi([vol], [np.eye(4, dtype=np.float32)])
+    V = p[-1]
+    full_p, full_n = m.raycast(K.width, K.height, K.as_array(), V)
+    mask = np.zeros((K.height, K.width), bool)
+    mask.flat[np.random.default_rng(3).choice(K.width * K.height, 500, replace=False)] = True
+    mp, mn = m.raycast(K.width, K.height, K.as_array(), V, mask=mask)
+    assert np.array_equal(mp[mask], full_p[mask]) and np.array_equal(mn[mask], full_n[mask])
+    assert not (mp[~mask][:, 3] == 1).any() and not (mn[~mask][:, 3] == 1).any()
+    assert (full_p[mask][:, 3] == 1).sum() > 100
