@@ -77,12 +77,16 @@ constexpr int kBinSlots = 1024;
 constexpr int kBinProbes = 32;        // probes before a tile takes the global path
 constexpr int kBinDirect = 16;        // blocks over more tiles take the global path for all of them
 constexpr uint32_t kNoTile = 0xffffffffu;
+constexpr int kBinBig = 128;          // blocks over many tiles whose tiles the workgroup shares
 struct MBinLds {
     uint32_t tile[kBinSlots];
     uint32_t cnt[kBinSlots];
     uint32_t pos[kBinSlots];
     uint32_t first[kMaxSubmaps + 1];   // flat index of each submap's first block
     float C[kMaxSubmaps][12];          // the view's camera composed with each submap pose
+    Rec big_rec[kBinBig];              // fill pass: the record of each queued block
+    int4 big_box[kBinBig];             // tx0, ty0, tiles per row, tiles
+    uint32_t nbig;
 };
 
 // slot of tile g in the chunk table, inserting it when `insert`; -1 when
@@ -126,6 +130,7 @@ __global__ __launch_bounds__(256) void k_m_bin(const MSub *subs, const MFrame *f
     }
     for (int k = threadIdx.x; k < n_sub * 12; k += 256) B.C[k / 12][k % 12] = f->C[vi][k / 12][k % 12];
     if (threadIdx.x == 0) {
+        B.nbig = 0u;
         uint32_t acc = 0u;
         for (int sm = 0; sm < n_sub; ++sm) {
             B.first[sm] = acc;
@@ -184,18 +189,32 @@ __global__ __launch_bounds__(256) void k_m_bin(const MSub *subs, const MFrame *f
         }
         const int tx0 = hit ? ex.x0 / tw : 1, tx1 = hit ? ex.x1 / tw : 0;
         const int ty0 = hit ? ex.y0 / th : 1, ty1 = hit ? ex.y1 / th : 0;
-        const bool direct = (tx1 - tx0 + 1) * (ty1 - ty0 + 1) > kBinDirect;
-        // entries per distinct tile of the chunk
-        for (int ty = ty0; ty <= ty1; ++ty)
-            for (int tx = tx0; tx <= tx1; ++tx) {
-                const uint32_t g = (uint32_t)(base + ty * ntx + tx);
-                const int sl = direct ? -1 : bin_slot(B, g, true);
-                if (sl >= 0)
-                    atomicAdd(&B.cnt[sl], 1u);
-                else if (!FILL)
-                    atomicAdd(&t.cnt[g], 1);
+        const int nx = tx1 - tx0 + 1, ntl = nx * (ty1 - ty0 + 1);
+        const bool direct = ntl > kBinDirect;
+        // a block over many tiles: queued for the whole workgroup (the count
+        // pass here, the fill pass with its record below), unless the queue
+        // is full; its tiles then take one global atomic each from this thread
+        bool queued = false;
+        if (!FILL && hit && direct) {
+            const uint32_t j = atomicAdd(&B.nbig, 1u);
+            if (j < (uint32_t)kBinBig) {
+                B.big_box[j] = make_int4(tx0, ty0, nx, ntl);
+                queued = true;
             }
+        }
+        // entries per distinct tile of the chunk
+        if (!queued)
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) {
+                    const uint32_t g = (uint32_t)(base + ty * ntx + tx);
+                    const int sl = direct ? -1 : bin_slot(B, g, true);
+                    if (sl >= 0)
+                        atomicAdd(&B.cnt[sl], 1u);
+                    else if (!FILL)
+                        atomicAdd(&t.cnt[g], 1);
+                }
         __syncthreads();
+        const uint32_t nq = FILL ? 0u : (B.nbig < (uint32_t)kBinBig ? B.nbig : (uint32_t)kBinBig);
         // one global atomic per distinct tile: its count, or its range in the bin
         for (int k = threadIdx.x; k < kBinSlots; k += 256) {
             const uint32_t g = B.tile[k];
@@ -206,6 +225,12 @@ __global__ __launch_bounds__(256) void k_m_bin(const MSub *subs, const MFrame *f
                 atomicAdd(&t.cnt[g], (int)B.cnt[k]);
         }
         __syncthreads();
+        // count pass: the queued blocks' tiles, shared by every thread
+        for (uint32_t j = 0; j < nq; ++j) {
+            const int4 bb = B.big_box[j];
+            for (int k = (int)threadIdx.x; k < bb.w; k += 256)
+                atomicAdd(&t.cnt[(uint32_t)(base + (bb.y + k / bb.z) * ntx + bb.x + k % bb.z)], 1);
+        }
         if (FILL && hit) {
             // the search-range box of the block itself (empty when it is
             // behind the near plane or off the image: then it only feeds
@@ -224,20 +249,44 @@ __global__ __launch_bounds__(256) void k_m_bin(const MSub *subs, const MFrame *f
             r.pad = (int16_t)sm;
             r.ptr = ptr;
             r.pad2 = (int32_t)__float_as_uint(ex.zlo);   // the grown cube's least camera depth (table depth cut)
-            for (int ty = ty0; ty <= ty1; ++ty)
-                for (int tx = tx0; tx <= tx1; ++tx) {
-                    const uint32_t g = (uint32_t)(base + ty * ntx + tx);
-                    const int sl = direct ? -1 : bin_slot(B, g, false);
-                    const uint32_t idx =
-                        sl >= 0 ? atomicAdd(&B.pos[sl], 1u) : t.off[g] + (uint32_t)atomicAdd(&t.cur[g], 1);
-                    if (idx < t.cap) t.bins[idx] = r;
+            bool fq = false;
+            if (direct) {
+                const uint32_t j = atomicAdd(&B.nbig, 1u);
+                if (j < (uint32_t)kBinBig) {
+                    B.big_rec[j] = r;
+                    B.big_box[j] = make_int4(tx0, ty0, nx, ntl);
+                    fq = true;
                 }
+            }
+            if (!fq)
+                for (int ty = ty0; ty <= ty1; ++ty)
+                    for (int tx = tx0; tx <= tx1; ++tx) {
+                        const uint32_t g = (uint32_t)(base + ty * ntx + tx);
+                        const int sl = direct ? -1 : bin_slot(B, g, false);
+                        const uint32_t idx =
+                            sl >= 0 ? atomicAdd(&B.pos[sl], 1u) : t.off[g] + (uint32_t)atomicAdd(&t.cur[g], 1);
+                        if (idx < t.cap) t.bins[idx] = r;
+                    }
         }
-        if (FILL) __syncthreads();   // every slot position taken before the table is cleared
+        if (FILL) {
+            __syncthreads();   // every block queued
+            // fill pass: the queued blocks' records, each tile by one thread
+            const uint32_t nf = B.nbig < (uint32_t)kBinBig ? B.nbig : (uint32_t)kBinBig;
+            for (uint32_t j = 0; j < nf; ++j) {
+                const int4 bb = B.big_box[j];
+                for (int k = (int)threadIdx.x; k < bb.w; k += 256) {
+                    const uint32_t g = (uint32_t)(base + (bb.y + k / bb.z) * ntx + bb.x + k % bb.z);
+                    const uint32_t idx = t.off[g] + (uint32_t)atomicAdd(&t.cur[g], 1);
+                    if (idx < t.cap) t.bins[idx] = B.big_rec[j];
+                }
+            }
+            __syncthreads();   // every slot position taken and the queue read before both are cleared
+        }
         for (int k = threadIdx.x; k < kBinSlots; k += 256) {
             B.tile[k] = kNoTile;
             B.cnt[k] = 0u;
         }
+        if (threadIdx.x == 0) B.nbig = 0u;
         __syncthreads();
     }
 }
