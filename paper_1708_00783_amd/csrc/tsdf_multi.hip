@@ -87,6 +87,7 @@ struct MBinLds {
     Rec big_rec[kBinBig];              // fill pass: the record of each queued block
     int4 big_box[kBinBig];             // tx0, ty0, tiles per row, tiles
     uint32_t nbig;
+    uint32_t pairs;                    // count pass: (block, view) pairs of the workgroup
 };
 
 // slot of tile g in the chunk table, inserting it when `insert`; -1 when
@@ -131,6 +132,7 @@ __global__ __launch_bounds__(256) void k_m_bin(const MSub *subs, const MFrame *f
     for (int k = threadIdx.x; k < n_sub * 12; k += 256) B.C[k / 12][k % 12] = f->C[vi][k / 12][k % 12];
     if (threadIdx.x == 0) {
         B.nbig = 0u;
+        B.pairs = 0u;
         uint32_t acc = 0u;
         for (int sm = 0; sm < n_sub; ++sm) {
             B.first[sm] = acc;
@@ -184,8 +186,7 @@ __global__ __launch_bounds__(256) void k_m_bin(const MSub *subs, const MFrame *f
         }
         if (!FILL) {
             const unsigned long long m = __ballot(hit);
-            if (m && lane_id() == (uint32_t)(__ffsll((long long)m) - 1))
-                atomicAdd(&t.mc->tot_blkview, (unsigned long long)__popcll(m));
+            if (m && lane_id() == (uint32_t)(__ffsll((long long)m) - 1)) atomicAdd(&B.pairs, (uint32_t)__popcll(m));
         }
         const int tx0 = hit ? ex.x0 / tw : 1, tx1 = hit ? ex.x1 / tw : 0;
         const int ty0 = hit ? ex.y0 / th : 1, ty1 = hit ? ex.y1 / th : 0;
@@ -289,6 +290,9 @@ __global__ __launch_bounds__(256) void k_m_bin(const MSub *subs, const MFrame *f
         if (threadIdx.x == 0) B.nbig = 0u;
         __syncthreads();
     }
+    // one global atomic per workgroup for the statistics (a same-address
+    // atomic from every wave and chunk serialised the count pass)
+    if (!FILL && threadIdx.x == 0 && B.pairs) atomicAdd(&t.mc->tot_blkview, (unsigned long long)B.pairs);
 }
 
 // exclusive offsets of the tile counts (one workgroup); clears the counts and
