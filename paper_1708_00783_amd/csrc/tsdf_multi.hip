@@ -113,8 +113,10 @@ __device__ __forceinline__ int bin_slot(MBinLds &B, uint32_t g, bool insert)
 // submap); a workgroup takes 256 consecutive blocks at a time and aggregates
 // their (block, tile) entries per distinct tile in LDS, so a tile costs one
 // global atomic per chunk instead of one per entry (an entry whose tile the
-// chunk table refuses, or of a block over many tiles, takes a global atomic
-// of its own).  The order of records within a bin is not fixed.
+// chunk table refuses takes a global atomic of its own).  A block over more
+// than kBinDirect tiles -- near the camera it can cover thousands -- is queued
+// and its tiles are shared by the workgroup's threads, one global atomic
+// each.  The order of records within a bin is not fixed.
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_m_bin(const MSub *subs, const MFrame *f, MTiles t, float voxel)
 {
