@@ -1251,9 +1251,10 @@ hipError_t launch_conv_fwd(int layer, const uint16_t *in, int Hs, int Ws, const 
                            const uint16_t *skip, uint16_t *out, int N, int Ho, int Wo, hipStream_t s)
 {
     // encoder tiles: 4 / NS output rows x 16 T columns per workgroup, the
-    // deeper, smaller layers splitting their output channels over 2 or 4
-    // waves; decoder tiles: one source row x 16 T columns, the smaller
-    // layers' channels split over NS workgroups (shapes measured at 640x480)
+    // stride-2 layers splitting their output channels over the 4 waves (one
+    // output row per workgroup); decoder tiles: one source row x 16 T
+    // columns, the smaller layers' channels split over NS workgroups (shapes
+    // measured at 640x480)
     const dim3 b(256);
     auto enc_grid = [&](int T, int NS) {
         const long nt = (long)N * ((Ho + 4 / NS - 1) / (4 / NS)) * ((Wo + 16 * T - 1) / (16 * T));
@@ -1267,7 +1268,7 @@ hipError_t launch_conv_fwd(int layer, const uint16_t *in, int Hs, int Ws, const 
     if (layer >= 4 && (Ho != 2 * Hs || Wo != 2 * Ws)) return hipErrorInvalidValue;
     switch (layer) {
     case 0: hipLaunchKernelGGL((k_conv_fwd<8, 32, 1, 2, 1>), enc_grid(2, 1), b, 0, s, in, Hs, Ws, g, bias, out, N, Ho, Wo); break;
-    case 1: hipLaunchKernelGGL((k_conv_fwd<32, 64, 2, 2, 2>), enc_grid(2, 2), b, 0, s, in, Hs, Ws, g, bias, out, N, Ho, Wo); break;
+    case 1: hipLaunchKernelGGL((k_conv_fwd<32, 64, 2, 2, 4>), enc_grid(2, 4), b, 0, s, in, Hs, Ws, g, bias, out, N, Ho, Wo); break;
     case 2: hipLaunchKernelGGL((k_conv_fwd<64, 64, 2, 1, 4>), enc_grid(1, 4), b, 0, s, in, Hs, Ws, g, bias, out, N, Ho, Wo); break;
     case 3: hipLaunchKernelGGL((k_conv_fwd<64, 128, 2, 1, 4>), enc_grid(1, 4), b, 0, s, in, Hs, Ws, g, bias, out, N, Ho, Wo); break;
     case 4: hipLaunchKernelGGL((k_conv_fwd_up<128, 64, true, 2, 4>), up_grid(2, 4), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
