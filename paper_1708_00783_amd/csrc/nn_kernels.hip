@@ -1271,7 +1271,7 @@ hipError_t launch_conv_fwd(int layer, const uint16_t *in, int Hs, int Ws, const 
     case 1: hipLaunchKernelGGL((k_conv_fwd<32, 64, 2, 2, 4>), enc_grid(2, 4), b, 0, s, in, Hs, Ws, g, bias, out, N, Ho, Wo); break;
     case 2: hipLaunchKernelGGL((k_conv_fwd<64, 64, 2, 1, 4>), enc_grid(1, 4), b, 0, s, in, Hs, Ws, g, bias, out, N, Ho, Wo); break;
     case 3: hipLaunchKernelGGL((k_conv_fwd<64, 128, 2, 1, 4>), enc_grid(1, 4), b, 0, s, in, Hs, Ws, g, bias, out, N, Ho, Wo); break;
-    case 4: hipLaunchKernelGGL((k_conv_fwd_up<128, 64, true, 2, 4>), up_grid(2, 4), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
+    case 4: hipLaunchKernelGGL((k_conv_fwd_up<128, 64, true, 1, 4>), up_grid(1, 4), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
     case 5: hipLaunchKernelGGL((k_conv_fwd_up<64, 64, true, 2, 2>), up_grid(2, 2), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
     case 6: hipLaunchKernelGGL((k_conv_fwd_up<64, 32, true, 2, 1>), up_grid(2, 1), b, 0, s, in, Hs, Ws, g, bias, skip, out, N); break;
     default: return hipErrorInvalidValue;
